@@ -1,0 +1,159 @@
+"""Python access to the C oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by __graft_entry__.smoke() and by
+the benchmark's CPU-baseline leg.  The GPU library never imports, links or
+calls anything here, and nothing here imports the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+TRACE_ROUNDS = 4096
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (plain -O2, single thread)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared",
+                               "-o", tmp, src])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("num_colors", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("vertex_visits", ctypes.c_int64), ("edge_visits", ctypes.c_int64),
+                ("boundary_conflicts", ctypes.c_int64), ("remote_losers", ctypes.c_int64),
+                ("worklist_trace", ctypes.c_int64 * TRACE_ROUNDS)]
+
+
+@dataclass
+class Result:
+    colors: np.ndarray
+    num_colors: int
+    rounds: int
+    vertex_visits: int
+    edge_visits: int
+    boundary_conflicts: int = 0
+    remote_losers: int = 0
+    remote_loser: np.ndarray | None = None
+    worklist: list = field(default_factory=list)
+    converged: bool = True
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        l = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        l.orc_fmix32.restype = ctypes.c_uint32
+        l.orc_fmix32.argtypes = [ctypes.c_uint32]
+        l.orc_priority.restype = ctypes.c_uint32
+        l.orc_priority.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        sig = [ctypes.c_int32, P, P, ctypes.c_uint32, P, P, ctypes.c_int32, P, P]
+        for name in ("orc_color_d1", "orc_color_d2"):
+            getattr(l, name).restype = ctypes.c_int
+            getattr(l, name).argtypes = sig
+        l.orc_color_pd2.restype = ctypes.c_int
+        l.orc_color_pd2.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, ctypes.c_uint32,
+                                    P, P, ctypes.c_int32, P, P]
+        l.orc_color_d1_ghost.restype = ctypes.c_int
+        l.orc_color_d1_ghost.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, P, P, P, P, ctypes.c_uint32, P, P, P]
+        l.orc_serial_greedy.restype = None
+        l.orc_serial_greedy.argtypes = [ctypes.c_int32, P, P, P, P]
+        _lib = l
+    return _lib
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _result(colors, st, ret, remote=None) -> Result:
+    nr = min(st.rounds, TRACE_ROUNDS)
+    return Result(colors, st.num_colors, st.rounds, st.vertex_visits, st.edge_visits,
+                  st.boundary_conflicts, st.remote_losers, remote,
+                  list(st.worklist_trace[:nr]), ret == 0)
+
+
+def fmix32(h: int) -> int:
+    return int(lib().orc_fmix32(h & 0xFFFFFFFF))
+
+
+def priority(gid: int, seed: int) -> int:
+    return int(lib().orc_priority(gid & 0xFFFFFFFF, seed & 0xFFFFFFFF))
+
+
+def priorities(ids, seed: int) -> np.ndarray:
+    return np.array([priority(int(i), seed) for i in ids], dtype=np.uint32)
+
+
+def _prio_init(prio, init):
+    p = None if prio is None else np.ascontiguousarray(prio, dtype=np.uint32)
+    i = None if init is None else _i32(init)
+    return p, i
+
+
+def color_d1(g, seed: int = 1, prio=None, init=None, max_rounds: int = 0) -> Result:
+    rp, col = _i32(g.row_ptr), _i32(g.col)
+    p, i = _prio_init(prio, init)
+    out = np.zeros(g.n, dtype=np.int32)
+    st = _Stats()
+    ret = lib().orc_color_d1(g.n, _ptr(rp), _ptr(col), seed & 0xFFFFFFFF, _ptr(p), _ptr(i),
+                             max_rounds, _ptr(out), ctypes.byref(st))
+    return _result(out, st, ret)
+
+
+def color_d2(g, seed: int = 1, prio=None, init=None, max_rounds: int = 0) -> Result:
+    rp, col = _i32(g.row_ptr), _i32(g.col)
+    p, i = _prio_init(prio, init)
+    out = np.zeros(g.n, dtype=np.int32)
+    st = _Stats()
+    ret = lib().orc_color_d2(g.n, _ptr(rp), _ptr(col), seed & 0xFFFFFFFF, _ptr(p), _ptr(i),
+                             max_rounds, _ptr(out), ctypes.byref(st))
+    return _result(out, st, ret)
+
+
+def color_pd2(b, seed: int = 1, prio=None, init=None, max_rounds: int = 0) -> Result:
+    arrs = [_i32(x) for x in (b.row_ptr, b.col_idx, b.col_ptr, b.row_idx)]
+    p, i = _prio_init(prio, init)
+    out = np.zeros(b.n_cols, dtype=np.int32)
+    st = _Stats()
+    ret = lib().orc_color_pd2(b.n_rows, b.n_cols, *[_ptr(a) for a in arrs], seed & 0xFFFFFFFF,
+                              _ptr(p), _ptr(i), max_rounds, _ptr(out), ctypes.byref(st))
+    return _result(out, st, ret)
+
+
+def color_d1_ghost(lg, seed: int = 1) -> Result:
+    rp, col, gid, gc = (_i32(x) for x in (lg.row_ptr, lg.col, lg.gid, lg.ghost_colors))
+    out = np.zeros(lg.n_owned, dtype=np.int32)
+    remote = np.zeros(max(lg.n_ghost, 1), dtype=np.uint8)
+    st = _Stats()
+    ret = lib().orc_color_d1_ghost(lg.n_owned, lg.n_ghost, lg.layers, lg.n_g1, _ptr(rp), _ptr(col),
+                                   _ptr(gid), _ptr(gc), seed & 0xFFFFFFFF, _ptr(out), _ptr(remote),
+                                   ctypes.byref(st))
+    return _result(out, st, ret, remote[:lg.n_ghost].copy())
+
+
+def serial_greedy(g, order) -> np.ndarray:
+    rp, col, o = _i32(g.row_ptr), _i32(g.col), _i32(order)
+    out = np.zeros(g.n, dtype=np.int32)
+    lib().orc_serial_greedy(g.n, _ptr(rp), _ptr(col), _ptr(o), _ptr(out))
+    return out

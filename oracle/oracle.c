@@ -1,0 +1,404 @@
+/*
+ * CPU oracle for synchronous speculative graph coloring.  TEST INFRASTRUCTURE
+ * ONLY: it is called by the test suite, by the smoke check and by the
+ * benchmark's CPU-baseline leg, never by the library's product path.  It
+ * shares no code, header, table or constant generator with the GPU library.
+ *
+ * Plain, slow, single-threaded C: every per-round loop below is written the
+ * way the method is defined, with no bitmasks, no blocking and no fusion, so
+ * that a reader can check it against the paper by eye.
+ *
+ * The method (Bogle et al., "Parallel Graph Coloring Algorithms for
+ * Distributed GPU Environments"):
+ *   - colors are integers, 0 means "uncolored" (Section 2.2, Algorithm 1;
+ *     Section 3.2, the coloring functions treat color zero as uncolored);
+ *   - a vertex takes the smallest color not used by its neighbours
+ *     (first-fit, Section 2.2, Algorithm 1);
+ *   - speculate and iterate (Section 2.3, Section 3, Algorithm 2): color every
+ *     uncolored vertex, detect conflicts, uncolor one endpoint of each
+ *     conflict, repeat until no conflict remains;
+ *   - the endpoint to recolor is chosen by a random number derived from the
+ *     global id, ties broken by the id (Section 3.2, Algorithm 4).
+ *
+ * Readings taken where the paper leaves freedom (each is listed with its
+ * reason in the design notes):
+ *   R1  rounds are synchronous: every vertex of the round's worklist picks its
+ *       tentative color from the colors committed before the round, and all
+ *       conflicts of the round are judged at once on the tentative colors;
+ *   R2  key(v) = (p(v), gid(v)) compared lexicographically; in a conflict the
+ *       LOWER key is uncolored (the mirror of Algorithm 4's direction, which
+ *       is statistically equivalent);
+ *   R3  p(v) = fmix32(gid ^ S), S = fmix32(seed ^ 0x9E3779B9), fmix32 being
+ *       the MurmurHash3 32-bit finalizer (public domain, A. Appleby); a
+ *       bijection of uint32, so keys never tie;
+ *   R4  distance-2 neighbourhood N2(v) = (N(v) u N(N(v))) \ {v}
+ *       (Section 2.1: all vertices within two hops differ);
+ *   R5  partial distance-2 colors the columns of a pattern only; two columns
+ *       conflict when they share a row (Section 2.1; Section 3.6, the
+ *       doPartialColoring mode of Algorithm 5 checks two-hop pairs only);
+ *   R6  ghost variant (Algorithm 2, one rank's step): phase 1 colors the
+ *       owned vertices ghost-blind (Section 3.2: the initial coloring does not
+ *       need ghost information); phase 2 compares every owned-ghost edge
+ *       against the ghosts' fixed colors with the key rule (Algorithm 3/4);
+ *       phase 3 recolors the owned losers with the ghost colors as
+ *       constraints; ghost colors are never written (save/restore of gc).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+/* ---------------------------------------------------------------------- */
+/* Priority: rand(GID) of Algorithm 4                                      */
+/* ---------------------------------------------------------------------- */
+
+/* MurmurHash3 32-bit finalizer: xor-shift 16, multiply, xor-shift 13,
+ * multiply, xor-shift 16, all modulo 2^32. */
+uint32_t orc_fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+uint32_t orc_priority(uint32_t gid, uint32_t seed)
+{
+    uint32_t s = orc_fmix32(seed ^ 0x9E3779B9u);
+    return orc_fmix32(gid ^ s);
+}
+
+/* 1 if key(a) > key(b); key = (p, gid) lexicographic (reading R2). */
+static int key_greater(uint32_t pa, uint32_t ga, uint32_t pb, uint32_t gb)
+{
+    if (pa != pb) return pa > pb;
+    return ga > gb;
+}
+
+/* ---------------------------------------------------------------------- */
+/* A neighbourhood is a plain list of vertex ids (duplicates allowed: the  */
+/* rules below only ask "does some member satisfy ...", which duplicates   */
+/* do not change).                                                         */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int kind;                 /* 1 = distance-1, 2 = distance-2, 3 = partial distance-2 */
+    int32_t n;                /* vertices being colored */
+    const int32_t *row_ptr;   /* D1/D2: adjacency CSR; PD2: pattern CSR (rows -> cols) */
+    const int32_t *col;
+    const int32_t *col_ptr;   /* PD2 only: pattern CSC (cols -> rows) */
+    const int32_t *row_idx;
+} graph_t;
+
+typedef struct {
+    int32_t *ids;
+    int64_t len, cap;
+} list_t;
+
+static void list_push(list_t *l, int32_t x)
+{
+    if (l->len == l->cap) {
+        l->cap = l->cap ? 2 * l->cap : 64;
+        l->ids = (int32_t *)realloc(l->ids, (size_t)l->cap * sizeof(int32_t));
+    }
+    l->ids[l->len++] = x;
+}
+
+/* Fills l with the neighbourhood of v used by the coloring problem:
+ * D1: N(v); D2: N(v) and N(u) for u in N(v), minus v (reading R4);
+ * PD2: every column sharing a row with column v, minus v (reading R5).
+ * Returns the number of adjacency entries read (for the work counters). */
+static int64_t neighbourhood(const graph_t *g, int32_t v, list_t *l)
+{
+    int64_t visits = 0;
+    l->len = 0;
+    if (g->kind == 1) {
+        for (int32_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; e++) {
+            list_push(l, g->col[e]);
+            visits++;
+        }
+    } else if (g->kind == 2) {
+        for (int32_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; e++) {
+            int32_t u = g->col[e];
+            list_push(l, u);
+            visits++;
+            for (int32_t f = g->row_ptr[u]; f < g->row_ptr[u + 1]; f++) {
+                int32_t x = g->col[f];
+                visits++;
+                if (x != v) list_push(l, x);
+            }
+        }
+    } else {
+        for (int32_t e = g->col_ptr[v]; e < g->col_ptr[v + 1]; e++) {
+            int32_t r = g->row_idx[e];
+            visits++;
+            for (int32_t f = g->row_ptr[r]; f < g->row_ptr[r + 1]; f++) {
+                int32_t c = g->col[f];
+                visits++;
+                if (c != v) list_push(l, c);
+            }
+        }
+    }
+    return visits;
+}
+
+/* Smallest color c >= 1 that no member of nb carries in colors[] (first-fit,
+ * Algorithm 1).  'extra' (nullable) supplies the colors of ids >= n_base
+ * (ghosts), which are read as extra[id - n_base]. */
+static int32_t first_fit(const list_t *nb, const int32_t *colors, int32_t n_base,
+                         const int32_t *extra, int32_t ignore_from)
+{
+    /* used[c] for c in [0, len+1]: a color above len+1 can never be the answer */
+    int64_t m = nb->len + 2;
+    unsigned char *used = (unsigned char *)calloc((size_t)m, 1);
+    for (int64_t i = 0; i < nb->len; i++) {
+        int32_t u = nb->ids[i];
+        int32_t c;
+        if (u >= ignore_from) continue;
+        c = (u < n_base) ? colors[u] : extra[u - n_base];
+        if (c > 0 && c < m) used[c] = 1;
+    }
+    int32_t c = 1;
+    while (used[c]) c++;
+    free(used);
+    return c;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The synchronous round loop (readings R1, R2)                            */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    const graph_t *g;
+    int32_t n;                /* colorable vertices: ids [0, n) */
+    int32_t n_base;           /* ids >= n_base are fixed-color ghosts */
+    const int32_t *ghost_col; /* colors of ids >= n_base */
+    int32_t ignore_from;      /* neighbours with id >= ignore_from are ignored */
+    const uint32_t *pkey;     /* p(v) for every id the rules may read */
+    const uint32_t *gkey;     /* gid(v) */
+    int32_t max_rounds;
+} rounds_t;
+
+/* Runs rounds until the worklist is empty or max_rounds is reached.
+ * colors[] holds the committed colors C on entry (0 = in the worklist) and
+ * on exit.  Returns the number of rounds; accumulates work counters. */
+static int32_t run_rounds(const rounds_t *rc, int32_t *colors, orc_stats *st,
+                          int32_t round0)
+{
+    int32_t n = rc->n;
+    int32_t *T = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    unsigned char *in_w = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    unsigned char *lost = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    list_t W = {0}, nb = {0};
+    int32_t r = 0;
+
+    for (int32_t v = 0; v < n; v++)
+        if (colors[v] == 0) { list_push(&W, v); in_w[v] = 1; }
+
+    while (W.len > 0 && r < rc->max_rounds) {
+        r++;
+        if (st) {
+            st->vertex_visits += W.len;
+            if (round0 + r - 1 < ORC_TRACE_ROUNDS) st->worklist_trace[round0 + r - 1] = W.len;
+        }
+        /* color step: reads the committed snapshot only */
+        for (int64_t i = 0; i < W.len; i++) {
+            int32_t v = W.ids[i];
+            int64_t vis = neighbourhood(rc->g, v, &nb);
+            if (st) st->edge_visits += vis;
+            T[v] = first_fit(&nb, colors, rc->n_base, rc->ghost_col, rc->ignore_from);
+        }
+        /* detect step: v loses when a worklist neighbour holds the same
+         * tentative color with a greater key; judged all at once */
+        for (int64_t i = 0; i < W.len; i++) {
+            int32_t v = W.ids[i];
+            lost[v] = 0;
+            neighbourhood(rc->g, v, &nb);
+            for (int64_t k = 0; k < nb.len; k++) {
+                int32_t u = nb.ids[k];
+                if (u >= rc->ignore_from || u >= n) continue;  /* ghosts are never in the worklist */
+                if (!in_w[u]) continue;
+                if (T[u] == T[v] && key_greater(rc->pkey[u], rc->gkey[u], rc->pkey[v], rc->gkey[v])) {
+                    lost[v] = 1;
+                    break;
+                }
+            }
+        }
+        /* commit winners, losers form the next worklist */
+        {
+            list_t next = {0};
+            for (int64_t i = 0; i < W.len; i++) {
+                int32_t v = W.ids[i];
+                if (lost[v]) {
+                    list_push(&next, v);
+                } else {
+                    colors[v] = T[v];
+                    in_w[v] = 0;
+                }
+            }
+            free(W.ids);
+            W = next;
+        }
+    }
+    free(T);
+    free(in_w);
+    free(lost);
+    free(W.ids);
+    free(nb.ids);
+    return r;
+}
+
+static void fill_keys(int32_t m, const int32_t *gid, uint32_t seed, const uint32_t *prio,
+                      uint32_t *pkey, uint32_t *gkey)
+{
+    for (int32_t v = 0; v < m; v++) {
+        uint32_t g = gid ? (uint32_t)gid[v] : (uint32_t)v;
+        gkey[v] = g;
+        pkey[v] = prio ? prio[v] : orc_priority(g, seed);
+    }
+}
+
+static void finish_stats(orc_stats *st, const int32_t *colors, int32_t n, int32_t rounds)
+{
+    if (!st) return;
+    int32_t mx = 0;
+    for (int32_t v = 0; v < n; v++)
+        if (colors[v] > mx) mx = colors[v];
+    st->num_colors = mx;
+    st->rounds = rounds;
+}
+
+static int color_common(const graph_t *g, uint32_t seed, const uint32_t *prio,
+                        const int32_t *init, int32_t max_rounds, int32_t *colors, orc_stats *st)
+{
+    int32_t n = g->n;
+    uint32_t *pkey = (uint32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    uint32_t *gkey = (uint32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    rounds_t rc;
+    int32_t rounds;
+    if (st) memset(st, 0, sizeof(*st));
+    fill_keys(n, NULL, seed, prio, pkey, gkey);
+    for (int32_t v = 0; v < n; v++) colors[v] = init ? init[v] : 0;
+    rc.g = g;
+    rc.n = n;
+    rc.n_base = n;
+    rc.ghost_col = NULL;
+    rc.ignore_from = n;
+    rc.pkey = pkey;
+    rc.gkey = gkey;
+    rc.max_rounds = max_rounds > 0 ? max_rounds : INT32_MAX;
+    rounds = run_rounds(&rc, colors, st, 0);
+    finish_stats(st, colors, n, rounds);
+    free(pkey);
+    free(gkey);
+    for (int32_t v = 0; v < n; v++)
+        if (colors[v] == 0) return 1;   /* round cap reached: partial state */
+    return 0;
+}
+
+int orc_color_d1(int32_t n, const int32_t *row_ptr, const int32_t *col, uint32_t seed,
+                 const uint32_t *prio, const int32_t *init, int32_t max_rounds,
+                 int32_t *colors, orc_stats *st)
+{
+    graph_t g = {1, n, row_ptr, col, NULL, NULL};
+    return color_common(&g, seed, prio, init, max_rounds, colors, st);
+}
+
+int orc_color_d2(int32_t n, const int32_t *row_ptr, const int32_t *col, uint32_t seed,
+                 const uint32_t *prio, const int32_t *init, int32_t max_rounds,
+                 int32_t *colors, orc_stats *st)
+{
+    graph_t g = {2, n, row_ptr, col, NULL, NULL};
+    return color_common(&g, seed, prio, init, max_rounds, colors, st);
+}
+
+int orc_color_pd2(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
+                  const int32_t *col_ptr, const int32_t *row_idx, uint32_t seed,
+                  const uint32_t *prio, const int32_t *init, int32_t max_rounds,
+                  int32_t *col_colors, orc_stats *st)
+{
+    (void)n_rows;
+    graph_t g = {3, n_cols, row_ptr, col_idx, col_ptr, row_idx};
+    return color_common(&g, seed, prio, init, max_rounds, col_colors, st);
+}
+
+/* One rank's step of Algorithm 2 for distance-1 (reading R6). */
+int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1,
+                       const int32_t *row_ptr, const int32_t *col, const int32_t *gid,
+                       const int32_t *ghost_colors, uint32_t seed,
+                       int32_t *owned_colors, unsigned char *remote_loser, orc_stats *st)
+{
+    int32_t m = n_owned + n_ghost;
+    uint32_t *pkey = (uint32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(uint32_t));
+    uint32_t *gkey = (uint32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(uint32_t));
+    unsigned char *loser = (unsigned char *)calloc((size_t)(n_owned > 0 ? n_owned : 1), 1);
+    graph_t g = {1, n_owned, row_ptr, col, NULL, NULL};
+    rounds_t rc;
+    int32_t r1, r3;
+    (void)layers;
+    (void)n_g1;   /* second-layer rows are carried but never read (ghosts are fixed) */
+    if (st) memset(st, 0, sizeof(*st));
+    fill_keys(m, gid, seed, NULL, pkey, gkey);
+    for (int32_t v = 0; v < n_owned; v++) owned_colors[v] = 0;
+    if (remote_loser)
+        for (int32_t j = 0; j < n_ghost; j++) remote_loser[j] = 0;
+
+    /* phase 1: ghost-blind rounds on the owned-induced subgraph */
+    rc.g = &g;
+    rc.n = n_owned;
+    rc.n_base = n_owned;
+    rc.ghost_col = ghost_colors;
+    rc.ignore_from = n_owned;
+    rc.pkey = pkey;
+    rc.gkey = gkey;
+    rc.max_rounds = INT32_MAX;
+    r1 = run_rounds(&rc, owned_colors, st, 0);
+
+    /* phase 2: every owned-ghost edge against the fixed ghost colors, all
+     * pairs judged on the phase-1 colors (Algorithm 3 with Algorithm 4) */
+    for (int32_t v = 0; v < n_owned; v++) {
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int32_t u = col[e];
+            if (u < n_owned) continue;
+            if (owned_colors[v] != ghost_colors[u - n_owned]) continue;
+            if (st) st->boundary_conflicts++;
+            if (key_greater(pkey[u], gkey[u], pkey[v], gkey[v]))
+                loser[v] = 1;
+            else if (remote_loser)
+                remote_loser[u - n_owned] = 1;
+        }
+    }
+    for (int32_t v = 0; v < n_owned; v++)
+        if (loser[v]) owned_colors[v] = 0;
+
+    /* phase 3: recolor the losers; ghosts are constraints with fixed colors */
+    rc.ignore_from = m;
+    r3 = run_rounds(&rc, owned_colors, st, r1);
+
+    finish_stats(st, owned_colors, n_owned, r1 + r3);
+    if (st && remote_loser) {
+        for (int32_t j = 0; j < n_ghost; j++) st->remote_losers += remote_loser[j];
+    }
+    free(pkey);
+    free(gkey);
+    free(loser);
+    return 0;
+}
+
+/* Algorithm 1: serial greedy in the given order. */
+void orc_serial_greedy(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                       const int32_t *order, int32_t *colors)
+{
+    graph_t g = {1, n, row_ptr, col, NULL, NULL};
+    list_t nb = {0};
+    for (int32_t v = 0; v < n; v++) colors[v] = 0;
+    for (int32_t i = 0; i < n; i++) {
+        int32_t v = order[i];
+        neighbourhood(&g, v, &nb);
+        colors[v] = first_fit(&nb, colors, n, NULL, n);
+    }
+    free(nb.ids);
+}
