@@ -1,0 +1,252 @@
+/*
+ * graphcolor.h — C-ABI of the MI355X (gfx950) speculative graph-coloring
+ * library (libgraphcolor.so).
+ *
+ * The library computes the on-node step of the distributed speculative
+ * coloring of Bogle et al., "Parallel Graph Coloring Algorithms for
+ * Distributed GPU Environments": distance-1 (D1), distance-2 (D2) and partial
+ * distance-2 (PD2) colorings (Section 2.1), by speculate-and-iterate rounds
+ * (Section 2.3; Section 3, Algorithm 2): every uncolored vertex takes the
+ * smallest color its neighbourhood does not use (first-fit, Section 2.2,
+ * Algorithm 1), conflicts are detected (Section 3.2, Algorithms 3 and 4;
+ * Section 3.5, Algorithm 5) and one endpoint of each conflict is uncolored and
+ * recolored in the next round.
+ *
+ * Result contract.  Rounds are synchronous: in each round every worklist
+ * vertex reads only the colors committed before the round, and all conflicts
+ * are judged at once on the round's tentative colors.  In a conflict the
+ * vertex with the LOWER key loses, key(v) = (p(v), gid(v)) compared
+ * lexicographically, p(v) = fmix32(gid(v) ^ fmix32(seed ^ 0x9E3779B9)) with
+ * fmix32 the MurmurHash3 32-bit finalizer (a bijection, so keys never tie).
+ * The coloring is therefore a deterministic function of (graph, keys) and is
+ * identical for every launch geometry, degree-bin setting, stream and
+ * batching mode.  Colors are 1-based; 0 means "uncolored" (Section 3.2) and
+ * never appears in a successful result.
+ *
+ * Memory.  Unless stated otherwise every array argument is a DEVICE pointer
+ * (memory from hipMalloc / a torch CUDA tensor) owned by the caller; the
+ * library never frees or retains it.  `stream` is a hipStream_t (NULL = the
+ * default stream).  Calls are blocking: they return after all work they
+ * enqueued on `stream` has finished.  The library keeps a per-device
+ * workspace that grows to the largest call seen (released by
+ * color_release_workspace); calls on one device are serialized by an
+ * internal lock.
+ *
+ * Graph layout.  A graph with n vertices is CSR: row_ptr int32[n+1]
+ * (row_ptr[0] = 0, non-decreasing), col_idx int32[row_ptr[n]] with
+ * 0 <= col_idx < n.  D1/D2 need a symmetric adjacency without self-loops
+ * (the paper removes self-loops and multi-edges before coloring, Section 4).
+ * With COLOR_FLAG_VALIDATE the library checks the contract on the device
+ * (rows must then be strictly increasing) and returns COLOR_EGRAPH on a
+ * violation; without it the input is trusted.
+ *
+ * Errors.  Every entry point returns COLOR_OK (0) or a negative code; no
+ * entry point aborts the process.  On an error the output arrays are
+ * unspecified except for COLOR_ENOCONVERGE, where they hold the committed
+ * partial coloring (0 = not yet colored) from which a later call can resume
+ * via init_colors.
+ */
+#ifndef GRAPHCOLOR_H
+#define GRAPHCOLOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COLOR_OK            0
+#define COLOR_EINVAL       -1   /* bad size, null pointer, bad parameter */
+#define COLOR_EGRAPH       -2   /* COLOR_FLAG_VALIDATE: graph violates the input contract */
+#define COLOR_EOVERFLOW    -3   /* a size does not fit the int32 indexing */
+#define COLOR_ENOMEM       -4   /* device or host allocation failed */
+#define COLOR_EHIP         -5   /* a HIP runtime call failed */
+#define COLOR_ENOCONVERGE  -6   /* params->max_rounds reached: outputs hold the partial state */
+#define COLOR_E2BIG        -7   /* server: the job can never fit the HBM budget */
+#define COLOR_EQUEUED       1   /* server: job accepted, waiting for memory/slots */
+#define COLOR_EPENDING      2   /* server: job not finished yet */
+
+#define COLOR_FLAG_VALIDATE 0x1u  /* check the input contract on the device first */
+#define COLOR_FLAG_NO_TAIL  0x2u  /* never switch to the single-workgroup tail kernel */
+
+/* Per-call statistics (HOST struct, every pointer argument of this type is
+ * nullable). */
+typedef struct color_stats {
+    int32_t num_colors;          /* largest color in the output */
+    int32_t rounds;              /* rounds with a non-empty worklist */
+    int64_t vertex_visits;       /* sum over rounds of |W_r| */
+    int64_t edge_visits;         /* sum over rounds of the adjacency entries of W_r
+                                    (D2/PD2: entries of the two-hop walk) */
+    int64_t boundary_conflicts;  /* ghost variant: equal-colored owned-ghost pairs after phase 1 */
+    int64_t remote_losers;       /* ghost variant: ghosts that lost a boundary conflict */
+    int64_t* worklist_trace;     /* in: HOST array or NULL; out: |W_r| for r = 1..min(rounds, trace_cap) */
+    int32_t trace_cap;           /* in: capacity of worklist_trace */
+    int32_t kernel_launches;     /* kernels the call enqueued */
+} color_stats;
+
+/* Tuning knobs (HOST struct, nullable = library defaults / autotuned).  None
+ * of them changes a coloring; they only change how the work is mapped onto
+ * the GPU.  A zero field means "default". */
+typedef struct color_params {
+    int32_t bin_hi[4];      /* work bounds of degree bins 0..3 (bin 4 = above bin_hi[3]) */
+    int32_t lanes[3];       /* lanes per vertex of bins 0..2: 1,2,4,8,16,32 or 64 */
+    int32_t split_chunks;   /* workgroups per vertex in bin 4 */
+    int32_t max_rounds;     /* stop after this many rounds: COLOR_ENOCONVERGE */
+    int32_t rounds_per_poll;/* rounds enqueued between host checks of the worklist size */
+    int32_t tail_threshold; /* worklist size below which the tail kernel finishes the call */
+    int32_t max_workgroups; /* cap on the grid of the round kernels */
+    uint32_t flags;         /* COLOR_FLAG_* */
+} color_params;
+
+/* Distance-1 coloring (Section 2.1; Section 3.2).
+ *   n            vertices (>= 0)
+ *   row_ptr      int32[n+1], col_idx int32[row_ptr[n]]: symmetric CSR
+ *   seed         selects the priority hash p(v) (gid(v) = v)
+ *   prio         nullable uint32[n]: explicit p(v) replacing the hash
+ *   init_colors  nullable int32[n]: non-zero entries are committed colors
+ *                that stay fixed (a proper partial coloring, e.g. the
+ *                partial state returned with COLOR_ENOCONVERGE); zero
+ *                entries are colored (Section 3.2: the coloring functions
+ *                accept a partial coloring)
+ *   colors       out int32[n]
+ * Returns COLOR_OK, COLOR_EINVAL, COLOR_EGRAPH, COLOR_EOVERFLOW,
+ * COLOR_ENOMEM, COLOR_EHIP or COLOR_ENOCONVERGE. */
+int color_d1(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t seed,
+             const uint32_t* prio, const int32_t* init_colors, int32_t* colors,
+             color_stats* stats, const color_params* params, void* stream);
+
+/* Distance-2 coloring (Section 2.1; Section 3.5, Algorithm 5 without
+ * doPartialColoring): vertices within two hops get different colors;
+ * the two-hop neighbourhood of v is N(v) u N(N(v)) minus v.  Same arguments
+ * and errors as color_d1. */
+int color_d2(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t seed,
+             const uint32_t* prio, const int32_t* init_colors, int32_t* colors,
+             color_stats* stats, const color_params* params, void* stream);
+
+/* Partial distance-2 coloring of the columns of an n_rows x n_cols sparse
+ * pattern (Section 2.1; Section 3.6, doPartialColoring): two columns that
+ * share a row get different colors; rows are not colored.
+ *   row_ptr int32[n_rows+1], col_idx int32[nnz]  pattern in CSR
+ *   col_ptr int32[n_cols+1], row_idx int32[nnz]  the same pattern in CSC
+ *   prio, init_colors: nullable, indexed by column; col_colors out int32[n_cols]
+ * gid(column) = column index.  Same errors as color_d1. */
+int color_pd2(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr, const int32_t* col_idx,
+              const int32_t* col_ptr, const int32_t* row_idx, uint32_t seed,
+              const uint32_t* prio, const int32_t* init_colors, int32_t* col_colors,
+              color_stats* stats, const color_params* params, void* stream);
+
+/* One rank's step of the distributed D1 method (Section 3, Algorithm 2 with
+ * Algorithms 3 and 4; Section 3.4 for the second ghost layer) on its local
+ * graph G_l = {V_l + V_g, E_l + E_g} (Section 2.4).
+ *   Local ids: owned vertices [0, n_owned), then ghosts
+ *   [n_owned, n_owned + n_ghost); with layers == 2 the first n_g1 ghosts are
+ *   the first ghost layer and carry rows.
+ *   row_ptr int32[n_rows+1], n_rows = n_owned (layers 1) or n_owned + n_g1
+ *   (layers 2); col_idx local ids in [0, n_owned + n_ghost).
+ *   gid          int32[n_owned + n_ghost]: global ids (keys use gid)
+ *   ghost_colors int32[n_ghost]: the ghosts' fixed colors (>= 1), read only
+ *   owned_colors out int32[n_owned]
+ *   remote_loser out uint8[n_ghost], nullable: 1 where a ghost lost a
+ *                boundary conflict to an owned vertex (its owner recolors it)
+ * Phase 1 colors the owned vertices ignoring ghosts (Section 3.2: the
+ * initial coloring needs no ghost information); phase 2 compares every
+ * owned-ghost edge with the key rule on the ghosts' colors; phase 3 recolors
+ * the owned losers with the ghost colors as constraints.  Ghost colors are
+ * never written (the save/restore of gc in Algorithm 2).  The second layer's
+ * rows are accepted; with fixed ghost colors they do not change the result.
+ * Same errors as color_d1 (COLOR_EINVAL also for layers not 1 or 2). */
+int color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1,
+                   const int32_t* row_ptr, const int32_t* col_idx, const int32_t* gid,
+                   const int32_t* ghost_colors, uint32_t seed, int32_t* owned_colors,
+                   uint8_t* remote_loser, color_stats* stats, const color_params* params,
+                   void* stream);
+
+/* The priority p of Algorithm 4's rand(GID) as the kernels compute it:
+ * out[i] = p(gid ? gid[i] : i) for i < n.  gid nullable (identity).
+ * Returns COLOR_OK, COLOR_EINVAL or COLOR_EHIP. */
+int color_priority(int32_t n, const int32_t* gid, uint32_t seed, uint32_t* out, void* stream);
+
+/* ----------------------------------------------------------------------- */
+/* Batched form: many graphs in one persistent, worklist-driven launch.     */
+/* ----------------------------------------------------------------------- */
+
+#define COLOR_KIND_D1  1
+#define COLOR_KIND_D2  2
+#define COLOR_KIND_PD2 3
+
+/* One coloring job.  D1/D2: n = vertices, row_ptr/col_idx = adjacency,
+ * col_ptr/row_idx unused.  PD2: n = columns, n_rows = rows, row_ptr/col_idx
+ * = CSR, col_ptr/row_idx = CSC.  Device pointers; colors = output. */
+typedef struct color_job {
+    int32_t kind;
+    int32_t n;
+    int32_t n_rows;
+    uint32_t seed;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const int32_t* col_ptr;
+    const int32_t* row_idx;
+    int32_t* colors;
+} color_job;
+
+/* Colors num_jobs independent graphs in one persistent launch whose
+ * workgroups pull (job, round, phase, tile) items from a device queue; each
+ * job's coloring is identical to the single-graph call of its kind.
+ * jobs: HOST array of device-pointer descriptors; per_job: nullable HOST
+ * array of num_jobs stats.  Returns the first error met. */
+int color_batch(int32_t num_jobs, const color_job* jobs, color_stats* per_job,
+                const color_params* params, void* stream);
+
+/* ----------------------------------------------------------------------- */
+/* Served form: continuous batching with HBM-footprint admission.          */
+/* ----------------------------------------------------------------------- */
+
+typedef struct color_server color_server;
+
+/* A served job carries HOST arrays (the server copies them to the device
+ * while other jobs run).  Same field meaning as color_job. */
+typedef struct color_host_job {
+    int32_t kind;
+    int32_t n;
+    int32_t n_rows;
+    uint32_t seed;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const int32_t* col_ptr;
+    const int32_t* row_idx;
+} color_host_job;
+
+/* Creates a server on the current device with an HBM budget (bytes) for
+ * resident job state and at most max_slots jobs on the device at once.
+ * *err receives COLOR_OK or an error; returns NULL on error. */
+color_server* color_server_create(size_t hbm_budget_bytes, int32_t max_slots, int* err);
+
+/* Queues a job (arrays are copied before return).  Returns COLOR_OK (job
+ * admitted to the device), COLOR_EQUEUED (waiting for memory or a slot),
+ * COLOR_E2BIG (can never fit the budget) or COLOR_EINVAL.  *job_id is set
+ * when the job was accepted. */
+int color_server_submit(color_server* s, const color_host_job* job, uint64_t* job_id);
+
+/* Advances the server (admits queued jobs, runs rounds of the resident
+ * jobs).  Returns COLOR_OK when job_id has finished (host_colors receives
+ * its n colors, stats is filled; the job's slot and memory are freed),
+ * COLOR_EPENDING when it has not, COLOR_EINVAL for an unknown id. */
+int color_server_poll(color_server* s, uint64_t job_id, int32_t* host_colors, color_stats* stats);
+
+/* Runs the server until every accepted job has finished. */
+int color_server_drain(color_server* s);
+
+int color_server_destroy(color_server* s);
+
+/* Frees the per-device workspace cache of the single-graph entry points. */
+int color_release_workspace(void);
+
+/* Static description of an error code. */
+const char* color_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAPHCOLOR_H */

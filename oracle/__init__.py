@@ -62,6 +62,8 @@ def lib():
         l.orc_fmix32.argtypes = [ctypes.c_uint32]
         l.orc_priority.restype = ctypes.c_uint32
         l.orc_priority.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        l.orc_priorities.restype = None
+        l.orc_priorities.argtypes = [ctypes.c_int32, ctypes.c_uint32, P]
         sig = [ctypes.c_int32, P, P, ctypes.c_uint32, P, P, ctypes.c_int32, P, P]
         for name in ("orc_color_d1", "orc_color_d2"):
             getattr(l, name).restype = ctypes.c_int
@@ -101,8 +103,11 @@ def priority(gid: int, seed: int) -> int:
     return int(lib().orc_priority(gid & 0xFFFFFFFF, seed & 0xFFFFFFFF))
 
 
-def priorities(ids, seed: int) -> np.ndarray:
-    return np.array([priority(int(i), seed) for i in ids], dtype=np.uint32)
+def priorities(n: int, seed: int) -> np.ndarray:
+    """p(i) for i in [0, n)."""
+    out = np.empty(n, dtype=np.uint32)
+    lib().orc_priorities(n, seed & 0xFFFFFFFF, _ptr(out))
+    return out
 
 
 def _prio_init(prio, init):

@@ -71,6 +71,11 @@ uint32_t orc_priority(uint32_t gid, uint32_t seed)
     return orc_fmix32(gid ^ s);
 }
 
+void orc_priorities(int32_t n, uint32_t seed, uint32_t *out)
+{
+    for (int32_t i = 0; i < n; i++) out[i] = orc_priority((uint32_t)i, seed);
+}
+
 /* 1 if key(a) > key(b); key = (p, gid) lexicographic (reading R2). */
 static int key_greater(uint32_t pa, uint32_t ga, uint32_t pb, uint32_t gb)
 {

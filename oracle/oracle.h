@@ -19,6 +19,7 @@ typedef struct {
 
 uint32_t orc_fmix32(uint32_t h);
 uint32_t orc_priority(uint32_t gid, uint32_t seed);
+void orc_priorities(int32_t n, uint32_t seed, uint32_t *out);  /* out[i] = p(i) */
 
 /* Return 0 when every vertex is colored, 1 when max_rounds (>0) stopped the
  * loop first (colors then hold the committed partial state, 0 = uncolored). */

@@ -1,0 +1,535 @@
+// C-ABI entry points and the host round driver of libgraphcolor.
+//
+// Driver (Algorithm 2's "while conflicts > 0" loop, on one GPU): the static
+// setup (work, bins, initial worklist) costs one host synchronization; then
+// rounds are enqueued in batches of R back-to-back (color, detect) launch
+// pairs with no host round trip inside a batch.  Kernels read the worklist
+// sizes from device memory, so rounds enqueued after the worklist emptied
+// are no-ops; the host reads the sizes once per batch and doubles R up to a
+// cap, so a call with r rounds costs O(log r) synchronizations.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "api_internal.hpp"
+
+namespace gcol {
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+
+int DevBuf::ensure(size_t need, bool zero, hipStream_t st) {
+  if (need == 0) need = 1;
+  if (bytes >= need) return COLOR_OK;
+  if (p) {
+    if (hipFree(p) != hipSuccess) return COLOR_EHIP;
+    p = nullptr;
+    bytes = 0;
+  }
+  size_t want = need + need / 4;  // headroom so slowly growing calls do not reallocate each time
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    if (hipMalloc(&p, need) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return COLOR_ENOMEM;
+    }
+    want = need;
+  }
+  bytes = want;
+  if (zero && hipMemsetAsync(p, 0, want, st) != hipSuccess) return COLOR_EHIP;
+  return COLOR_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+Workspace::~Workspace() { release(); }
+
+void Workspace::release() {
+  for (DevBuf* b : {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
+                    &split_flag, &split_mask, &aux0, &aux1})
+    b->release();
+  if (host) (void)hipHostFree(host);
+  host = nullptr;
+}
+
+static std::mutex g_ws_mu;
+static std::map<int, Workspace*> g_ws;
+
+Workspace* workspace_for_current_device(int* err) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *err = COLOR_EHIP;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto it = g_ws.find(dev);
+  if (it != g_ws.end()) return it->second;
+  Workspace* w = new Workspace();
+  w->device = dev;
+  if (hipHostMalloc(reinterpret_cast<void**>(&w->host), sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
+    delete w;
+    *err = COLOR_ENOMEM;
+    return nullptr;
+  }
+  g_ws[dev] = w;
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// parameters
+// ---------------------------------------------------------------------------
+
+static bool valid_lanes(int x) {
+  return x == 1 || x == 2 || x == 4 || x == 8 || x == 16 || x == 32 || x == 64;
+}
+
+void default_params(int mode, color_params* p) {
+  std::memset(p, 0, sizeof(*p));
+  if (mode == kD1) {
+    const int32_t hi[4] = {12, 96, 2048, 65536};
+    const int32_t ln[3] = {4, 16, 64};
+    std::memcpy(p->bin_hi, hi, sizeof(hi));
+    std::memcpy(p->lanes, ln, sizeof(ln));
+    p->split_chunks = 64;
+  } else if (mode == kD2) {
+    const int32_t hi[4] = {64, 512, 8192, 262144};
+    const int32_t ln[3] = {4, 16, 64};
+    std::memcpy(p->bin_hi, hi, sizeof(hi));
+    std::memcpy(p->lanes, ln, sizeof(ln));
+    p->split_chunks = 64;
+  } else {
+    const int32_t hi[4] = {256, 2048, 32768, 524288};
+    const int32_t ln[3] = {8, 32, 64};
+    std::memcpy(p->bin_hi, hi, sizeof(hi));
+    std::memcpy(p->lanes, ln, sizeof(ln));
+    p->split_chunks = 256;
+  }
+  p->max_rounds = 0;
+  p->rounds_per_poll = 4;
+  p->tail_threshold = 0;
+  p->max_workgroups = 2048;
+  p->flags = 0;
+}
+
+int merge_params(int mode, const color_params* user, color_params* out) {
+  default_params(mode, out);
+  if (!user) return COLOR_OK;
+  for (int i = 0; i < 4; ++i)
+    if (user->bin_hi[i] > 0) out->bin_hi[i] = user->bin_hi[i];
+  for (int i = 0; i < 3; ++i) {
+    if (user->lanes[i] != 0) {
+      if (!valid_lanes(user->lanes[i])) return COLOR_EINVAL;
+      out->lanes[i] = user->lanes[i];
+    }
+  }
+  for (int i = 1; i < 4; ++i)
+    if (out->bin_hi[i] < out->bin_hi[i - 1]) return COLOR_EINVAL;
+  if (user->split_chunks < 0 || user->max_rounds < 0 || user->rounds_per_poll < 0 ||
+      user->max_workgroups < 0 || user->tail_threshold < 0)
+    return COLOR_EINVAL;
+  if (user->split_chunks > 0) out->split_chunks = std::min(user->split_chunks, 1 << 16);
+  if (user->max_rounds > 0) out->max_rounds = user->max_rounds;
+  if (user->rounds_per_poll > 0) out->rounds_per_poll = std::min(user->rounds_per_poll, 1024);
+  if (user->max_workgroups > 0) out->max_workgroups = user->max_workgroups;
+  if (user->tail_threshold > 0) out->tail_threshold = user->tail_threshold;
+  out->flags = user->flags;
+  return COLOR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the round loop
+// ---------------------------------------------------------------------------
+
+template <int MODE>
+int run_phase(Call& c, const GraphView& g, const KeySource& k, const BinLayout& L, const RoundBufs& base,
+              int32_t known[kBins], int round0, int max_rounds) {
+  Scalars* S = c.S;
+  Scalars* H = c.H;
+  int32_t* wl[2] = {c.wl[0], c.wl[1]};
+  int local = 0;
+  int R = std::max(1, c.P.rounds_per_poll);
+  while (true) {
+    int64_t total = 0;
+    for (int i = 0; i < kBins; ++i) total += known[i];
+    if (total == 0) break;
+    if (max_rounds > 0 && local >= max_rounds) return COLOR_ENOCONVERGE;
+    const int64_t units = round_units(known, L);
+    const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(units, c.P.max_workgroups)));
+    int n_launch = R;
+    if (max_rounds > 0) n_launch = std::min(n_launch, max_rounds - local);
+    for (int i = 0; i < n_launch; ++i) {
+      ++local;
+      RoundBufs b = base;
+      const int pin = (local - 1) & 1, pout = local & 1;
+      b.wl_in = wl[pin];
+      b.wl_out = wl[pout];
+      b.cnt_in = S->cnt[pin];
+      b.cnt_out = S->cnt[pout];
+      launch_color_round<MODE>(g, k, b, L, round0 + local, grid, c.st);
+      launch_detect_round<MODE>(g, k, b, L, round0 + local, grid, c.st);
+      c.launches += 2;
+    }
+    if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
+    if (hipMemcpyAsync(H->cnt[local & 1], S->cnt[local & 1], sizeof(int32_t) * 8, hipMemcpyDeviceToHost,
+                       c.st) != hipSuccess)
+      return COLOR_EHIP;
+    if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+    for (int i = 0; i < kBins; ++i) known[i] = H->cnt[local & 1][i];
+    R = std::min(R * 2, 64);
+  }
+  return COLOR_OK;
+}
+
+template int run_phase<kD1>(Call&, const GraphView&, const KeySource&, const BinLayout&, const RoundBufs&,
+                            int32_t*, int, int);
+template int run_phase<kD2>(Call&, const GraphView&, const KeySource&, const BinLayout&, const RoundBufs&,
+                            int32_t*, int, int);
+template int run_phase<kPD2>(Call&, const GraphView&, const KeySource&, const BinLayout&, const RoundBufs&,
+                             int32_t*, int, int);
+
+// Static setup of a phase-1 worklist: work and bins, region layout, split
+// scratch, initial worklist.  Leaves the initial per-bin counts in known[].
+template <int MODE>
+int setup_bins(Call& c, const GraphView& g, const int32_t* init, int32_t* C, int32_t n_total, BinLayout& L,
+               RoundBufs& rb, int32_t known[kBins]) {
+  Workspace* w = c.ws;
+  Scalars* S = c.S;
+  Scalars* H = c.H;
+  const int32_t n = g.n;
+  BinSetup s;
+  for (int i = 0; i < 4; ++i) s.bin_hi[i] = c.P.bin_hi[i];
+  s.init = init;
+  s.C = C;
+  s.T = w->T.as<int32_t>();
+  s.work = w->work.as<int32_t>();
+  s.bin = w->bin.as<int8_t>();
+  s.count_all = S->count_all;
+  s.count_unc = S->count_unc;
+  s.maxc = &S->maxc;
+  s.max_split_work = &S->max_split_work;
+  s.total_work = &S->total_work;
+  launch_bin<MODE>(g, s, c.st);
+  c.launches += 1;
+  if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
+  if (hipMemcpyAsync(H, S, sizeof(Scalars), hipMemcpyDeviceToHost, c.st) != hipSuccess) return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+
+  int32_t off = 0;
+  for (int i = 0; i < kBins; ++i) {
+    L.off[i] = off;
+    off += H->count_all[i];
+  }
+  for (int i = 0; i < 3; ++i) L.lanes[i] = c.P.lanes[i];
+  L.split_chunks = c.P.split_chunks;
+  L.grab = 4;
+  const int32_t nsplit = H->count_all[kSplitBin];
+  const int64_t bound = std::min<int64_t>(H->max_split_work, n_total);
+  int32_t capw = static_cast<int32_t>(bound / 32 + 2);
+  if (nsplit > 0) {
+    int e;
+    if ((e = w->split_vertex.ensure(sizeof(int32_t) * nsplit, false, c.st))) return e;
+    if ((e = w->split_ctr.ensure(sizeof(uint32_t) * nsplit, true, c.st))) return e;
+    if ((e = w->split_flag.ensure(sizeof(uint32_t) * nsplit, true, c.st))) return e;
+    if ((e = w->split_mask.ensure(sizeof(uint32_t) * static_cast<size_t>(nsplit) * capw, true, c.st)))
+      return e;
+  }
+  rb.C = C;
+  rb.T = w->T.as<int32_t>();
+  rb.work = w->work.as<int32_t>();
+  rb.tile_ctr = S->tile_ctr;
+  rb.split_vertex = w->split_vertex.as<int32_t>();
+  rb.split_mask = w->split_mask.as<uint32_t>();
+  rb.capw = capw;
+  rb.split_ctr = w->split_ctr.as<uint32_t>();
+  rb.split_flag = w->split_flag.as<uint32_t>();
+  rb.maxc = &S->maxc;
+  rb.visits = S->visits;
+  rb.trace = w->trace.as<int32_t>();
+  rb.trace_cap = c.trace_cap;
+  rb.rounds_done = &S->rounds_done;
+
+  launch_scatter(n, C, w->bin.as<int8_t>(), L, c.wl[0], S->cnt[0], w->split_vertex.as<int32_t>(), c.st);
+  c.launches += 1;
+  for (int i = 0; i < kBins; ++i) known[i] = H->count_unc[i];
+  return hipGetLastError() == hipSuccess ? COLOR_OK : COLOR_EHIP;
+}
+
+template int setup_bins<kD1>(Call&, const GraphView&, const int32_t*, int32_t*, int32_t, BinLayout&,
+                             RoundBufs&, int32_t*);
+template int setup_bins<kD2>(Call&, const GraphView&, const int32_t*, int32_t*, int32_t, BinLayout&,
+                             RoundBufs&, int32_t*);
+template int setup_bins<kPD2>(Call&, const GraphView&, const int32_t*, int32_t*, int32_t, BinLayout&,
+                              RoundBufs&, int32_t*);
+
+int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, void* stream, int32_t n,
+               int32_t n_total) {
+  int e = merge_params(mode, user, &c.P);
+  if (e) return e;
+  c.st = static_cast<hipStream_t>(stream);
+  c.ws = workspace_for_current_device(&e);
+  if (!c.ws) return e;
+  c.trace_cap = (stats && stats->worklist_trace && stats->trace_cap > 0) ? stats->trace_cap : 0;
+  Workspace* w = c.ws;
+  if ((e = w->small.ensure(sizeof(Scalars), false, c.st))) return e;
+  if ((e = w->T.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n_total, 1)), false, c.st))) return e;
+  if ((e = w->work.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n, 1)), false, c.st))) return e;
+  if ((e = w->bin.ensure(static_cast<size_t>(std::max(n, 1)), false, c.st))) return e;
+  if ((e = w->wl0.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n, 1)), false, c.st))) return e;
+  if ((e = w->wl1.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n, 1)), false, c.st))) return e;
+  if ((e = w->trace.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(c.trace_cap, 1)), false, c.st)))
+    return e;
+  c.S = w->small.as<Scalars>();
+  c.H = w->host;
+  c.wl[0] = w->wl0.as<int32_t>();
+  c.wl[1] = w->wl1.as<int32_t>();
+  if (hipMemsetAsync(c.S, 0, sizeof(Scalars), c.st) != hipSuccess) return COLOR_EHIP;
+  return COLOR_OK;
+}
+
+int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc) {
+  if (hipMemcpyAsync(c.H, c.S, sizeof(Scalars), hipMemcpyDeviceToHost, c.st) != hipSuccess) return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  if (stats) {
+    stats->num_colors = num_colors_hint >= 0 ? num_colors_hint : c.H->maxc;
+    stats->rounds = c.H->rounds_done;
+    stats->vertex_visits = static_cast<int64_t>(c.H->visits[0]);
+    stats->edge_visits = static_cast<int64_t>(c.H->visits[1]);
+    stats->boundary_conflicts = static_cast<int64_t>(c.H->conflicts);
+    stats->remote_losers = static_cast<int64_t>(c.H->remote);
+    stats->kernel_launches = c.launches;
+    if (c.trace_cap > 0) {
+      const int nr = std::min(c.trace_cap, c.H->rounds_done);
+      if (nr > 0) {
+        int32_t* tmp = new int32_t[nr];
+        if (hipMemcpy(tmp, c.ws->trace.p, sizeof(int32_t) * nr, hipMemcpyDeviceToHost) != hipSuccess) {
+          delete[] tmp;
+          return COLOR_EHIP;
+        }
+        for (int i = 0; i < nr; ++i) stats->worklist_trace[i] = tmp[i];
+        delete[] tmp;
+      }
+    }
+  }
+  return rc;
+}
+
+static int check_rowptr_graph(Call& c, int32_t n_rows, int32_t n_cols, const int32_t* rp, const int32_t* ci,
+                              const int32_t* rpT, const int32_t* ciT, int square) {
+  launch_validate(n_rows, n_cols, rp, ci, rpT, ciT, n_cols, square, &c.S->err, c.st);
+  c.launches += 2;
+  if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
+  if (hipMemcpyAsync(&c.H->err, &c.S->err, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) != hipSuccess)
+    return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  return c.H->err ? COLOR_EGRAPH : COLOR_OK;
+}
+
+// nnz = row_ptr[n] read from the device (sizes the validation and stats).
+static int read_nnz(Call& c, const int32_t* rp, int32_t n, int32_t* nnz) {
+  if (hipMemcpyAsync(&c.H->err, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) != hipSuccess)
+    return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  *nnz = c.H->err;
+  c.H->err = 0;
+  return COLOR_OK;
+}
+
+template <int MODE>
+static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32_t* ci, const int32_t* rp2,
+                       const int32_t* ci2, uint32_t seed, const uint32_t* prio, const int32_t* init,
+                       int32_t* colors, color_stats* stats, const color_params* params, void* stream) {
+  if (n < 0 || n_rows < 0) return COLOR_EINVAL;
+  if (n > 0 && (!rp || !ci || !colors)) return COLOR_EINVAL;
+  if (MODE == kPD2 && n > 0 && (!rp2 || !ci2)) return COLOR_EINVAL;
+  if (n == INT_MAX || n_rows == INT_MAX) return COLOR_EOVERFLOW;
+  Call c;
+  int e = begin_call(c, MODE, params, stats, stream, n, n);
+  if (e) return e;
+  std::unique_lock<std::mutex> lk(c.ws->mu);
+  if (n == 0) return finish_call(c, stats, 0, COLOR_OK);
+  if (c.P.flags & COLOR_FLAG_VALIDATE) {
+    int32_t nnz = 0;
+    if ((e = read_nnz(c, rp, n, &nnz))) return e;
+    if (nnz < 0) return COLOR_EGRAPH;
+    if (MODE == kPD2) {
+      int32_t nnz2 = 0;
+      if ((e = read_nnz(c, rp2, n_rows, &nnz2))) return e;
+      if (nnz2 != nnz) return COLOR_EGRAPH;
+      // CSC (column -> rows) against CSR (row -> columns), both directions
+      if ((e = check_rowptr_graph(c, n, n_rows, rp, ci, rp2, ci2, 0))) return e;
+      if ((e = check_rowptr_graph(c, n_rows, n, rp2, ci2, rp, ci, 0))) return e;
+    } else {
+      if ((e = check_rowptr_graph(c, n, n, rp, ci, rp, ci, 1))) return e;
+    }
+    if (init) {
+      // init colors must be a proper partial coloring: validated on the host
+      // side is too costly for large graphs; the device check below covers
+      // the D1 case, the D2/PD2 cases rely on the caller.
+    }
+  }
+  GraphView g{n, n, rp, ci, MODE == kD1 ? rp : rp2, MODE == kD1 ? ci : ci2};
+  if (MODE == kD2) {
+    g.rp2 = rp;
+    g.ci2 = ci;
+  }
+  KeySource k{prio, nullptr, hash_seed(seed)};
+  BinLayout L;
+  RoundBufs rb;
+  int32_t known[kBins];
+  if ((e = setup_bins<MODE>(c, g, init, colors, n, L, rb, known))) return e;
+  const int rc = run_phase<MODE>(c, g, k, L, rb, known, 0, c.P.max_rounds);
+  if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
+  return finish_call(c, stats, -1, rc);
+}
+
+}  // namespace gcol
+
+using namespace gcol;
+
+extern "C" {
+
+int color_d1(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t seed, const uint32_t* prio,
+             const int32_t* init_colors, int32_t* colors, color_stats* stats, const color_params* params,
+             void* stream) {
+  return color_graph<kD1>(n, n, row_ptr, col_idx, row_ptr, col_idx, seed, prio, init_colors, colors, stats,
+                          params, stream);
+}
+
+int color_d2(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t seed, const uint32_t* prio,
+             const int32_t* init_colors, int32_t* colors, color_stats* stats, const color_params* params,
+             void* stream) {
+  return color_graph<kD2>(n, n, row_ptr, col_idx, row_ptr, col_idx, seed, prio, init_colors, colors, stats,
+                          params, stream);
+}
+
+int color_pd2(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr, const int32_t* col_idx,
+              const int32_t* col_ptr, const int32_t* row_idx, uint32_t seed, const uint32_t* prio,
+              const int32_t* init_colors, int32_t* col_colors, color_stats* stats, const color_params* params,
+              void* stream) {
+  if (n_cols > 0 && n_rows > 0 && (!row_ptr || !col_idx)) return COLOR_EINVAL;
+  // hop 1: column -> rows (CSC); hop 2: row -> columns (CSR)
+  return color_graph<kPD2>(n_cols, n_rows, col_ptr, row_idx, row_ptr, col_idx, seed, prio, init_colors,
+                           col_colors, stats, params, stream);
+}
+
+int color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1, const int32_t* row_ptr,
+                   const int32_t* col_idx, const int32_t* gid, const int32_t* ghost_colors, uint32_t seed,
+                   int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats, const color_params* params,
+                   void* stream) {
+  if (n_owned < 0 || n_ghost < 0 || n_g1 < 0 || n_g1 > n_ghost) return COLOR_EINVAL;
+  if (layers != 1 && layers != 2) return COLOR_EINVAL;
+  if (static_cast<int64_t>(n_owned) + n_ghost >= INT_MAX) return COLOR_EOVERFLOW;
+  if (n_owned > 0 && (!row_ptr || !col_idx || !gid || !owned_colors)) return COLOR_EINVAL;
+  if (n_ghost > 0 && (!ghost_colors || !gid)) return COLOR_EINVAL;
+  const int32_t m = n_owned + n_ghost;
+  Call c;
+  int e = begin_call(c, kD1, params, stats, stream, n_owned, m);
+  if (e) return e;
+  std::unique_lock<std::mutex> lk(c.ws->mu);
+  if (n_owned == 0) return finish_call(c, stats, 0, COLOR_OK);
+  Workspace* w = c.ws;
+  if ((e = w->C.ensure(sizeof(int32_t) * static_cast<size_t>(m), false, c.st))) return e;
+  if ((e = w->aux0.ensure(sizeof(int32_t) * static_cast<size_t>(n_owned), false, c.st))) return e;
+  if ((e = w->aux1.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n_ghost, 1)), false, c.st))) return e;
+  int32_t* Cint = w->C.as<int32_t>();
+  const int32_t n_rows = layers == 2 ? n_owned + n_g1 : n_owned;
+  if (c.P.flags & COLOR_FLAG_VALIDATE) {
+    // rows of owned (and layer-1) vertices: in range, sorted; symmetry is not
+    // required for the ghost rows' partners outside the local graph
+    launch_validate(n_rows, m, row_ptr, col_idx, row_ptr, col_idx, n_rows, 1, &c.S->err, c.st);
+    if (hipMemcpyAsync(&c.H->err, &c.S->err, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) != hipSuccess)
+      return COLOR_EHIP;
+    if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+    if (c.H->err) return COLOR_EGRAPH;
+    if (hipMemsetAsync(&c.S->err, 0, sizeof(int32_t), c.st) != hipSuccess) return COLOR_EHIP;
+  }
+  KeySource k{nullptr, gid, hash_seed(seed)};
+  // phase 1: ghost-blind rounds on the owned-induced subgraph
+  GraphView g{n_owned, n_owned, row_ptr, col_idx, row_ptr, col_idx};
+  BinLayout L;
+  RoundBufs rb;
+  int32_t known[kBins];
+  if ((e = setup_bins<kD1>(c, g, nullptr, Cint, m, L, rb, known))) return e;
+  int rc = run_phase<kD1>(c, g, k, L, rb, known, 0, c.P.max_rounds);
+  if (rc != COLOR_OK) return rc == COLOR_ENOCONVERGE ? finish_call(c, stats, -1, rc) : rc;
+  if (hipMemcpyAsync(&c.H->rounds_done, &c.S->rounds_done, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) !=
+      hipSuccess)
+    return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  const int r1 = c.H->rounds_done;
+  // phase 2: boundary conflicts against the ghosts' fixed colors
+  int32_t* loser = w->aux0.as<int32_t>();
+  int32_t* gflag = w->aux1.as<int32_t>();
+  if (hipMemsetAsync(gflag, 0, sizeof(int32_t) * static_cast<size_t>(std::max(n_ghost, 1)), c.st) != hipSuccess)
+    return COLOR_EHIP;
+  launch_boundary(n_owned, row_ptr, col_idx, Cint, ghost_colors, k, loser, gflag, &c.S->conflicts, c.st);
+  launch_boundary_uncolor(n_owned, loser, Cint, c.st);
+  // phase 3: ghosts become fixed committed colors; losers are recolored
+  launch_ghost_fill(n_owned, n_ghost, ghost_colors, Cint, rb.T, &c.S->maxc, c.st);
+  c.launches += 3;
+  if (hipMemsetAsync(c.S->cnt[0], 0, sizeof(int32_t) * 8, c.st) != hipSuccess) return COLOR_EHIP;
+  launch_scatter(n_owned, Cint, w->bin.as<int8_t>(), L, c.wl[0], c.S->cnt[0], w->split_vertex.as<int32_t>(), c.st);
+  c.launches += 1;
+  if (hipMemcpyAsync(c.H->cnt[0], c.S->cnt[0], sizeof(int32_t) * 8, hipMemcpyDeviceToHost, c.st) != hipSuccess)
+    return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  for (int i = 0; i < kBins; ++i) known[i] = c.H->cnt[0][i];
+  g.limit = m;
+  rc = run_phase<kD1>(c, g, k, L, rb, known, r1, c.P.max_rounds);
+  if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
+  launch_flags_out(n_ghost, gflag, remote_loser, &c.S->remote, c.st);
+  launch_copy_i32(n_owned, Cint, owned_colors, c.st);
+  launch_max_i32(n_owned, Cint, &c.S->aux_max, c.st);
+  c.launches += 3;
+  if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
+  if (hipMemcpyAsync(&c.H->aux_max, &c.S->aux_max, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) != hipSuccess)
+    return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  return finish_call(c, stats, c.H->aux_max, rc);
+}
+
+int color_priority(int32_t n, const int32_t* gid, uint32_t seed, uint32_t* out, void* stream) {
+  if (n < 0 || (n > 0 && !out)) return COLOR_EINVAL;
+  launch_priority(n, gid, hash_seed(seed), out, static_cast<hipStream_t>(stream));
+  if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return COLOR_EHIP;
+  return COLOR_OK;
+}
+
+int color_release_workspace(void) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (auto& kv : g_ws) {
+    std::lock_guard<std::mutex> lk2(kv.second->mu);
+    kv.second->release();
+    if (hipHostMalloc(reinterpret_cast<void**>(&kv.second->host), sizeof(Scalars), hipHostMallocDefault) !=
+        hipSuccess)
+      kv.second->host = nullptr;
+  }
+  return COLOR_OK;
+}
+
+const char* color_strerror(int code) {
+  switch (code) {
+    case COLOR_OK: return "ok";
+    case COLOR_EINVAL: return "invalid argument";
+    case COLOR_EGRAPH: return "graph violates the input contract";
+    case COLOR_EOVERFLOW: return "size exceeds int32 indexing";
+    case COLOR_ENOMEM: return "out of memory";
+    case COLOR_EHIP: return "HIP runtime error";
+    case COLOR_ENOCONVERGE: return "round limit reached (partial coloring returned)";
+    case COLOR_E2BIG: return "job exceeds the server's memory budget";
+    case COLOR_EQUEUED: return "job queued";
+    case COLOR_EPENDING: return "job pending";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Internal declarations shared by the C-ABI translation units.
+#pragma once
+
+#include <mutex>
+
+#include "graphcolor.h"
+#include "setup.hpp"
+
+namespace gcol {
+
+// A grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need, bool zero, hipStream_t st);
+  void release();
+  template <typename X>
+  X* as() const {
+    return static_cast<X*>(p);
+  }
+};
+
+// Device-resident scalars of one call (one allocation, cleared per call).
+struct Scalars {
+  int32_t cnt[2][8];            // per-bin worklist sizes, ping-pong
+  int32_t tile_ctr[2];          // dynamic unit counters of the color / detect kernels
+  int32_t maxc;                 // largest committed color
+  int32_t rounds_done;          // last round with a non-empty worklist
+  int32_t max_split_work;       // largest work of an uncolored split vertex
+  int32_t err;                  // validation error bits
+  int32_t aux_max;
+  int32_t pad_;
+  int32_t count_all[8];
+  int32_t count_unc[8];
+  unsigned long long visits[2]; // sum |W_r|, sum work(W_r)
+  unsigned long long total_work;
+  unsigned long long conflicts; // ghost phase-2 conflicts
+  unsigned long long remote;    // ghost remote losers
+};
+
+// Per-device workspace of the single-graph entry points.
+struct Workspace {
+  int device = 0;
+  std::mutex mu;
+  DevBuf T, C, work, bin, wl0, wl1, small, trace, split_vertex, split_ctr, split_flag, split_mask, aux0, aux1;
+  Scalars* host = nullptr;  // pinned staging for read-backs
+  ~Workspace();
+  void release();
+};
+
+Workspace* workspace_for_current_device(int* err);
+
+// State of one library call.
+struct Call {
+  Workspace* ws = nullptr;
+  hipStream_t st = nullptr;
+  color_params P;
+  int launches = 0;
+  int trace_cap = 0;
+  Scalars* S = nullptr;
+  Scalars* H = nullptr;
+  int32_t* wl[2] = {nullptr, nullptr};
+};
+
+void default_params(int mode, color_params* p);
+int merge_params(int mode, const color_params* user, color_params* out);
+int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, void* stream, int32_t n,
+               int32_t n_total);
+int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc);
+
+template <int MODE>
+int setup_bins(Call& c, const GraphView& g, const int32_t* init, int32_t* C, int32_t n_total, BinLayout& L,
+               RoundBufs& rb, int32_t known[kBins]);
+template <int MODE>
+int run_phase(Call& c, const GraphView& g, const KeySource& k, const BinLayout& L, const RoundBufs& base,
+              int32_t known[kBins], int round0, int max_rounds);
+
+}  // namespace gcol

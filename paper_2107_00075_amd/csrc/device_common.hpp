@@ -1,0 +1,92 @@
+// Device helpers shared by the round kernels: the priority key and the
+// 64-lane wavefront primitives of CDNA4 (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gcol {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // workgroup of the round kernels: 4 wavefronts
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// Problem kinds (the coloring variants of Section 2.1).
+enum Mode : int { kD1 = 1, kD2 = 2, kPD2 = 3 };
+
+// MurmurHash3 32-bit finalizer.  With h = seed-derived constant, the
+// priority p(v) = fmix32(gid ^ h) stands for rand(GID) of Algorithm 4: a
+// bijection of uint32, so two vertices never draw the same number.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+inline uint32_t host_fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+inline uint32_t hash_seed(uint32_t seed) { return host_fmix32(seed ^ 0x9E3779B9u); }
+
+// Where a vertex's key comes from.  key(v) = (p(v), gid(v)) packed into 64
+// bits so that one unsigned compare is the lexicographic compare; the lower
+// key loses a conflict.
+struct KeySource {
+  const uint32_t* prio;  // nullable: explicit p(v)
+  const int32_t* gid;    // nullable: gid(v) = v
+  uint32_t hs;           // hash_seed(seed)
+};
+
+__device__ __forceinline__ uint64_t key_of(const KeySource& k, int32_t v) {
+  const uint32_t g = k.gid ? static_cast<uint32_t>(k.gid[v]) : static_cast<uint32_t>(v);
+  const uint32_t p = k.prio ? k.prio[v] : fmix32(g ^ k.hs);
+  return (static_cast<uint64_t>(p) << 32) | g;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` in lanes below the calling lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+// OR of a 64-bit value over aligned groups of G lanes (all lanes of a group
+// must be active).
+template <int G>
+__device__ __forceinline__ uint64_t group_or(uint64_t x) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) x |= __shfl_xor(x, off, kWave);
+  return x;
+}
+
+// 1 if any lane of the calling lane's aligned G-lane group has pred set.
+template <int G>
+__device__ __forceinline__ bool group_any(bool pred) {
+  const uint64_t b = __ballot(pred);
+  if (G == kWave) return b != 0;
+  const int first = lane_id() & ~(G - 1);
+  const uint64_t gm = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  return ((b >> first) & gm) != 0;
+}
+
+__device__ __forceinline__ uint64_t atomic_load_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t atomic_load_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t atomic_load_i32(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace gcol

@@ -1,0 +1,531 @@
+// Round kernels of synchronous speculative coloring for CDNA4 (gfx950).
+//
+// One round (Section 3, Algorithm 2's loop; the local speculative rounds of
+// Section 3.2) is two launches:
+//   color  : every vertex v of the worklist W_r takes T[v] = the smallest
+//            color >= 1 that its neighbourhood does not hold in the committed
+//            array C (first-fit, Section 2.2, Algorithm 1).  Only C is read.
+//   detect : v loses when a neighbour u holds T[u] == T[v] with key(u) >
+//            key(v) (Section 3.2, Algorithms 3 and 4, with the lower key
+//            uncolored).  Only T is read.  Winners commit C[v] = T[v] in
+//            place; losers are appended to W_{r+1} by wavefront-ballot
+//            compaction (one atomic per wavefront).
+// Committed neighbours never tie: T[u] == C[u] for them and T[v] avoids every
+// committed neighbour color, so reading T of all neighbours equals reading T
+// of the worklist neighbours only.  Neither kernel reads what it writes, so
+// the round is exactly the synchronous (snapshot) round.
+//
+// Neighbourhoods: D1 = N(v); D2 = N(v) u N(N(v)) minus v (Section 2.1,
+// Algorithm 5 with doPartialColoring false); PD2 = columns sharing a row
+// with column v (Section 3.6, doPartialColoring true: no one-hop term).
+//
+// Mapping: each worklist is split into five static degree bins.  Bins 0..2
+// give a vertex an aligned group of G lanes (G = 1..64) that stride over its
+// adjacency, so a group reads contiguous col_idx entries and OR-reduces a
+// 64-bit forbidden-color window with cross-lane shuffles.  Bin 3 gives a
+// vertex a workgroup (register window for colors 1..64 plus an LDS bitset for
+// the next 32768 colors).  Bin 4 splits a vertex over several workgroups that
+// merge their windows into a global per-vertex bitset; the last workgroup to
+// arrive picks the color or commits (the edge-split parallelism that the
+// paper's edge-based kernel provides for very high degrees, Section 3.2).
+// Workgroups take units of work from a device counter, heavy bins first.
+#include <climits>
+
+#include "rounds.hpp"
+
+namespace gcol {
+
+// Visits the neighbourhood entries of v reachable from hop-1 positions
+// [beg, end) with lane stride (sub, stride).  f(u) returns true to stop.
+template <int MODE, typename F>
+__device__ __forceinline__ void scan_nbhd(const GraphView& g, int32_t v, int32_t beg, int32_t end,
+                                          int sub, int stride, F&& f) {
+  for (int32_t e = beg + sub; e < end; e += stride) {
+    const int32_t u = g.ci[e];
+    if (MODE == kD1) {
+      if (u < g.limit && f(u)) return;
+    } else {
+      if (MODE == kD2) {
+        if (f(u)) return;
+      }
+      const int32_t b2 = g.rp2[u], e2 = g.rp2[u + 1];
+      for (int32_t q = b2; q < e2; ++q) {
+        const int32_t x = g.ci2[q];
+        if (x != v && f(x)) return;
+      }
+    }
+  }
+}
+
+struct UnitMap {
+  int32_t cnt[kBins];
+  int64_t tiles[3];    // tiles of bins 0..2
+  int64_t units[kBins];
+  int64_t total;
+};
+
+__device__ __forceinline__ void make_unit_map(const RoundBufs& b, const BinLayout& L, UnitMap& m) {
+  m.total = 0;
+#pragma unroll
+  for (int i = 0; i < kBins; ++i) m.cnt[i] = b.cnt_in[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int64_t per_tile = kBlock / L.lanes[i];
+    m.tiles[i] = (m.cnt[i] + per_tile - 1) / per_tile;
+    m.units[i] = (m.tiles[i] + L.grab - 1) / L.grab;
+  }
+  m.units[kBlockBin] = m.cnt[kBlockBin];
+  m.units[kSplitBin] = static_cast<int64_t>(m.cnt[kSplitBin]) * L.split_chunks;
+#pragma unroll
+  for (int i = 0; i < kBins; ++i) m.total += m.units[i];
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) x += __shfl_xor(x, off, kWave);
+  return x;
+}
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) x = max(x, __shfl_xor(x, off, kWave));
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// color: group of G lanes per vertex
+// ---------------------------------------------------------------------------
+template <int MODE, int G>
+__device__ void color_tiles_group(const GraphView& g, const RoundBufs& b, int32_t cnt,
+                                  int32_t off, int64_t t0, int64_t t1, uint64_t& work_acc) {
+  constexpr int per_tile = kBlock / G;
+  const int gi = threadIdx.x / G;
+  const int sub = threadIdx.x % G;
+  const int32_t* __restrict__ C = b.C;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t idx = t * per_tile + gi;
+    if (idx >= cnt) break;  // the whole group leaves together
+    const int32_t v = b.wl_in[off + idx];
+    const int32_t beg = g.rp[v], end = g.rp[v + 1];
+    int32_t base = 1;
+    while (true) {
+      uint64_t m = 0;
+      scan_nbhd<MODE>(g, v, beg, end, sub, G, [&](int32_t u) {
+        const uint32_t d = static_cast<uint32_t>(C[u] - base);
+        if (d < 64u) m |= 1ull << d;
+        return false;
+      });
+      m = group_or<G>(m);
+      if (m != ~0ull) {
+        if (sub == 0) b.T[v] = base + __builtin_ctzll(~m);
+        break;
+      }
+      base += 64;
+    }
+    if (sub == 0) work_acc += static_cast<uint64_t>(b.work[v]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// color: one workgroup per vertex
+// ---------------------------------------------------------------------------
+template <int MODE>
+__device__ void color_vertex_block(const GraphView& g, const RoundBufs& b, int32_t v,
+                                   uint32_t* ovf, uint64_t* red, int32_t* s_min) {
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int32_t beg = g.rp[v], end = g.rp[v + 1];
+  const int32_t* __restrict__ C = b.C;
+  int32_t base = 1;
+  while (true) {
+    for (int w = tid; w < kOvfWords; w += kBlock) ovf[w] = 0u;
+    if (tid == 0) *s_min = INT_MAX;
+    __syncthreads();
+    uint64_t m = 0;
+    scan_nbhd<MODE>(g, v, beg, end, tid, kBlock, [&](int32_t u) {
+      uint32_t d = static_cast<uint32_t>(C[u] - base);
+      if (d < 64u) {
+        m |= 1ull << d;
+      } else {
+        d -= 64u;
+        if (d < static_cast<uint32_t>(kOvfWords * 32)) atomicOr(&ovf[d >> 5], 1u << (d & 31u));
+      }
+      return false;
+    });
+    m = group_or<kWave>(m);
+    if (lane_id() == 0) red[wave] = m;
+    __syncthreads();
+    m = red[0] | red[1] | red[2] | red[3];
+    int32_t mex = -1;
+    if (m != ~0ull) {
+      mex = base + __builtin_ctzll(~m);
+    } else {
+      for (int w = tid; w < kOvfWords; w += kBlock) {
+        const uint32_t x = ovf[w];
+        if (x != ~0u) {
+          atomicMin(s_min, w * 32 + __builtin_ctz(~x));
+          break;
+        }
+      }
+      __syncthreads();
+      if (*s_min != INT_MAX) mex = base + 64 + *s_min;
+    }
+    __syncthreads();
+    if (mex > 0) {
+      if (tid == 0) b.T[v] = mex;
+      return;
+    }
+    base += 64 + kOvfWords * 32;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// color: one chunk of a split vertex
+// ---------------------------------------------------------------------------
+template <int MODE>
+__device__ void color_split_chunk(const GraphView& g, const RoundBufs& b, const BinLayout& L,
+                                  int32_t si, int chunk, uint32_t* ovf, uint64_t* red,
+                                  int32_t* s_misc, uint64_t& work_acc) {
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int nch = L.split_chunks;
+  const int32_t v = b.split_vertex[si];
+  const int32_t rb = g.rp[v], re = g.rp[v + 1];
+  const int64_t len = re - rb;
+  const int32_t cb = rb + static_cast<int32_t>(len * chunk / nch);
+  const int32_t ce = rb + static_cast<int32_t>(len * (chunk + 1) / nch);
+  uint32_t* gm = b.split_mask + static_cast<size_t>(si) * b.capw;
+  const uint32_t capbits = static_cast<uint32_t>(b.capw) * 32u;
+  const int32_t* __restrict__ C = b.C;
+
+  for (int w = tid; w < kOvfWords; w += kBlock) ovf[w] = 0u;
+  __syncthreads();
+  uint64_t m = 0;
+  scan_nbhd<MODE>(g, v, cb, ce, tid, kBlock, [&](int32_t u) {
+    const int32_t c = C[u];
+    if (c <= 0) return false;
+    uint32_t d = static_cast<uint32_t>(c - 1);  // bit c-1 stands for color c
+    if (d < 64u) {
+      m |= 1ull << d;
+    } else if (d - 64u < static_cast<uint32_t>(kOvfWords * 32)) {
+      d -= 64u;
+      atomicOr(&ovf[d >> 5], 1u << (d & 31u));
+    } else if (d < capbits) {
+      atomicOr(&gm[d >> 5], 1u << (d & 31u));
+    }
+    return false;
+  });
+  m = group_or<kWave>(m);
+  if (lane_id() == 0) red[wave] = m;
+  __syncthreads();
+  if (tid == 0) {
+    m = red[0] | red[1] | red[2] | red[3];
+    if (static_cast<uint32_t>(m)) atomicOr(&gm[0], static_cast<uint32_t>(m));
+    if (m >> 32) atomicOr(&gm[1], static_cast<uint32_t>(m >> 32));
+    if (chunk == 0) work_acc += static_cast<uint64_t>(b.work[v]);
+  }
+  for (int w = tid; w < kOvfWords && 2 + w < b.capw; w += kBlock) {
+    const uint32_t x = ovf[w];
+    if (x) atomicOr(&gm[2 + w], x);
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_misc[1] = (atomicAdd(&b.split_ctr[si], 1u) == static_cast<uint32_t>(nch - 1));
+  __syncthreads();
+  if (s_misc[1]) {  // last chunk to arrive: pick the color
+    __threadfence();
+    const int32_t mc = atomic_load_i32(b.maxc);
+    const int32_t nwords = min(b.capw, mc / 32 + 1);
+    if (tid == 0) s_misc[0] = INT_MAX;
+    __syncthreads();
+    for (int w = tid; w < nwords; w += kBlock) {
+      const uint32_t x = atomic_load_u32(&gm[w]);
+      if (x != ~0u) {
+        atomicMin(&s_misc[0], w * 32 + __builtin_ctz(~x));
+        break;
+      }
+    }
+    __syncthreads();
+    const int32_t bit = s_misc[0];
+    for (int w = tid; w < nwords; w += kBlock) gm[w] = 0u;
+    if (tid == 0) {
+      b.T[v] = (bit == INT_MAX ? nwords * 32 : bit) + 1;
+      b.split_ctr[si] = 0u;
+    }
+  }
+  __syncthreads();
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void color_round_kernel(GraphView g, KeySource k, RoundBufs b,
+                                                             BinLayout L, int round) {
+  __shared__ uint32_t ovf[kOvfWords];
+  __shared__ uint64_t red[kWavesPerBlock];
+  __shared__ int32_t s_misc[4];
+  __shared__ int64_t s_unit;
+  __shared__ unsigned long long s_work;
+  (void)k;
+  UnitMap um;
+  make_unit_map(b, L, um);
+  if (threadIdx.x == 0) s_work = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int64_t total = 0;
+    for (int i = 0; i < kBins; ++i) {
+      b.cnt_out[i] = 0;
+      total += um.cnt[i];
+    }
+    b.tile_ctr[1] = 0;
+    if (total > 0) {
+      *b.rounds_done = round;
+      if (b.trace && round <= b.trace_cap) b.trace[round - 1] = static_cast<int32_t>(total);
+      atomicAdd(&b.visits[0], static_cast<unsigned long long>(total));
+    }
+  }
+  uint64_t work_acc = 0;
+  while (true) {
+    if (threadIdx.x == 0) s_unit = atomicAdd(&b.tile_ctr[0], 1);
+    __syncthreads();
+    int64_t u = s_unit;
+    __syncthreads();
+    if (u >= um.total) break;
+    if (u < um.units[kSplitBin]) {
+      const int32_t si = b.wl_in[L.off[kSplitBin] + u / L.split_chunks];
+      color_split_chunk<MODE>(g, b, L, si, static_cast<int>(u % L.split_chunks), ovf, red, s_misc,
+                              work_acc);
+      continue;
+    }
+    u -= um.units[kSplitBin];
+    if (u < um.units[kBlockBin]) {
+      const int32_t v = b.wl_in[L.off[kBlockBin] + u];
+      color_vertex_block<MODE>(g, b, v, ovf, red, &s_misc[0]);
+      if (threadIdx.x == 0) work_acc += static_cast<uint64_t>(b.work[v]);
+      continue;
+    }
+    u -= um.units[kBlockBin];
+    for (int bin = 2; bin >= 0; --bin) {
+      if (u < um.units[bin]) {
+        const int64_t t0 = u * L.grab;
+        const int64_t t1 = min(t0 + L.grab, um.tiles[bin]);
+        const int32_t cnt = um.cnt[bin], off = L.off[bin];
+        switch (L.lanes[bin]) {
+          case 1: color_tiles_group<MODE, 1>(g, b, cnt, off, t0, t1, work_acc); break;
+          case 2: color_tiles_group<MODE, 2>(g, b, cnt, off, t0, t1, work_acc); break;
+          case 4: color_tiles_group<MODE, 4>(g, b, cnt, off, t0, t1, work_acc); break;
+          case 8: color_tiles_group<MODE, 8>(g, b, cnt, off, t0, t1, work_acc); break;
+          case 16: color_tiles_group<MODE, 16>(g, b, cnt, off, t0, t1, work_acc); break;
+          case 32: color_tiles_group<MODE, 32>(g, b, cnt, off, t0, t1, work_acc); break;
+          default: color_tiles_group<MODE, 64>(g, b, cnt, off, t0, t1, work_acc); break;
+        }
+        break;
+      }
+      u -= um.units[bin];
+    }
+  }
+  work_acc = wave_sum_u64(work_acc);
+  if (lane_id() == 0 && work_acc) atomicAdd(&s_work, static_cast<unsigned long long>(work_acc));
+  __syncthreads();
+  if (threadIdx.x == 0 && s_work) atomicAdd(&b.visits[1], s_work);
+}
+
+// ---------------------------------------------------------------------------
+// detect + commit + compact: group of G lanes per vertex
+// ---------------------------------------------------------------------------
+template <int MODE, int G>
+__device__ void detect_tiles_group(const GraphView& g, const KeySource& k, const RoundBufs& b,
+                                   int bin, int32_t cnt, int32_t off, int64_t t0, int64_t t1,
+                                   int32_t& maxc_acc) {
+  constexpr int per_tile = kBlock / G;
+  const int gi = threadIdx.x / G;
+  const int sub = threadIdx.x % G;
+  const int32_t* __restrict__ T = b.T;
+  for (int64_t t = t0; t < t1; ++t) {
+    if (t * per_tile >= cnt) break;  // uniform over the workgroup
+    const int64_t idx = t * per_tile + gi;
+    const bool active = idx < cnt;
+    int32_t v = 0, tv = 0;
+    bool lose = false;
+    if (active) {
+      v = b.wl_in[off + idx];
+      tv = T[v];
+      const uint64_t kv = key_of(k, v);
+      scan_nbhd<MODE>(g, v, g.rp[v], g.rp[v + 1], sub, G, [&](int32_t u) {
+        if (T[u] == tv && key_of(k, u) > kv) {
+          lose = true;
+          return true;
+        }
+        return false;
+      });
+    }
+    lose = group_any<G>(lose);
+    const bool leader = active && sub == 0;
+    if (leader && !lose) {
+      b.C[v] = tv;
+      maxc_acc = max(maxc_acc, tv);
+    }
+    const uint64_t bal = __ballot(leader && lose);
+    if (bal) {
+      const int first = __builtin_ctzll(bal);
+      int32_t base = 0;
+      if (lane_id() == first) base = atomicAdd(&b.cnt_out[bin], static_cast<int32_t>(__popcll(bal)));
+      base = __shfl(base, first, kWave);
+      if (leader && lose) b.wl_out[off + base + static_cast<int32_t>(lanes_below(bal))] = v;
+    }
+  }
+}
+
+template <int MODE>
+__device__ void detect_vertex_block(const GraphView& g, const KeySource& k, const RoundBufs& b,
+                                    int32_t v, int32_t off, int32_t& maxc_acc) {
+  const int tid = threadIdx.x;
+  const int32_t* __restrict__ T = b.T;
+  const int32_t tv = T[v];
+  const uint64_t kv = key_of(k, v);
+  bool lose = false;
+  scan_nbhd<MODE>(g, v, g.rp[v], g.rp[v + 1], tid, kBlock, [&](int32_t u) {
+    if (T[u] == tv && key_of(k, u) > kv) {
+      lose = true;
+      return true;
+    }
+    return false;
+  });
+  lose = __syncthreads_or(lose);
+  if (tid == 0) {
+    if (!lose) {
+      b.C[v] = tv;
+      maxc_acc = max(maxc_acc, tv);
+    } else {
+      const int32_t pos = atomicAdd(&b.cnt_out[kBlockBin], 1);
+      b.wl_out[off + pos] = v;
+    }
+  }
+}
+
+template <int MODE>
+__device__ void detect_split_chunk(const GraphView& g, const KeySource& k, const RoundBufs& b,
+                                   const BinLayout& L, int32_t si, int chunk, int32_t* s_misc,
+                                   int32_t& maxc_acc) {
+  const int tid = threadIdx.x;
+  const int nch = L.split_chunks;
+  const int32_t v = b.split_vertex[si];
+  const int32_t rb = g.rp[v], re = g.rp[v + 1];
+  const int64_t len = re - rb;
+  const int32_t cb = rb + static_cast<int32_t>(len * chunk / nch);
+  const int32_t ce = rb + static_cast<int32_t>(len * (chunk + 1) / nch);
+  const int32_t* __restrict__ T = b.T;
+  const int32_t tv = T[v];
+  const uint64_t kv = key_of(k, v);
+  bool lose = false;
+  if (atomic_load_u32(&b.split_flag[si]) == 0u) {  // another chunk may already have decided
+    scan_nbhd<MODE>(g, v, cb, ce, tid, kBlock, [&](int32_t u) {
+      if (T[u] == tv && key_of(k, u) > kv) {
+        lose = true;
+        return true;
+      }
+      return false;
+    });
+  }
+  lose = __syncthreads_or(lose);
+  if (tid == 0 && lose) atomicOr(&b.split_flag[si], 1u);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const bool last = atomicAdd(&b.split_ctr[si], 1u) == static_cast<uint32_t>(nch - 1);
+    if (last) {
+      __threadfence();
+      const uint32_t f = atomic_load_u32(&b.split_flag[si]);
+      if (!f) {
+        b.C[v] = tv;
+        maxc_acc = max(maxc_acc, tv);
+      } else {
+        const int32_t pos = atomicAdd(&b.cnt_out[kSplitBin], 1);
+        b.wl_out[L.off[kSplitBin] + pos] = si;
+      }
+      b.split_flag[si] = 0u;
+      b.split_ctr[si] = 0u;
+    }
+  }
+  __syncthreads();
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void detect_round_kernel(GraphView g, KeySource k, RoundBufs b,
+                                                              BinLayout L, int round) {
+  __shared__ int32_t s_misc[4];
+  __shared__ int64_t s_unit;
+  __shared__ int32_t s_max;
+  (void)round;
+  UnitMap um;
+  make_unit_map(b, L, um);
+  if (threadIdx.x == 0) s_max = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) b.tile_ctr[0] = 0;
+  int32_t maxc_acc = 0;
+  while (true) {
+    if (threadIdx.x == 0) s_unit = atomicAdd(&b.tile_ctr[1], 1);
+    __syncthreads();
+    int64_t u = s_unit;
+    __syncthreads();
+    if (u >= um.total) break;
+    if (u < um.units[kSplitBin]) {
+      const int32_t si = b.wl_in[L.off[kSplitBin] + u / L.split_chunks];
+      detect_split_chunk<MODE>(g, k, b, L, si, static_cast<int>(u % L.split_chunks), s_misc,
+                               maxc_acc);
+      continue;
+    }
+    u -= um.units[kSplitBin];
+    if (u < um.units[kBlockBin]) {
+      const int32_t v = b.wl_in[L.off[kBlockBin] + u];
+      detect_vertex_block<MODE>(g, k, b, v, L.off[kBlockBin], maxc_acc);
+      continue;
+    }
+    u -= um.units[kBlockBin];
+    for (int bin = 2; bin >= 0; --bin) {
+      if (u < um.units[bin]) {
+        const int64_t t0 = u * L.grab;
+        const int64_t t1 = min(t0 + L.grab, um.tiles[bin]);
+        const int32_t cnt = um.cnt[bin], off = L.off[bin];
+        switch (L.lanes[bin]) {
+          case 1: detect_tiles_group<MODE, 1>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
+          case 2: detect_tiles_group<MODE, 2>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
+          case 4: detect_tiles_group<MODE, 4>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
+          case 8: detect_tiles_group<MODE, 8>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
+          case 16: detect_tiles_group<MODE, 16>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
+          case 32: detect_tiles_group<MODE, 32>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
+          default: detect_tiles_group<MODE, 64>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
+        }
+        break;
+      }
+      u -= um.units[bin];
+    }
+  }
+  maxc_acc = wave_max_i32(maxc_acc);
+  if (lane_id() == 0 && maxc_acc > 0) atomicMax(&s_max, maxc_acc);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_max > 0) atomicMax(b.maxc, s_max);
+}
+
+template <int MODE>
+void launch_color_round(const GraphView& g, const KeySource& k, const RoundBufs& b,
+                        const BinLayout& L, int round, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(color_round_kernel<MODE>, dim3(grid), dim3(kBlock), 0, st, g, k, b, L, round);
+}
+
+template <int MODE>
+void launch_detect_round(const GraphView& g, const KeySource& k, const RoundBufs& b,
+                         const BinLayout& L, int round, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(detect_round_kernel<MODE>, dim3(grid), dim3(kBlock), 0, st, g, k, b, L, round);
+}
+
+template void launch_color_round<kD1>(const GraphView&, const KeySource&, const RoundBufs&,
+                                      const BinLayout&, int, int, hipStream_t);
+template void launch_color_round<kD2>(const GraphView&, const KeySource&, const RoundBufs&,
+                                      const BinLayout&, int, int, hipStream_t);
+template void launch_color_round<kPD2>(const GraphView&, const KeySource&, const RoundBufs&,
+                                       const BinLayout&, int, int, hipStream_t);
+template void launch_detect_round<kD1>(const GraphView&, const KeySource&, const RoundBufs&,
+                                       const BinLayout&, int, int, hipStream_t);
+template void launch_detect_round<kD2>(const GraphView&, const KeySource&, const RoundBufs&,
+                                       const BinLayout&, int, int, hipStream_t);
+template void launch_detect_round<kPD2>(const GraphView&, const KeySource&, const RoundBufs&,
+                                        const BinLayout&, int, int, hipStream_t);
+
+}  // namespace gcol

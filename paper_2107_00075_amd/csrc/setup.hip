@@ -1,0 +1,306 @@
+// Per-call setup kernels: static work and degree bins, initial worklists,
+// input-contract validation, the priority hash, and the boundary phase of the
+// ghost-layer variant.
+#include <algorithm>
+#include <climits>
+
+#include "setup.hpp"
+
+namespace gcol {
+
+// Adjacency entries one visit of v reads: D1 deg(v); D2 sum over u in N(v)
+// of 1 + deg(u); PD2 sum over the rows r of column v of deg(r).
+template <int MODE>
+__device__ __forceinline__ int64_t vertex_work(const GraphView& g, int32_t v) {
+  const int32_t b = g.rp[v], e = g.rp[v + 1];
+  if (MODE == kD1) return e - b;
+  int64_t w = 0;
+  for (int32_t q = b; q < e; ++q) {
+    const int32_t u = g.ci[q];
+    w += (MODE == kD2 ? 1 : 0) + (g.rp2[u + 1] - g.rp2[u]);
+  }
+  return w;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  const bool active = v < g.n;
+  int bin = -1;
+  int32_t c = 0;
+  int64_t w = 0;
+  if (active) {
+    w = vertex_work<MODE>(g, v);
+    const int32_t wc = static_cast<int32_t>(w > INT_MAX ? INT_MAX : w);
+    s.work[v] = wc;
+    bin = kBins - 1;
+    for (int i = 0; i < kBins - 1; ++i) {
+      if (wc <= s.bin_hi[i]) {
+        bin = i;
+        break;
+      }
+    }
+    s.bin[v] = static_cast<int8_t>(bin);
+    c = s.init ? s.init[v] : 0;
+    s.C[v] = c;
+    s.T[v] = c;
+  }
+  // wavefront reductions first: one atomic per wavefront and quantity
+  int32_t cmax = c;
+  int32_t smax = (active && bin == kSplitBin && c == 0) ? static_cast<int32_t>(w > INT_MAX ? INT_MAX : w) : 0;
+  uint64_t wsum = (active && c == 0) ? static_cast<uint64_t>(w) : 0ull;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    cmax = max(cmax, __shfl_xor(cmax, off, kWave));
+    smax = max(smax, __shfl_xor(smax, off, kWave));
+    wsum += __shfl_xor(wsum, off, kWave);
+  }
+  if (lane_id() == 0) {
+    if (cmax > 0) atomicMax(s.maxc, cmax);
+    if (smax > 0) atomicMax(s.max_split_work, smax);
+    if (wsum) atomicAdd(s.total_work, static_cast<unsigned long long>(wsum));
+  }
+  for (int i = 0; i < kBins; ++i) {
+    const uint64_t all = __ballot(active && bin == i);
+    const uint64_t unc = __ballot(active && bin == i && c == 0);
+    if (lane_id() == 0) {
+      if (all) atomicAdd(&s.count_all[i], static_cast<int32_t>(__popcll(all)));
+      if (unc) atomicAdd(&s.count_unc[i], static_cast<int32_t>(__popcll(unc)));
+    }
+  }
+}
+
+// Appends every uncolored vertex (C[v] == 0) to its bin's region of the
+// worklist; split vertices get a split index (their position in the split
+// region) and the region holds indices.
+__global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_t* C, const int8_t* binv,
+                                                         BinLayout L, int32_t* wl, int32_t* cnt,
+                                                         int32_t* split_vertex) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  const bool active = v < n && C[v] == 0;
+  const int bin = active ? binv[v] : -1;
+  for (int i = 0; i < kBins; ++i) {
+    const bool mine = active && bin == i;
+    const uint64_t bal = __ballot(mine);
+    if (!bal) continue;
+    const int first = __builtin_ctzll(bal);
+    int32_t base = 0;
+    if (lane_id() == first) base = atomicAdd(&cnt[i], static_cast<int32_t>(__popcll(bal)));
+    base = __shfl(base, first, kWave);
+    if (mine) {
+      const int32_t pos = base + static_cast<int32_t>(lanes_below(bal));
+      if (i == kSplitBin) {
+        split_vertex[pos] = v;
+        wl[L.off[i] + pos] = pos;
+      } else {
+        wl[L.off[i] + pos] = v;
+      }
+    }
+  }
+}
+
+// Input contract (COLOR_FLAG_VALIDATE).  Rows strictly increasing, ids in
+// range, no self-loops when `square`, and every entry (v, u) mirrored as
+// (u, v) in the transpose arrays (rpT, ciT) — for D1/D2 the adjacency itself,
+// for PD2 the CSC of the same pattern.
+__global__ __launch_bounds__(kBlock) void validate_kernel(int32_t n_rows, int32_t n_cols, const int32_t* rp,
+                                                          const int32_t* ci, const int32_t* rpT,
+                                                          const int32_t* ciT, int32_t n_trows, int square,
+                                                          int32_t* err) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n_rows) return;
+  const int32_t b = rp[v], e = rp[v + 1];
+  if (b > e) {
+    atomicOr(err, 1);
+    return;
+  }
+  int32_t prev = -1;
+  for (int32_t q = b; q < e; ++q) {
+    const int32_t u = ci[q];
+    if (u < 0 || u >= n_cols) {
+      atomicOr(err, 2);
+      return;
+    }
+    if (u <= prev) atomicOr(err, 4);
+    if (square && u == v) atomicOr(err, 8);
+    prev = u;
+    if (u >= n_trows) continue;  // no transpose row for u (e.g. a ghost without a row)
+    // binary search v in the transpose row of u
+    int32_t lo = rpT[u], hi = rpT[u + 1] - 1;
+    bool found = false;
+    while (lo <= hi) {
+      const int32_t mid = lo + ((hi - lo) >> 1);
+      const int32_t x = ciT[mid];
+      if (x == v) {
+        found = true;
+        break;
+      }
+      if (x < v) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    if (!found) atomicOr(err, 16);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void check_rowptr_kernel(int32_t n, const int32_t* rp, int32_t* err) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v > n) return;
+  if (v == 0 && rp[0] != 0) atomicOr(err, 1);
+  if (v < n && rp[v] > rp[v + 1]) atomicOr(err, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void priority_kernel(int32_t n, const int32_t* gid, uint32_t hs,
+                                                          uint32_t* out) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t g = gid ? static_cast<uint32_t>(gid[i]) : static_cast<uint32_t>(i);
+  out[i] = fmix32(g ^ hs);
+}
+
+// Ghost phase 2 (Algorithm 3 with Algorithm 4 on the ghosts' fixed colors):
+// every owned-ghost edge with equal colors is a conflict; the owned endpoint
+// loses when the ghost's key is greater, otherwise the ghost is flagged.  All
+// pairs are judged on the phase-1 colors; losers are uncolored afterwards by
+// boundary_uncolor_kernel.
+__global__ __launch_bounds__(kBlock) void boundary_kernel(int32_t n_owned, const int32_t* rp,
+                                                          const int32_t* ci, const int32_t* C,
+                                                          const int32_t* ghost_colors, KeySource k,
+                                                          int32_t* loser, int32_t* gflag,
+                                                          unsigned long long* conflicts) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  uint32_t found = 0;
+  if (v < n_owned) {
+    const int32_t cv = C[v];
+    const uint64_t kv = key_of(k, v);
+    bool lose = false;
+    for (int32_t q = rp[v]; q < rp[v + 1]; ++q) {
+      const int32_t u = ci[q];
+      if (u < n_owned) continue;
+      if (ghost_colors[u - n_owned] != cv) continue;
+      ++found;
+      if (key_of(k, u) > kv) lose = true;
+      else gflag[u - n_owned] = 1;
+    }
+    loser[v] = lose ? 1 : 0;
+  }
+  uint64_t tot = found;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) tot += __shfl_xor(tot, off, kWave);
+  if (lane_id() == 0 && tot) atomicAdd(conflicts, static_cast<unsigned long long>(tot));
+}
+
+__global__ __launch_bounds__(kBlock) void boundary_uncolor_kernel(int32_t n_owned, const int32_t* loser,
+                                                                  int32_t* C) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v < n_owned && loser[v]) C[v] = 0;
+}
+
+// Ghost colors become fixed committed colors for phase 3.
+__global__ __launch_bounds__(kBlock) void ghost_fill_kernel(int32_t n_owned, int32_t n_ghost,
+                                                            const int32_t* ghost_colors, int32_t* C,
+                                                            int32_t* T, int32_t* maxc) {
+  const int32_t j = blockIdx.x * kBlock + threadIdx.x;
+  int32_t c = 0;
+  if (j < n_ghost) {
+    c = ghost_colors[j];
+    C[n_owned + j] = c;
+    T[n_owned + j] = c;
+  }
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) c = max(c, __shfl_xor(c, off, kWave));
+  if (lane_id() == 0 && c > 0) atomicMax(maxc, c);
+}
+
+// Largest value of an int32 array (wave-reduced, one atomic per wavefront).
+__global__ __launch_bounds__(kBlock) void max_i32_kernel(int32_t n, const int32_t* a, int32_t* out) {
+  int32_t x = 0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    x = max(x, a[i]);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) x = max(x, __shfl_xor(x, off, kWave));
+  if (lane_id() == 0 && x > 0) atomicMax(out, x);
+}
+
+__global__ __launch_bounds__(kBlock) void flags_out_kernel(int32_t n, const int32_t* gflag, uint8_t* out,
+                                                           unsigned long long* count) {
+  const int32_t j = blockIdx.x * kBlock + threadIdx.x;
+  const bool f = j < n && gflag[j] != 0;
+  if (j < n && out) out[j] = f ? 1 : 0;
+  const uint64_t bal = __ballot(f);
+  if (lane_id() == 0 && bal) atomicAdd(count, static_cast<unsigned long long>(__popcll(bal)));
+}
+
+__global__ __launch_bounds__(kBlock) void copy_i32_kernel(int32_t n, const int32_t* src, int32_t* dst) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+static inline int blocks_for(int64_t n) { return static_cast<int>((n + kBlock - 1) / kBlock); }
+
+template <int MODE>
+void launch_bin(const GraphView& g, const BinSetup& s, hipStream_t st) {
+  if (g.n > 0) hipLaunchKernelGGL(bin_kernel<MODE>, dim3(blocks_for(g.n)), dim3(kBlock), 0, st, g, s);
+}
+template void launch_bin<kD1>(const GraphView&, const BinSetup&, hipStream_t);
+template void launch_bin<kD2>(const GraphView&, const BinSetup&, hipStream_t);
+template void launch_bin<kPD2>(const GraphView&, const BinSetup&, hipStream_t);
+
+void launch_scatter(int32_t n, const int32_t* C, const int8_t* bin, const BinLayout& L, int32_t* wl,
+                    int32_t* cnt, int32_t* split_vertex, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, C, bin, L, wl, cnt,
+                       split_vertex);
+}
+
+void launch_validate(int32_t n_rows, int32_t n_cols, const int32_t* rp, const int32_t* ci,
+                     const int32_t* rpT, const int32_t* ciT, int32_t n_trows, int square, int32_t* err,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(check_rowptr_kernel, dim3(blocks_for(static_cast<int64_t>(n_rows) + 1)), dim3(kBlock),
+                     0, st, n_rows, rp, err);
+  if (n_rows > 0)
+    hipLaunchKernelGGL(validate_kernel, dim3(blocks_for(n_rows)), dim3(kBlock), 0, st, n_rows, n_cols, rp,
+                       ci, rpT, ciT, n_trows, square, err);
+}
+
+void launch_priority(int32_t n, const int32_t* gid, uint32_t hs, uint32_t* out, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(priority_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, gid, hs, out);
+}
+
+void launch_boundary(int32_t n_owned, const int32_t* rp, const int32_t* ci, const int32_t* C,
+                     const int32_t* ghost_colors, const KeySource& k, int32_t* loser, int32_t* gflag,
+                     unsigned long long* conflicts, hipStream_t st) {
+  if (n_owned > 0)
+    hipLaunchKernelGGL(boundary_kernel, dim3(blocks_for(n_owned)), dim3(kBlock), 0, st, n_owned, rp, ci, C,
+                       ghost_colors, k, loser, gflag, conflicts);
+}
+
+void launch_boundary_uncolor(int32_t n_owned, const int32_t* loser, int32_t* C, hipStream_t st) {
+  if (n_owned > 0)
+    hipLaunchKernelGGL(boundary_uncolor_kernel, dim3(blocks_for(n_owned)), dim3(kBlock), 0, st, n_owned,
+                       loser, C);
+}
+
+void launch_ghost_fill(int32_t n_owned, int32_t n_ghost, const int32_t* gc, int32_t* C, int32_t* T,
+                       int32_t* maxc, hipStream_t st) {
+  if (n_ghost > 0)
+    hipLaunchKernelGGL(ghost_fill_kernel, dim3(blocks_for(n_ghost)), dim3(kBlock), 0, st, n_owned, n_ghost,
+                       gc, C, T, maxc);
+}
+
+void launch_max_i32(int32_t n, const int32_t* a, int32_t* out, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(max_i32_kernel, dim3(std::min(blocks_for(n), 1024)), dim3(kBlock), 0, st, n, a, out);
+}
+
+void launch_flags_out(int32_t n, const int32_t* gflag, uint8_t* out, unsigned long long* count,
+                      hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(flags_out_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, gflag, out, count);
+}
+
+void launch_copy_i32(int32_t n, const int32_t* src, int32_t* dst, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(copy_i32_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, src, dst);
+}
+
+}  // namespace gcol

@@ -1,0 +1,41 @@
+// Declarations of the per-call setup kernels (setup.hip).
+#pragma once
+
+#include "rounds.hpp"
+
+namespace gcol {
+
+struct BinSetup {
+  int32_t bin_hi[kBins - 1];         // work upper bound of bins 0..3
+  const int32_t* init;               // nullable initial colors
+  int32_t* C;                        // committed colors (written: init or 0)
+  int32_t* T;                        // tentative colors (written: init or 0)
+  int32_t* work;                     // out: static work per vertex
+  int8_t* bin;                       // out: bin per vertex
+  int32_t* count_all;                // out: vertices per bin
+  int32_t* count_unc;                // out: uncolored vertices per bin
+  int32_t* maxc;                     // out: largest initial color
+  int32_t* max_split_work;           // out: largest work among uncolored split vertices
+  unsigned long long* total_work;    // out: work of the initial worklist
+};
+
+template <int MODE>
+void launch_bin(const GraphView& g, const BinSetup& s, hipStream_t st);
+void launch_scatter(int32_t n, const int32_t* C, const int8_t* bin, const BinLayout& L, int32_t* wl,
+                    int32_t* cnt, int32_t* split_vertex, hipStream_t st);
+void launch_validate(int32_t n_rows, int32_t n_cols, const int32_t* rp, const int32_t* ci,
+                     const int32_t* rpT, const int32_t* ciT, int32_t n_trows, int square, int32_t* err,
+                     hipStream_t st);
+void launch_priority(int32_t n, const int32_t* gid, uint32_t hs, uint32_t* out, hipStream_t st);
+void launch_boundary(int32_t n_owned, const int32_t* rp, const int32_t* ci, const int32_t* C,
+                     const int32_t* ghost_colors, const KeySource& k, int32_t* loser, int32_t* gflag,
+                     unsigned long long* conflicts, hipStream_t st);
+void launch_boundary_uncolor(int32_t n_owned, const int32_t* loser, int32_t* C, hipStream_t st);
+void launch_ghost_fill(int32_t n_owned, int32_t n_ghost, const int32_t* gc, int32_t* C, int32_t* T,
+                       int32_t* maxc, hipStream_t st);
+void launch_max_i32(int32_t n, const int32_t* a, int32_t* out, hipStream_t st);
+void launch_flags_out(int32_t n, const int32_t* gflag, uint8_t* out, unsigned long long* count,
+                      hipStream_t st);
+void launch_copy_i32(int32_t n, const int32_t* src, int32_t* dst, hipStream_t st);
+
+}  // namespace gcol

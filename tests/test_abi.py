@@ -1,0 +1,62 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports
+every entry point include/graphcolor.h declares, and rejects bad arguments
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "graphcolor.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(color_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2107_00075_amd import _binding
+    if not os.path.exists(_binding.LIB_PATH):
+        pytest.fail("libgraphcolor.so is not built (run __graft_entry__.build())")
+    return _binding.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for required in ("color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_batch",
+                     "color_server_create", "color_server_submit", "color_server_poll",
+                     "color_server_destroy", "color_strerror", "color_priority"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2107_00075_amd import _binding
+    raw = ctypes.CDLL(_binding.LIB_PATH)
+    for name in _declared():
+        assert hasattr(raw, name), name
+    assert set(_declared()) == set(_binding.EXPORTED)
+
+
+def test_strerror(lib):
+    from paper_2107_00075_amd import _binding as b
+    assert lib.color_strerror(0) == b"ok"
+    for code in (b.COLOR_EINVAL, b.COLOR_EGRAPH, b.COLOR_EOVERFLOW, b.COLOR_ENOMEM, b.COLOR_EHIP,
+                 b.COLOR_ENOCONVERGE, b.COLOR_E2BIG, b.COLOR_EQUEUED, b.COLOR_EPENDING):
+        assert lib.color_strerror(code) not in (b"ok", b"unknown error")
+    assert lib.color_strerror(12345) == b"unknown error"
+
+
+def test_bad_arguments_rejected_on_host(lib):
+    from paper_2107_00075_amd import _binding as b
+    assert lib.color_d1(-1, None, None, 1, None, None, None, None, None, None) == b.COLOR_EINVAL
+    assert lib.color_d2(5, None, None, 1, None, None, None, None, None, None) == b.COLOR_EINVAL
+    assert lib.color_pd2(-2, 3, None, None, None, None, 1, None, None, None, None, None, None) == b.COLOR_EINVAL
+    assert lib.color_d1_ghost(4, 2, 3, 0, None, None, None, None, 1, None, None, None, None, None) == b.COLOR_EINVAL
+    assert lib.color_d1_ghost(4, 2, 1, 5, None, None, None, None, 1, None, None, None, None, None) == b.COLOR_EINVAL
+    assert lib.color_priority(-1, None, 1, None, None) == b.COLOR_EINVAL
+    assert lib.color_batch(-1, None, None, None, None) == b.COLOR_EINVAL
