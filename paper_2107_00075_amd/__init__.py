@@ -40,7 +40,20 @@ def _dev_ptr(t, name, dtype=None, n=None):
         raise ValueError(f"{name} must be contiguous")
     if n is not None and t.numel() < n:
         raise ValueError(f"{name} has {t.numel()} elements, needs {n}")
+    if t.numel() == 0:  # an empty array still needs a valid (never read) address
+        t = _placeholder(t.device)
     return ctypes.c_void_p(t.data_ptr())
+
+
+_PLACEHOLDERS = {}
+
+
+def _placeholder(device):
+    torch = _torch()
+    key = str(device)
+    if key not in _PLACEHOLDERS:
+        _PLACEHOLDERS[key] = torch.zeros(16, dtype=torch.int32, device=device)
+    return _PLACEHOLDERS[key]
 
 
 def _stream(stream):
