@@ -69,6 +69,7 @@ extern "C" {
 
 #define COLOR_FLAG_VALIDATE 0x1u  /* check the input contract on the device first */
 #define COLOR_FLAG_NO_TAIL  0x2u  /* never switch to the single-workgroup tail kernel */
+#define COLOR_FLAG_KERNEL_TIMING 0x4u  /* time every round kernel with HIP events on `stream` */
 
 /* Per-call statistics (HOST struct, every pointer argument of this type is
  * nullable). */
@@ -83,6 +84,12 @@ typedef struct color_stats {
     int64_t* worklist_trace;     /* in: HOST array or NULL; out: |W_r| for r = 1..min(rounds, trace_cap) */
     int32_t trace_cap;           /* in: capacity of worklist_trace */
     int32_t kernel_launches;     /* kernels the call enqueued */
+    /* COLOR_FLAG_KERNEL_TIMING only (else 0): summed HIP-event durations of
+       the color and the detect round kernels, and their launch counts */
+    int64_t color_kernel_ns;
+    int64_t detect_kernel_ns;
+    int32_t color_launches;
+    int32_t detect_launches;
 } color_stats;
 
 /* Tuning knobs (HOST struct, nullable = library defaults / autotuned).  None

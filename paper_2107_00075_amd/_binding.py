@@ -27,6 +27,7 @@ COLOR_EPENDING = 2
 
 COLOR_FLAG_VALIDATE = 0x1
 COLOR_FLAG_NO_TAIL = 0x2
+COLOR_FLAG_KERNEL_TIMING = 0x4
 
 KIND_D1, KIND_D2, KIND_PD2 = 1, 2, 3
 
@@ -48,7 +49,9 @@ class CStats(ctypes.Structure):
                 ("vertex_visits", ctypes.c_int64), ("edge_visits", ctypes.c_int64),
                 ("boundary_conflicts", ctypes.c_int64), ("remote_losers", ctypes.c_int64),
                 ("worklist_trace", ctypes.POINTER(ctypes.c_int64)), ("trace_cap", ctypes.c_int32),
-                ("kernel_launches", ctypes.c_int32)]
+                ("kernel_launches", ctypes.c_int32), ("color_kernel_ns", ctypes.c_int64),
+                ("detect_kernel_ns", ctypes.c_int64), ("color_launches", ctypes.c_int32),
+                ("detect_launches", ctypes.c_int32)]
 
 
 class CParams(ctypes.Structure):
@@ -79,6 +82,11 @@ class Stats:
     boundary_conflicts: int = 0
     remote_losers: int = 0
     kernel_launches: int = 0
+    color_kernel_ns: int = 0
+    detect_kernel_ns: int = 0
+    color_launches: int = 0
+    detect_launches: int = 0
+    converged: bool = True
     worklist: list = field(default_factory=list)
 
 

@@ -52,7 +52,22 @@ void DevBuf::release() {
 
 Workspace::~Workspace() { release(); }
 
+int Call::record_event(int kind_of_next) {
+  std::vector<hipEvent_t>& ev = ws->events;
+  if (n_events == ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return COLOR_EHIP;
+    ev.push_back(e);
+  }
+  if (hipEventRecord(ev[n_events], st) != hipSuccess) return COLOR_EHIP;
+  event_kind.push_back(kind_of_next);
+  ++n_events;
+  return COLOR_OK;
+}
+
 void Workspace::release() {
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  events.clear();
   for (DevBuf* b : {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
                     &split_flag, &split_mask, &aux0, &aux1})
     b->release();
@@ -173,9 +188,14 @@ int run_phase(Call& c, const GraphView& g, const KeySource& k, const BinLayout& 
       b.wl_out = wl[pout];
       b.cnt_in = S->cnt[pin];
       b.cnt_out = S->cnt[pout];
+      if (c.timing && c.record_event(0)) return COLOR_EHIP;
       launch_color_round<MODE>(g, k, b, L, round0 + local, grid, c.st);
+      if (c.timing && c.record_event(1)) return COLOR_EHIP;
       launch_detect_round<MODE>(g, k, b, L, round0 + local, grid, c.st);
+      if (c.timing && c.record_event(-1)) return COLOR_EHIP;
       c.launches += 2;
+      c.color_launches += 1;
+      c.detect_launches += 1;
     }
     if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
     if (hipMemcpyAsync(H->cnt[local & 1], S->cnt[local & 1], sizeof(int32_t) * 8, hipMemcpyDeviceToHost,
@@ -277,6 +297,7 @@ int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, 
   c.ws = workspace_for_current_device(&e);
   if (!c.ws) return e;
   c.trace_cap = (stats && stats->worklist_trace && stats->trace_cap > 0) ? stats->trace_cap : 0;
+  c.timing = (c.P.flags & COLOR_FLAG_KERNEL_TIMING) != 0 && stats != nullptr;
   Workspace* w = c.ws;
   if ((e = w->small.ensure(sizeof(Scalars), false, c.st))) return e;
   if ((e = w->T.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n_total, 1)), false, c.st))) return e;
@@ -305,6 +326,22 @@ int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc) {
     stats->boundary_conflicts = static_cast<int64_t>(c.H->conflicts);
     stats->remote_losers = static_cast<int64_t>(c.H->remote);
     stats->kernel_launches = c.launches;
+    stats->color_kernel_ns = 0;
+    stats->detect_kernel_ns = 0;
+    stats->color_launches = c.color_launches;
+    stats->detect_launches = c.detect_launches;
+    if (c.timing) {
+      // event i opens a kernel of kind event_kind[i] that event i+1 closes
+      for (size_t i = 0; i + 1 < c.n_events; ++i) {
+        const int kind = c.event_kind[i];
+        if (kind < 0) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c.ws->events[i], c.ws->events[i + 1]) != hipSuccess) return COLOR_EHIP;
+        const int64_t ns = static_cast<int64_t>(static_cast<double>(ms) * 1e6);
+        if (kind == 0) stats->color_kernel_ns += ns;
+        else stats->detect_kernel_ns += ns;
+      }
+    }
     if (c.trace_cap > 0) {
       const int nr = std::min(c.trace_cap, c.H->rounds_done);
       if (nr > 0) {

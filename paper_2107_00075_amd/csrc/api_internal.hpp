@@ -2,6 +2,7 @@
 #pragma once
 
 #include <mutex>
+#include <vector>
 
 #include "graphcolor.h"
 #include "setup.hpp"
@@ -44,6 +45,7 @@ struct Workspace {
   std::mutex mu;
   DevBuf T, C, work, bin, wl0, wl1, small, trace, split_vertex, split_ctr, split_flag, split_mask, aux0, aux1;
   Scalars* host = nullptr;  // pinned staging for read-backs
+  std::vector<hipEvent_t> events;  // pool for COLOR_FLAG_KERNEL_TIMING
   ~Workspace();
   void release();
 };
@@ -60,6 +62,13 @@ struct Call {
   Scalars* S = nullptr;
   Scalars* H = nullptr;
   int32_t* wl[2] = {nullptr, nullptr};
+  // kernel timing (COLOR_FLAG_KERNEL_TIMING): events recorded around every
+  // round kernel, resolved after the call's last synchronization
+  bool timing = false;
+  size_t n_events = 0;
+  std::vector<int> event_kind;  // per event pair start index: 0 color, 1 detect
+  int color_launches = 0, detect_launches = 0;
+  int record_event(int kind_of_next);  // records the next pool event on st
 };
 
 void default_params(int mode, color_params* p);
