@@ -130,7 +130,7 @@ void default_params(int mode, color_params* p) {
   p->max_rounds = 0;
   p->rounds_per_poll = 4;
   p->tail_threshold = 0;
-  p->max_workgroups = 2048;
+  p->max_workgroups = resident_round_blocks(mode);
   p->flags = 0;
 }
 
@@ -177,7 +177,9 @@ int run_phase(Call& c, const GraphView& g, const KeySource& k, const BinLayout& 
     if (total == 0) break;
     if (max_rounds > 0 && local >= max_rounds) return COLOR_ENOCONVERGE;
     const int64_t units = round_units(known, L);
-    const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(units, c.P.max_workgroups)));
+    int64_t grid64 = std::min<int64_t>(units, c.P.max_workgroups);
+    if (grid64 >= 8) grid64 = grid64 / 8 * 8;  // one equal share per XCD
+    const int grid = static_cast<int>(std::max<int64_t>(1, grid64));
     int n_launch = R;
     if (max_rounds > 0) n_launch = std::min(n_launch, max_rounds - local);
     for (int i = 0; i < n_launch; ++i) {

@@ -89,4 +89,28 @@ __device__ __forceinline__ int32_t atomic_load_i32(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Kernel-boundary visibility across XCDs.  Each of the 8 XCDs has its own
+// L2, and measurement on MI355X showed plain stores of one kernel were not
+// reliably seen by plain loads of the next kernel on another XCD.  Every
+// kernel of the library therefore invalidates its non-coherent caches before
+// it reads data written by an earlier kernel (agent-scope acquire: buffer_inv)
+// and writes its L2 back before it ends (agent-scope release: buffer_wbl2).
+// One wavefront per workgroup issues each fence; the workgroup barrier orders
+// the other wavefronts' accesses after (acquire) or before (release) it.
+__device__ __forceinline__ void block_acquire() {
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+}
+__device__ __forceinline__ void block_release() {
+  __syncthreads();
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
+// Resets of words that other workgroups update with atomics in the same
+// kernel use an atomic read-modify-write too, so that every access to such a
+// word (and to its cache line) is performed at the same coherence point;
+// a plain store there could leave a dirty partial line in one XCD's L2.
+__device__ __forceinline__ void atomic_reset_u32(uint32_t* p) { (void)atomicExch(p, 0u); }
+__device__ __forceinline__ void atomic_reset_i32(int32_t* p) { (void)atomicExch(p, 0); }
+
 }  // namespace gcol

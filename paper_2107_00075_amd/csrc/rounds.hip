@@ -8,8 +8,8 @@
 //   detect : v loses when a neighbour u holds T[u] == T[v] with key(u) >
 //            key(v) (Section 3.2, Algorithms 3 and 4, with the lower key
 //            uncolored).  Only T is read.  Winners commit C[v] = T[v] in
-//            place; losers are appended to W_{r+1} by wavefront-ballot
-//            compaction (one atomic per wavefront).
+//            place; losers are appended to W_{r+1} by ballot/prefix
+//            compaction.
 // Committed neighbours never tie: T[u] == C[u] for them and T[v] avoids every
 // committed neighbour color, so reading T of all neighbours equals reading T
 // of the worklist neighbours only.  Neither kernel reads what it writes, so
@@ -28,7 +28,11 @@
 // merge their windows into a global per-vertex bitset; the last workgroup to
 // arrive picks the color or commits (the edge-split parallelism that the
 // paper's edge-based kernel provides for very high degrees, Section 3.2).
-// Workgroups take units of work from a device counter, heavy bins first.
+// Light bins are cut into chunks of 256 worklist entries that workgroups take
+// by a static XCD-aware partition (no device atomics on the hot path; one
+// atomic per chunk appends the chunk's losers); heavy units are taken
+// dynamically from a device counter afterwards.
+#include <algorithm>
 #include <climits>
 
 #include "rounds.hpp"
@@ -57,27 +61,51 @@ __device__ __forceinline__ void scan_nbhd(const GraphView& g, int32_t v, int32_t
   }
 }
 
-struct UnitMap {
+// Per-round work map, built once per workgroup in LDS.  Light bins (0..2) are
+// cut into chunks of kBlock worklist entries that workgroups take by a static,
+// XCD-aware partition; heavy units (one per bin-3 vertex, split_chunks per
+// bin-4 vertex) are taken dynamically from a device counter afterwards.
+struct RoundMap {
   int32_t cnt[kBins];
-  int64_t tiles[3];    // tiles of bins 0..2
-  int64_t units[kBins];
-  int64_t total;
+  int32_t chunks[3];
+  int32_t light_total;
+  int32_t heavy_block;   // units of bin 3
+  int32_t heavy_total;   // units of bins 3 and 4
 };
 
-__device__ __forceinline__ void make_unit_map(const RoundBufs& b, const BinLayout& L, UnitMap& m) {
-  m.total = 0;
-#pragma unroll
-  for (int i = 0; i < kBins; ++i) m.cnt[i] = b.cnt_in[i];
-#pragma unroll
+__device__ __forceinline__ void make_round_map(const RoundBufs& b, const BinLayout& L, RoundMap& m) {
+  int32_t lt = 0;
+  for (int i = 0; i < kBins; ++i) m.cnt[i] = atomic_load_i32(&b.cnt_in[i]);
   for (int i = 0; i < 3; ++i) {
-    const int64_t per_tile = kBlock / L.lanes[i];
-    m.tiles[i] = (m.cnt[i] + per_tile - 1) / per_tile;
-    m.units[i] = (m.tiles[i] + L.grab - 1) / L.grab;
+    m.chunks[i] = (m.cnt[i] + kBlock - 1) / kBlock;
+    lt += m.chunks[i];
   }
-  m.units[kBlockBin] = m.cnt[kBlockBin];
-  m.units[kSplitBin] = static_cast<int64_t>(m.cnt[kSplitBin]) * L.split_chunks;
-#pragma unroll
-  for (int i = 0; i < kBins; ++i) m.total += m.units[i];
+  m.light_total = lt;
+  m.heavy_block = m.cnt[kBlockBin];
+  m.heavy_total = m.cnt[kBlockBin] + m.cnt[kSplitBin] * L.split_chunks;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; this renumbering
+// gives every XCD a contiguous range of logical ids, so each XCD's L2 sees a
+// contiguous range of the worklist (neighbouring ids share cache lines).
+__device__ __forceinline__ int32_t xcd_logical_block() {
+  const int32_t nb = gridDim.x;
+  const int32_t per = nb / 8;
+  const int32_t i = blockIdx.x;
+  if (per == 0 || (nb & 7) != 0) return i;
+  return (i & 7) * per + (i >> 3);
+}
+
+// Chunk c of the light bins -> (bin, first entry, entries).
+__device__ __forceinline__ void light_chunk(const RoundMap& m, int32_t c, int& bin, int32_t& first,
+                                            int32_t& count) {
+  bin = 0;
+  while (bin < 2 && c >= m.chunks[bin]) {
+    c -= m.chunks[bin];
+    ++bin;
+  }
+  first = c * kBlock;
+  count = min(kBlock, m.cnt[bin] - first);
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
@@ -93,19 +121,17 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
 }
 
 // ---------------------------------------------------------------------------
-// color: group of G lanes per vertex
+// color: group of G lanes per vertex, one chunk of kBlock worklist entries
 // ---------------------------------------------------------------------------
 template <int MODE, int G>
-__device__ void color_tiles_group(const GraphView& g, const RoundBufs& b, int32_t cnt,
-                                  int32_t off, int64_t t0, int64_t t1, uint64_t& work_acc) {
-  constexpr int per_tile = kBlock / G;
+__device__ void color_chunk_group(const GraphView& g, const RoundBufs& b, const int32_t* wl, int32_t count,
+                                  uint64_t& work_acc) {
+  constexpr int per_pass = kBlock / G;
   const int gi = threadIdx.x / G;
   const int sub = threadIdx.x % G;
   const int32_t* __restrict__ C = b.C;
-  for (int64_t t = t0; t < t1; ++t) {
-    const int64_t idx = t * per_tile + gi;
-    if (idx >= cnt) break;  // the whole group leaves together
-    const int32_t v = b.wl_in[off + idx];
+  for (int32_t idx = gi; idx < count; idx += per_pass) {  // whole groups stay together
+    const int32_t v = wl[idx];
     const int32_t beg = g.rp[v], end = g.rp[v + 1];
     int32_t base = 1;
     while (true) {
@@ -247,10 +273,10 @@ __device__ void color_split_chunk(const GraphView& g, const RoundBufs& b, const 
     }
     __syncthreads();
     const int32_t bit = s_misc[0];
-    for (int w = tid; w < nwords; w += kBlock) gm[w] = 0u;
+    for (int w = tid; w < nwords; w += kBlock) atomic_reset_u32(&gm[w]);
     if (tid == 0) {
       b.T[v] = (bit == INT_MAX ? nwords * 32 : bit) + 1;
-      b.split_ctr[si] = 0u;
+      atomic_reset_u32(&b.split_ctr[si]);
     }
   }
   __syncthreads();
@@ -262,115 +288,130 @@ __global__ __launch_bounds__(kBlock) void color_round_kernel(GraphView g, KeySou
   __shared__ uint32_t ovf[kOvfWords];
   __shared__ uint64_t red[kWavesPerBlock];
   __shared__ int32_t s_misc[4];
-  __shared__ int64_t s_unit;
+  __shared__ int32_t s_unit;
   __shared__ unsigned long long s_work;
+  __shared__ RoundMap M;
   (void)k;
-  UnitMap um;
-  make_unit_map(b, L, um);
-  if (threadIdx.x == 0) s_work = 0ull;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    int64_t total = 0;
-    for (int i = 0; i < kBins; ++i) {
-      b.cnt_out[i] = 0;
-      total += um.cnt[i];
-    }
-    b.tile_ctr[1] = 0;
-    if (total > 0) {
-      *b.rounds_done = round;
-      if (b.trace && round <= b.trace_cap) b.trace[round - 1] = static_cast<int32_t>(total);
-      atomicAdd(&b.visits[0], static_cast<unsigned long long>(total));
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see block_acquire()
+    make_round_map(b, L, M);
+    s_work = 0ull;
+    if (blockIdx.x == 0) {
+      int64_t total = 0;
+      for (int i = 0; i < kBins; ++i) {
+        atomic_reset_i32(&b.cnt_out[i]);
+        total += M.cnt[i];
+      }
+      atomic_reset_i32(&b.tile_ctr[1]);
+      if (total > 0) {
+        atomicMax(b.rounds_done, round);
+        if (b.trace && round <= b.trace_cap) b.trace[round - 1] = static_cast<int32_t>(total);
+        atomicAdd(&b.visits[0], static_cast<unsigned long long>(total));
+      }
     }
   }
+  __syncthreads();
   uint64_t work_acc = 0;
-  while (true) {
-    if (threadIdx.x == 0) s_unit = atomicAdd(&b.tile_ctr[0], 1);
-    __syncthreads();
-    int64_t u = s_unit;
-    __syncthreads();
-    if (u >= um.total) break;
-    if (u < um.units[kSplitBin]) {
-      const int32_t si = b.wl_in[L.off[kSplitBin] + u / L.split_chunks];
-      color_split_chunk<MODE>(g, b, L, si, static_cast<int>(u % L.split_chunks), ovf, red, s_misc,
-                              work_acc);
-      continue;
+  // light bins: a static, contiguous share of chunks per workgroup
+  const int32_t lb = xcd_logical_block();
+  const int32_t c0 = static_cast<int32_t>(static_cast<int64_t>(lb) * M.light_total / gridDim.x);
+  const int32_t c1 = static_cast<int32_t>(static_cast<int64_t>(lb + 1) * M.light_total / gridDim.x);
+  for (int32_t c = c0; c < c1; ++c) {
+    int bin;
+    int32_t first, count;
+    light_chunk(M, c, bin, first, count);
+    const int32_t* wl = b.wl_in + L.off[bin] + first;
+    switch (L.lanes[bin]) {
+      case 1: color_chunk_group<MODE, 1>(g, b, wl, count, work_acc); break;
+      case 2: color_chunk_group<MODE, 2>(g, b, wl, count, work_acc); break;
+      case 4: color_chunk_group<MODE, 4>(g, b, wl, count, work_acc); break;
+      case 8: color_chunk_group<MODE, 8>(g, b, wl, count, work_acc); break;
+      case 16: color_chunk_group<MODE, 16>(g, b, wl, count, work_acc); break;
+      case 32: color_chunk_group<MODE, 32>(g, b, wl, count, work_acc); break;
+      default: color_chunk_group<MODE, 64>(g, b, wl, count, work_acc); break;
     }
-    u -= um.units[kSplitBin];
-    if (u < um.units[kBlockBin]) {
-      const int32_t v = b.wl_in[L.off[kBlockBin] + u];
-      color_vertex_block<MODE>(g, b, v, ovf, red, &s_misc[0]);
-      if (threadIdx.x == 0) work_acc += static_cast<uint64_t>(b.work[v]);
-      continue;
-    }
-    u -= um.units[kBlockBin];
-    for (int bin = 2; bin >= 0; --bin) {
-      if (u < um.units[bin]) {
-        const int64_t t0 = u * L.grab;
-        const int64_t t1 = min(t0 + L.grab, um.tiles[bin]);
-        const int32_t cnt = um.cnt[bin], off = L.off[bin];
-        switch (L.lanes[bin]) {
-          case 1: color_tiles_group<MODE, 1>(g, b, cnt, off, t0, t1, work_acc); break;
-          case 2: color_tiles_group<MODE, 2>(g, b, cnt, off, t0, t1, work_acc); break;
-          case 4: color_tiles_group<MODE, 4>(g, b, cnt, off, t0, t1, work_acc); break;
-          case 8: color_tiles_group<MODE, 8>(g, b, cnt, off, t0, t1, work_acc); break;
-          case 16: color_tiles_group<MODE, 16>(g, b, cnt, off, t0, t1, work_acc); break;
-          case 32: color_tiles_group<MODE, 32>(g, b, cnt, off, t0, t1, work_acc); break;
-          default: color_tiles_group<MODE, 64>(g, b, cnt, off, t0, t1, work_acc); break;
-        }
-        break;
+  }
+  // heavy bins: units taken dynamically
+  if (M.heavy_total > 0) {
+    while (true) {
+      if (threadIdx.x == 0) s_unit = atomicAdd(&b.tile_ctr[0], 1);
+      __syncthreads();
+      const int32_t u = s_unit;
+      __syncthreads();
+      if (u >= M.heavy_total) break;
+      if (u < M.heavy_block) {
+        const int32_t v = b.wl_in[L.off[kBlockBin] + u];
+        color_vertex_block<MODE>(g, b, v, ovf, red, &s_misc[0]);
+        if (threadIdx.x == 0) work_acc += static_cast<uint64_t>(b.work[v]);
+      } else {
+        const int32_t us = u - M.heavy_block;
+        const int32_t si = b.wl_in[L.off[kSplitBin] + us / L.split_chunks];
+        color_split_chunk<MODE>(g, b, L, si, us % L.split_chunks, ovf, red, s_misc, work_acc);
       }
-      u -= um.units[bin];
     }
   }
   work_acc = wave_sum_u64(work_acc);
   if (lane_id() == 0 && work_acc) atomicAdd(&s_work, static_cast<unsigned long long>(work_acc));
   __syncthreads();
   if (threadIdx.x == 0 && s_work) atomicAdd(&b.visits[1], s_work);
+  block_release();
 }
 
 // ---------------------------------------------------------------------------
-// detect + commit + compact: group of G lanes per vertex
+// detect + commit + compact: group of G lanes per vertex, one chunk
 // ---------------------------------------------------------------------------
+// Losers of the chunk are collected in LDS and appended to W_{r+1} with one
+// device atomic per chunk (workgroup prefix over the wavefront ballots).
 template <int MODE, int G>
-__device__ void detect_tiles_group(const GraphView& g, const KeySource& k, const RoundBufs& b,
-                                   int bin, int32_t cnt, int32_t off, int64_t t0, int64_t t1,
-                                   int32_t& maxc_acc) {
-  constexpr int per_tile = kBlock / G;
+__device__ void detect_chunk_group(const GraphView& g, const KeySource& k, const RoundBufs& b, int bin,
+                                   const int32_t* wl, int32_t count, int32_t off_out, int32_t* s_ent,
+                                   int32_t* s_wc, int32_t& maxc_acc) {
+  constexpr int per_pass = kBlock / G;
   const int gi = threadIdx.x / G;
   const int sub = threadIdx.x % G;
   const int32_t* __restrict__ T = b.T;
-  for (int64_t t = t0; t < t1; ++t) {
-    if (t * per_tile >= cnt) break;  // uniform over the workgroup
-    const int64_t idx = t * per_tile + gi;
-    const bool active = idx < cnt;
-    int32_t v = 0, tv = 0;
+  for (int32_t idx = gi; idx < count; idx += per_pass) {
+    const int32_t v = wl[idx];
+    const int32_t tv = T[v];
+    const uint64_t kv = key_of(k, v);
     bool lose = false;
-    if (active) {
-      v = b.wl_in[off + idx];
-      tv = T[v];
-      const uint64_t kv = key_of(k, v);
-      scan_nbhd<MODE>(g, v, g.rp[v], g.rp[v + 1], sub, G, [&](int32_t u) {
-        if (T[u] == tv && key_of(k, u) > kv) {
-          lose = true;
-          return true;
-        }
-        return false;
-      });
-    }
+    scan_nbhd<MODE>(g, v, g.rp[v], g.rp[v + 1], sub, G, [&](int32_t u) {
+      if (T[u] == tv && key_of(k, u) > kv) {
+        lose = true;
+        return true;
+      }
+      return false;
+    });
     lose = group_any<G>(lose);
-    const bool leader = active && sub == 0;
-    if (leader && !lose) {
-      b.C[v] = tv;
-      maxc_acc = max(maxc_acc, tv);
-    }
-    const uint64_t bal = __ballot(leader && lose);
-    if (bal) {
-      const int first = __builtin_ctzll(bal);
-      int32_t base = 0;
-      if (lane_id() == first) base = atomicAdd(&b.cnt_out[bin], static_cast<int32_t>(__popcll(bal)));
-      base = __shfl(base, first, kWave);
-      if (leader && lose) b.wl_out[off + base + static_cast<int32_t>(lanes_below(bal))] = v;
+    if (sub == 0) {
+      if (lose) {
+        s_ent[idx] = v;
+      } else {
+        s_ent[idx] = -1;
+        b.C[v] = tv;
+        maxc_acc = max(maxc_acc, tv);
+      }
     }
   }
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int32_t x = tid < count ? s_ent[tid] : -1;
+  const uint64_t bal = __ballot(x >= 0);
+  if (lane_id() == 0) s_wc[wave] = static_cast<int32_t>(__popcll(bal));
+  __syncthreads();
+  if (tid == 0) {
+    int32_t tot = 0;
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+      const int32_t c = s_wc[w];
+      s_wc[w] = tot;
+      tot += c;
+    }
+    s_wc[kWavesPerBlock] = tot ? atomicAdd(&b.cnt_out[bin], tot) : 0;
+  }
+  __syncthreads();
+  if (x >= 0) b.wl_out[off_out + s_wc[kWavesPerBlock] + s_wc[wave] + static_cast<int32_t>(lanes_below(bal))] = x;
+  __syncthreads();
 }
 
 template <int MODE>
@@ -440,8 +481,8 @@ __device__ void detect_split_chunk(const GraphView& g, const KeySource& k, const
         const int32_t pos = atomicAdd(&b.cnt_out[kSplitBin], 1);
         b.wl_out[L.off[kSplitBin] + pos] = si;
       }
-      b.split_flag[si] = 0u;
-      b.split_ctr[si] = 0u;
+      atomic_reset_u32(&b.split_flag[si]);
+      atomic_reset_u32(&b.split_ctr[si]);
     }
   }
   __syncthreads();
@@ -451,56 +492,85 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void detect_round_kernel(GraphView g, KeySource k, RoundBufs b,
                                                               BinLayout L, int round) {
   __shared__ int32_t s_misc[4];
-  __shared__ int64_t s_unit;
+  __shared__ int32_t s_unit;
   __shared__ int32_t s_max;
+  __shared__ int32_t s_ent[kBlock];
+  __shared__ int32_t s_wc[kWavesPerBlock + 1];
+  __shared__ RoundMap M;
   (void)round;
-  UnitMap um;
-  make_unit_map(b, L, um);
-  if (threadIdx.x == 0) s_max = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) b.tile_ctr[0] = 0;
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see block_acquire()
+    make_round_map(b, L, M);
+    s_max = 0;
+    if (blockIdx.x == 0) atomic_reset_i32(&b.tile_ctr[0]);
+  }
+  __syncthreads();
   int32_t maxc_acc = 0;
-  while (true) {
-    if (threadIdx.x == 0) s_unit = atomicAdd(&b.tile_ctr[1], 1);
-    __syncthreads();
-    int64_t u = s_unit;
-    __syncthreads();
-    if (u >= um.total) break;
-    if (u < um.units[kSplitBin]) {
-      const int32_t si = b.wl_in[L.off[kSplitBin] + u / L.split_chunks];
-      detect_split_chunk<MODE>(g, k, b, L, si, static_cast<int>(u % L.split_chunks), s_misc,
-                               maxc_acc);
-      continue;
+  const int32_t lb = xcd_logical_block();
+  const int32_t c0 = static_cast<int32_t>(static_cast<int64_t>(lb) * M.light_total / gridDim.x);
+  const int32_t c1 = static_cast<int32_t>(static_cast<int64_t>(lb + 1) * M.light_total / gridDim.x);
+  for (int32_t c = c0; c < c1; ++c) {
+    int bin;
+    int32_t first, count;
+    light_chunk(M, c, bin, first, count);
+    const int32_t* wl = b.wl_in + L.off[bin] + first;
+    const int32_t oo = L.off[bin];
+    switch (L.lanes[bin]) {
+      case 1: detect_chunk_group<MODE, 1>(g, k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc); break;
+      case 2: detect_chunk_group<MODE, 2>(g, k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc); break;
+      case 4: detect_chunk_group<MODE, 4>(g, k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc); break;
+      case 8: detect_chunk_group<MODE, 8>(g, k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc); break;
+      case 16: detect_chunk_group<MODE, 16>(g, k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc); break;
+      case 32: detect_chunk_group<MODE, 32>(g, k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc); break;
+      default: detect_chunk_group<MODE, 64>(g, k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc); break;
     }
-    u -= um.units[kSplitBin];
-    if (u < um.units[kBlockBin]) {
-      const int32_t v = b.wl_in[L.off[kBlockBin] + u];
-      detect_vertex_block<MODE>(g, k, b, v, L.off[kBlockBin], maxc_acc);
-      continue;
-    }
-    u -= um.units[kBlockBin];
-    for (int bin = 2; bin >= 0; --bin) {
-      if (u < um.units[bin]) {
-        const int64_t t0 = u * L.grab;
-        const int64_t t1 = min(t0 + L.grab, um.tiles[bin]);
-        const int32_t cnt = um.cnt[bin], off = L.off[bin];
-        switch (L.lanes[bin]) {
-          case 1: detect_tiles_group<MODE, 1>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
-          case 2: detect_tiles_group<MODE, 2>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
-          case 4: detect_tiles_group<MODE, 4>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
-          case 8: detect_tiles_group<MODE, 8>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
-          case 16: detect_tiles_group<MODE, 16>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
-          case 32: detect_tiles_group<MODE, 32>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
-          default: detect_tiles_group<MODE, 64>(g, k, b, bin, cnt, off, t0, t1, maxc_acc); break;
-        }
-        break;
+  }
+  if (M.heavy_total > 0) {
+    while (true) {
+      if (threadIdx.x == 0) s_unit = atomicAdd(&b.tile_ctr[1], 1);
+      __syncthreads();
+      const int32_t u = s_unit;
+      __syncthreads();
+      if (u >= M.heavy_total) break;
+      if (u < M.heavy_block) {
+        const int32_t v = b.wl_in[L.off[kBlockBin] + u];
+        detect_vertex_block<MODE>(g, k, b, v, L.off[kBlockBin], maxc_acc);
+      } else {
+        const int32_t us = u - M.heavy_block;
+        const int32_t si = b.wl_in[L.off[kSplitBin] + us / L.split_chunks];
+        detect_split_chunk<MODE>(g, k, b, L, si, us % L.split_chunks, s_misc, maxc_acc);
       }
-      u -= um.units[bin];
     }
   }
   maxc_acc = wave_max_i32(maxc_acc);
   if (lane_id() == 0 && maxc_acc > 0) atomicMax(&s_max, maxc_acc);
   __syncthreads();
   if (threadIdx.x == 0 && s_max > 0) atomicMax(b.maxc, s_max);
+  block_release();
+}
+
+template <int MODE>
+static int resident_blocks_of() {
+  int dev = 0, cus = 0, a = 0, d = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 2048;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 2048;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, color_round_kernel<MODE>, kBlock, 0) != hipSuccess)
+    return 2048;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, detect_round_kernel<MODE>, kBlock, 0) != hipSuccess)
+    return 2048;
+  const int per_cu = std::max(1, std::min(a, d));
+  return std::max(8, (per_cu * cus) / 8 * 8);
+}
+
+int resident_round_blocks(int mode) {
+  static int cache[4] = {0, 0, 0, 0};
+  if (mode < 1 || mode > 3) return 2048;
+  if (cache[mode] == 0) {
+    cache[mode] = mode == kD1 ? resident_blocks_of<kD1>()
+                  : mode == kD2 ? resident_blocks_of<kD2>()
+                                : resident_blocks_of<kPD2>();
+  }
+  return cache[mode];
 }
 
 template <int MODE>

@@ -62,17 +62,18 @@ template <int MODE>
 void launch_detect_round(const GraphView& g, const KeySource& k, const RoundBufs& b,
                          const BinLayout& L, int round, int grid, hipStream_t st);
 
-// Units (grabs) a round kernel has for the given per-bin counts.
+// Workgroups a round kernel can use for the given per-bin counts: light
+// chunks of kBlock entries plus heavy units.
 inline int64_t round_units(const int32_t cnt[kBins], const BinLayout& L) {
   int64_t u = 0;
-  for (int b = 0; b < 3; ++b) {
-    const int64_t per_tile = kBlock / L.lanes[b];
-    const int64_t tiles = (cnt[b] + per_tile - 1) / per_tile;
-    u += (tiles + L.grab - 1) / L.grab;
-  }
+  for (int b = 0; b < 3; ++b) u += (cnt[b] + kBlock - 1) / kBlock;
   u += cnt[kBlockBin];
   u += static_cast<int64_t>(cnt[kSplitBin]) * L.split_chunks;
   return u;
 }
+
+// Workgroups of the round kernels that are resident on the device at once
+// (occupancy x compute units), a multiple of 8 (one share per XCD).
+int resident_round_blocks(int mode);
 
 }  // namespace gcol

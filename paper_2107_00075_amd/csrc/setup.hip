@@ -24,6 +24,7 @@ __device__ __forceinline__ int64_t vertex_work(const GraphView& g, int32_t v) {
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
+  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
   const bool active = v < g.n;
   int bin = -1;
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
       if (unc) atomicAdd(&s.count_unc[i], static_cast<int32_t>(__popcll(unc)));
     }
   }
+  block_release();
 }
 
 // Appends every uncolored vertex (C[v] == 0) to its bin's region of the
@@ -76,6 +78,7 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
 __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_t* C, const int8_t* binv,
                                                          BinLayout L, int32_t* wl, int32_t* cnt,
                                                          int32_t* split_vertex) {
+  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
   const bool active = v < n && C[v] == 0;
   const int bin = active ? binv[v] : -1;
@@ -97,7 +100,12 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_
       }
     }
   }
+  block_release();
 }
+
+__device__ void validate_row(int32_t v, int32_t n_cols, const int32_t* rp, const int32_t* ci,
+                             const int32_t* rpT, const int32_t* ciT, int32_t n_trows, int square,
+                             int32_t* err);
 
 // Input contract (COLOR_FLAG_VALIDATE).  Rows strictly increasing, ids in
 // range, no self-loops when `square`, and every entry (v, u) mirrored as
@@ -107,8 +115,14 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(int32_t n_rows, int32_
                                                           const int32_t* ci, const int32_t* rpT,
                                                           const int32_t* ciT, int32_t n_trows, int square,
                                                           int32_t* err) {
+  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-  if (v >= n_rows) return;
+  if (v < n_rows) validate_row(v, n_cols, rp, ci, rpT, ciT, n_trows, square, err);
+}
+
+__device__ void validate_row(int32_t v, int32_t n_cols, const int32_t* rp, const int32_t* ci,
+                             const int32_t* rpT, const int32_t* ciT, int32_t n_trows, int square,
+                             int32_t* err) {
   const int32_t b = rp[v], e = rp[v + 1];
   if (b > e) {
     atomicOr(err, 1);
@@ -143,18 +157,21 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(int32_t n_rows, int32_
 }
 
 __global__ __launch_bounds__(kBlock) void check_rowptr_kernel(int32_t n, const int32_t* rp, int32_t* err) {
+  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-  if (v > n) return;
   if (v == 0 && rp[0] != 0) atomicOr(err, 1);
   if (v < n && rp[v] > rp[v + 1]) atomicOr(err, 1);
 }
 
 __global__ __launch_bounds__(kBlock) void priority_kernel(int32_t n, const int32_t* gid, uint32_t hs,
                                                           uint32_t* out) {
+  block_acquire();
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t g = gid ? static_cast<uint32_t>(gid[i]) : static_cast<uint32_t>(i);
-  out[i] = fmix32(g ^ hs);
+  if (i < n) {
+    const uint32_t g = gid ? static_cast<uint32_t>(gid[i]) : static_cast<uint32_t>(i);
+    out[i] = fmix32(g ^ hs);
+  }
+  block_release();
 }
 
 // Ghost phase 2 (Algorithm 3 with Algorithm 4 on the ghosts' fixed colors):
@@ -167,6 +184,7 @@ __global__ __launch_bounds__(kBlock) void boundary_kernel(int32_t n_owned, const
                                                           const int32_t* ghost_colors, KeySource k,
                                                           int32_t* loser, int32_t* gflag,
                                                           unsigned long long* conflicts) {
+  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
   uint32_t found = 0;
   if (v < n_owned) {
@@ -187,18 +205,22 @@ __global__ __launch_bounds__(kBlock) void boundary_kernel(int32_t n_owned, const
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) tot += __shfl_xor(tot, off, kWave);
   if (lane_id() == 0 && tot) atomicAdd(conflicts, static_cast<unsigned long long>(tot));
+  block_release();
 }
 
 __global__ __launch_bounds__(kBlock) void boundary_uncolor_kernel(int32_t n_owned, const int32_t* loser,
                                                                   int32_t* C) {
+  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
   if (v < n_owned && loser[v]) C[v] = 0;
+  block_release();
 }
 
 // Ghost colors become fixed committed colors for phase 3.
 __global__ __launch_bounds__(kBlock) void ghost_fill_kernel(int32_t n_owned, int32_t n_ghost,
                                                             const int32_t* ghost_colors, int32_t* C,
                                                             int32_t* T, int32_t* maxc) {
+  block_acquire();
   const int32_t j = blockIdx.x * kBlock + threadIdx.x;
   int32_t c = 0;
   if (j < n_ghost) {
@@ -209,10 +231,12 @@ __global__ __launch_bounds__(kBlock) void ghost_fill_kernel(int32_t n_owned, int
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) c = max(c, __shfl_xor(c, off, kWave));
   if (lane_id() == 0 && c > 0) atomicMax(maxc, c);
+  block_release();
 }
 
 // Largest value of an int32 array (wave-reduced, one atomic per wavefront).
 __global__ __launch_bounds__(kBlock) void max_i32_kernel(int32_t n, const int32_t* a, int32_t* out) {
+  block_acquire();
   int32_t x = 0;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock)
@@ -224,16 +248,20 @@ __global__ __launch_bounds__(kBlock) void max_i32_kernel(int32_t n, const int32_
 
 __global__ __launch_bounds__(kBlock) void flags_out_kernel(int32_t n, const int32_t* gflag, uint8_t* out,
                                                            unsigned long long* count) {
+  block_acquire();
   const int32_t j = blockIdx.x * kBlock + threadIdx.x;
   const bool f = j < n && gflag[j] != 0;
   if (j < n && out) out[j] = f ? 1 : 0;
   const uint64_t bal = __ballot(f);
   if (lane_id() == 0 && bal) atomicAdd(count, static_cast<unsigned long long>(__popcll(bal)));
+  block_release();
 }
 
 __global__ __launch_bounds__(kBlock) void copy_i32_kernel(int32_t n, const int32_t* src, int32_t* dst) {
+  block_acquire();
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i < n) dst[i] = src[i];
+  block_release();
 }
 
 static inline int blocks_for(int64_t n) { return static_cast<int>((n + kBlock - 1) / kBlock); }
