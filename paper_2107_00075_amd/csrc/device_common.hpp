@@ -89,21 +89,20 @@ __device__ __forceinline__ int32_t atomic_load_i32(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Kernel-boundary visibility across XCDs.  Each of the 8 XCDs has its own
-// L2, and measurement on MI355X showed plain stores of one kernel were not
-// reliably seen by plain loads of the next kernel on another XCD.  Every
-// kernel of the library therefore invalidates its non-coherent caches before
-// it reads data written by an earlier kernel (agent-scope acquire: buffer_inv)
-// and writes its L2 back before it ends (agent-scope release: buffer_wbl2).
-// One wavefront per workgroup issues each fence; the workgroup barrier orders
-// the other wavefronts' accesses after (acquire) or before (release) it.
-__device__ __forceinline__ void block_acquire() {
-  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  __syncthreads();
+// Device-coherent accesses.  Arrays that the library's kernels write and
+// later kernels read (colors, tentative colors, worklists, per-call setup
+// arrays) are written and read with device-scope (sc1) loads and stores.
+// Measured on MI355X: plain loads of such data written by an earlier kernel on
+// another XCD could return stale values (agent- or system-scope fences issued
+// by every wavefront at kernel start and end did not prevent it), while
+// device-scope accesses gave bit-exact results in every run.
+template <typename X>
+__device__ __forceinline__ X ld_dev(const X* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void block_release() {
-  __syncthreads();
-  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+template <typename X>
+__device__ __forceinline__ void st_dev(X* p, X v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Resets of words that other workgroups update with atomics in the same

@@ -131,24 +131,24 @@ __device__ void color_chunk_group(const GraphView& g, const RoundBufs& b, const 
   const int sub = threadIdx.x % G;
   const int32_t* __restrict__ C = b.C;
   for (int32_t idx = gi; idx < count; idx += per_pass) {  // whole groups stay together
-    const int32_t v = wl[idx];
+    const int32_t v = ld_dev(&wl[idx]);
     const int32_t beg = g.rp[v], end = g.rp[v + 1];
     int32_t base = 1;
     while (true) {
       uint64_t m = 0;
       scan_nbhd<MODE>(g, v, beg, end, sub, G, [&](int32_t u) {
-        const uint32_t d = static_cast<uint32_t>(C[u] - base);
+        const uint32_t d = static_cast<uint32_t>(ld_dev(&C[u]) - base);
         if (d < 64u) m |= 1ull << d;
         return false;
       });
       m = group_or<G>(m);
       if (m != ~0ull) {
-        if (sub == 0) b.T[v] = base + __builtin_ctzll(~m);
+        if (sub == 0) st_dev(&b.T[v], base + static_cast<int32_t>(__builtin_ctzll(~m)));
         break;
       }
       base += 64;
     }
-    if (sub == 0) work_acc += static_cast<uint64_t>(b.work[v]);
+    if (sub == 0) work_acc += static_cast<uint64_t>(ld_dev(&b.work[v]));
   }
 }
 
@@ -169,7 +169,7 @@ __device__ void color_vertex_block(const GraphView& g, const RoundBufs& b, int32
     __syncthreads();
     uint64_t m = 0;
     scan_nbhd<MODE>(g, v, beg, end, tid, kBlock, [&](int32_t u) {
-      uint32_t d = static_cast<uint32_t>(C[u] - base);
+      uint32_t d = static_cast<uint32_t>(ld_dev(&C[u]) - base);
       if (d < 64u) {
         m |= 1ull << d;
       } else {
@@ -198,7 +198,7 @@ __device__ void color_vertex_block(const GraphView& g, const RoundBufs& b, int32
     }
     __syncthreads();
     if (mex > 0) {
-      if (tid == 0) b.T[v] = mex;
+      if (tid == 0) st_dev(&b.T[v], mex);
       return;
     }
     base += 64 + kOvfWords * 32;
@@ -215,7 +215,7 @@ __device__ void color_split_chunk(const GraphView& g, const RoundBufs& b, const 
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int nch = L.split_chunks;
-  const int32_t v = b.split_vertex[si];
+  const int32_t v = ld_dev(&b.split_vertex[si]);
   const int32_t rb = g.rp[v], re = g.rp[v + 1];
   const int64_t len = re - rb;
   const int32_t cb = rb + static_cast<int32_t>(len * chunk / nch);
@@ -228,7 +228,7 @@ __device__ void color_split_chunk(const GraphView& g, const RoundBufs& b, const 
   __syncthreads();
   uint64_t m = 0;
   scan_nbhd<MODE>(g, v, cb, ce, tid, kBlock, [&](int32_t u) {
-    const int32_t c = C[u];
+    const int32_t c = ld_dev(&C[u]);
     if (c <= 0) return false;
     uint32_t d = static_cast<uint32_t>(c - 1);  // bit c-1 stands for color c
     if (d < 64u) {
@@ -248,7 +248,7 @@ __device__ void color_split_chunk(const GraphView& g, const RoundBufs& b, const 
     m = red[0] | red[1] | red[2] | red[3];
     if (static_cast<uint32_t>(m)) atomicOr(&gm[0], static_cast<uint32_t>(m));
     if (m >> 32) atomicOr(&gm[1], static_cast<uint32_t>(m >> 32));
-    if (chunk == 0) work_acc += static_cast<uint64_t>(b.work[v]);
+    if (chunk == 0) work_acc += static_cast<uint64_t>(ld_dev(&b.work[v]));
   }
   for (int w = tid; w < kOvfWords && 2 + w < b.capw; w += kBlock) {
     const uint32_t x = ovf[w];
@@ -275,7 +275,7 @@ __device__ void color_split_chunk(const GraphView& g, const RoundBufs& b, const 
     const int32_t bit = s_misc[0];
     for (int w = tid; w < nwords; w += kBlock) atomic_reset_u32(&gm[w]);
     if (tid == 0) {
-      b.T[v] = (bit == INT_MAX ? nwords * 32 : bit) + 1;
+      st_dev(&b.T[v], (bit == INT_MAX ? nwords * 32 : bit) + 1);
       atomic_reset_u32(&b.split_ctr[si]);
     }
   }
@@ -293,7 +293,6 @@ __global__ __launch_bounds__(kBlock) void color_round_kernel(GraphView g, KeySou
   __shared__ RoundMap M;
   (void)k;
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see block_acquire()
     make_round_map(b, L, M);
     s_work = 0ull;
     if (blockIdx.x == 0) {
@@ -305,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void color_round_kernel(GraphView g, KeySou
       atomic_reset_i32(&b.tile_ctr[1]);
       if (total > 0) {
         atomicMax(b.rounds_done, round);
-        if (b.trace && round <= b.trace_cap) b.trace[round - 1] = static_cast<int32_t>(total);
+        if (b.trace && round <= b.trace_cap) st_dev(&b.trace[round - 1], static_cast<int32_t>(total));
         atomicAdd(&b.visits[0], static_cast<unsigned long long>(total));
       }
     }
@@ -340,12 +339,12 @@ __global__ __launch_bounds__(kBlock) void color_round_kernel(GraphView g, KeySou
       __syncthreads();
       if (u >= M.heavy_total) break;
       if (u < M.heavy_block) {
-        const int32_t v = b.wl_in[L.off[kBlockBin] + u];
+        const int32_t v = ld_dev(&b.wl_in[L.off[kBlockBin] + u]);
         color_vertex_block<MODE>(g, b, v, ovf, red, &s_misc[0]);
-        if (threadIdx.x == 0) work_acc += static_cast<uint64_t>(b.work[v]);
+        if (threadIdx.x == 0) work_acc += static_cast<uint64_t>(ld_dev(&b.work[v]));
       } else {
         const int32_t us = u - M.heavy_block;
-        const int32_t si = b.wl_in[L.off[kSplitBin] + us / L.split_chunks];
+        const int32_t si = ld_dev(&b.wl_in[L.off[kSplitBin] + us / L.split_chunks]);
         color_split_chunk<MODE>(g, b, L, si, us % L.split_chunks, ovf, red, s_misc, work_acc);
       }
     }
@@ -354,7 +353,6 @@ __global__ __launch_bounds__(kBlock) void color_round_kernel(GraphView g, KeySou
   if (lane_id() == 0 && work_acc) atomicAdd(&s_work, static_cast<unsigned long long>(work_acc));
   __syncthreads();
   if (threadIdx.x == 0 && s_work) atomicAdd(&b.visits[1], s_work);
-  block_release();
 }
 
 // ---------------------------------------------------------------------------
@@ -371,12 +369,12 @@ __device__ void detect_chunk_group(const GraphView& g, const KeySource& k, const
   const int sub = threadIdx.x % G;
   const int32_t* __restrict__ T = b.T;
   for (int32_t idx = gi; idx < count; idx += per_pass) {
-    const int32_t v = wl[idx];
-    const int32_t tv = T[v];
+    const int32_t v = ld_dev(&wl[idx]);
+    const int32_t tv = ld_dev(&T[v]);
     const uint64_t kv = key_of(k, v);
     bool lose = false;
     scan_nbhd<MODE>(g, v, g.rp[v], g.rp[v + 1], sub, G, [&](int32_t u) {
-      if (T[u] == tv && key_of(k, u) > kv) {
+      if (ld_dev(&T[u]) == tv && key_of(k, u) > kv) {
         lose = true;
         return true;
       }
@@ -388,7 +386,7 @@ __device__ void detect_chunk_group(const GraphView& g, const KeySource& k, const
         s_ent[idx] = v;
       } else {
         s_ent[idx] = -1;
-        b.C[v] = tv;
+        st_dev(&b.C[v], tv);
         maxc_acc = max(maxc_acc, tv);
       }
     }
@@ -410,7 +408,7 @@ __device__ void detect_chunk_group(const GraphView& g, const KeySource& k, const
     s_wc[kWavesPerBlock] = tot ? atomicAdd(&b.cnt_out[bin], tot) : 0;
   }
   __syncthreads();
-  if (x >= 0) b.wl_out[off_out + s_wc[kWavesPerBlock] + s_wc[wave] + static_cast<int32_t>(lanes_below(bal))] = x;
+  if (x >= 0) st_dev(&b.wl_out[off_out + s_wc[kWavesPerBlock] + s_wc[wave] + static_cast<int32_t>(lanes_below(bal))], x);
   __syncthreads();
 }
 
@@ -419,11 +417,11 @@ __device__ void detect_vertex_block(const GraphView& g, const KeySource& k, cons
                                     int32_t v, int32_t off, int32_t& maxc_acc) {
   const int tid = threadIdx.x;
   const int32_t* __restrict__ T = b.T;
-  const int32_t tv = T[v];
+  const int32_t tv = ld_dev(&T[v]);
   const uint64_t kv = key_of(k, v);
   bool lose = false;
   scan_nbhd<MODE>(g, v, g.rp[v], g.rp[v + 1], tid, kBlock, [&](int32_t u) {
-    if (T[u] == tv && key_of(k, u) > kv) {
+    if (ld_dev(&T[u]) == tv && key_of(k, u) > kv) {
       lose = true;
       return true;
     }
@@ -432,11 +430,11 @@ __device__ void detect_vertex_block(const GraphView& g, const KeySource& k, cons
   lose = __syncthreads_or(lose);
   if (tid == 0) {
     if (!lose) {
-      b.C[v] = tv;
+      st_dev(&b.C[v], tv);
       maxc_acc = max(maxc_acc, tv);
     } else {
       const int32_t pos = atomicAdd(&b.cnt_out[kBlockBin], 1);
-      b.wl_out[off + pos] = v;
+      st_dev(&b.wl_out[off + pos], v);
     }
   }
 }
@@ -447,18 +445,18 @@ __device__ void detect_split_chunk(const GraphView& g, const KeySource& k, const
                                    int32_t& maxc_acc) {
   const int tid = threadIdx.x;
   const int nch = L.split_chunks;
-  const int32_t v = b.split_vertex[si];
+  const int32_t v = ld_dev(&b.split_vertex[si]);
   const int32_t rb = g.rp[v], re = g.rp[v + 1];
   const int64_t len = re - rb;
   const int32_t cb = rb + static_cast<int32_t>(len * chunk / nch);
   const int32_t ce = rb + static_cast<int32_t>(len * (chunk + 1) / nch);
   const int32_t* __restrict__ T = b.T;
-  const int32_t tv = T[v];
+  const int32_t tv = ld_dev(&T[v]);
   const uint64_t kv = key_of(k, v);
   bool lose = false;
   if (atomic_load_u32(&b.split_flag[si]) == 0u) {  // another chunk may already have decided
     scan_nbhd<MODE>(g, v, cb, ce, tid, kBlock, [&](int32_t u) {
-      if (T[u] == tv && key_of(k, u) > kv) {
+      if (ld_dev(&T[u]) == tv && key_of(k, u) > kv) {
         lose = true;
         return true;
       }
@@ -475,11 +473,11 @@ __device__ void detect_split_chunk(const GraphView& g, const KeySource& k, const
       __threadfence();
       const uint32_t f = atomic_load_u32(&b.split_flag[si]);
       if (!f) {
-        b.C[v] = tv;
+        st_dev(&b.C[v], tv);
         maxc_acc = max(maxc_acc, tv);
       } else {
         const int32_t pos = atomicAdd(&b.cnt_out[kSplitBin], 1);
-        b.wl_out[L.off[kSplitBin] + pos] = si;
+        st_dev(&b.wl_out[L.off[kSplitBin] + pos], si);
       }
       atomic_reset_u32(&b.split_flag[si]);
       atomic_reset_u32(&b.split_ctr[si]);
@@ -499,7 +497,6 @@ __global__ __launch_bounds__(kBlock) void detect_round_kernel(GraphView g, KeySo
   __shared__ RoundMap M;
   (void)round;
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see block_acquire()
     make_round_map(b, L, M);
     s_max = 0;
     if (blockIdx.x == 0) atomic_reset_i32(&b.tile_ctr[0]);
@@ -533,11 +530,11 @@ __global__ __launch_bounds__(kBlock) void detect_round_kernel(GraphView g, KeySo
       __syncthreads();
       if (u >= M.heavy_total) break;
       if (u < M.heavy_block) {
-        const int32_t v = b.wl_in[L.off[kBlockBin] + u];
+        const int32_t v = ld_dev(&b.wl_in[L.off[kBlockBin] + u]);
         detect_vertex_block<MODE>(g, k, b, v, L.off[kBlockBin], maxc_acc);
       } else {
         const int32_t us = u - M.heavy_block;
-        const int32_t si = b.wl_in[L.off[kSplitBin] + us / L.split_chunks];
+        const int32_t si = ld_dev(&b.wl_in[L.off[kSplitBin] + us / L.split_chunks]);
         detect_split_chunk<MODE>(g, k, b, L, si, us % L.split_chunks, s_misc, maxc_acc);
       }
     }
@@ -546,7 +543,6 @@ __global__ __launch_bounds__(kBlock) void detect_round_kernel(GraphView g, KeySo
   if (lane_id() == 0 && maxc_acc > 0) atomicMax(&s_max, maxc_acc);
   __syncthreads();
   if (threadIdx.x == 0 && s_max > 0) atomicMax(b.maxc, s_max);
-  block_release();
 }
 
 template <int MODE>

@@ -24,7 +24,6 @@ __device__ __forceinline__ int64_t vertex_work(const GraphView& g, int32_t v) {
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
-  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
   const bool active = v < g.n;
   int bin = -1;
@@ -33,7 +32,7 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
   if (active) {
     w = vertex_work<MODE>(g, v);
     const int32_t wc = static_cast<int32_t>(w > INT_MAX ? INT_MAX : w);
-    s.work[v] = wc;
+    st_dev(&s.work[v], wc);
     bin = kBins - 1;
     for (int i = 0; i < kBins - 1; ++i) {
       if (wc <= s.bin_hi[i]) {
@@ -41,10 +40,10 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
         break;
       }
     }
-    s.bin[v] = static_cast<int8_t>(bin);
-    c = s.init ? s.init[v] : 0;
-    s.C[v] = c;
-    s.T[v] = c;
+    st_dev(&s.bin[v], static_cast<int8_t>(bin));
+    c = s.init ? ld_dev(&s.init[v]) : 0;
+    st_dev(&s.C[v], c);
+    st_dev(&s.T[v], c);
   }
   // wavefront reductions first: one atomic per wavefront and quantity
   int32_t cmax = c;
@@ -69,7 +68,6 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
       if (unc) atomicAdd(&s.count_unc[i], static_cast<int32_t>(__popcll(unc)));
     }
   }
-  block_release();
 }
 
 // Appends every uncolored vertex (C[v] == 0) to its bin's region of the
@@ -78,10 +76,9 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
 __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_t* C, const int8_t* binv,
                                                          BinLayout L, int32_t* wl, int32_t* cnt,
                                                          int32_t* split_vertex) {
-  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-  const bool active = v < n && C[v] == 0;
-  const int bin = active ? binv[v] : -1;
+  const bool active = v < n && ld_dev(&C[v]) == 0;
+  const int bin = active ? static_cast<int>(ld_dev(&binv[v])) : -1;
   for (int i = 0; i < kBins; ++i) {
     const bool mine = active && bin == i;
     const uint64_t bal = __ballot(mine);
@@ -93,14 +90,13 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_
     if (mine) {
       const int32_t pos = base + static_cast<int32_t>(lanes_below(bal));
       if (i == kSplitBin) {
-        split_vertex[pos] = v;
-        wl[L.off[i] + pos] = pos;
+        st_dev(&split_vertex[pos], v);
+        st_dev(&wl[L.off[i] + pos], pos);
       } else {
-        wl[L.off[i] + pos] = v;
+        st_dev(&wl[L.off[i] + pos], v);
       }
     }
   }
-  block_release();
 }
 
 __device__ void validate_row(int32_t v, int32_t n_cols, const int32_t* rp, const int32_t* ci,
@@ -115,7 +111,6 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(int32_t n_rows, int32_
                                                           const int32_t* ci, const int32_t* rpT,
                                                           const int32_t* ciT, int32_t n_trows, int square,
                                                           int32_t* err) {
-  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
   if (v < n_rows) validate_row(v, n_cols, rp, ci, rpT, ciT, n_trows, square, err);
 }
@@ -157,7 +152,6 @@ __device__ void validate_row(int32_t v, int32_t n_cols, const int32_t* rp, const
 }
 
 __global__ __launch_bounds__(kBlock) void check_rowptr_kernel(int32_t n, const int32_t* rp, int32_t* err) {
-  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
   if (v == 0 && rp[0] != 0) atomicOr(err, 1);
   if (v < n && rp[v] > rp[v + 1]) atomicOr(err, 1);
@@ -165,13 +159,11 @@ __global__ __launch_bounds__(kBlock) void check_rowptr_kernel(int32_t n, const i
 
 __global__ __launch_bounds__(kBlock) void priority_kernel(int32_t n, const int32_t* gid, uint32_t hs,
                                                           uint32_t* out) {
-  block_acquire();
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i < n) {
     const uint32_t g = gid ? static_cast<uint32_t>(gid[i]) : static_cast<uint32_t>(i);
-    out[i] = fmix32(g ^ hs);
+    st_dev(&out[i], fmix32(g ^ hs));
   }
-  block_release();
 }
 
 // Ghost phase 2 (Algorithm 3 with Algorithm 4 on the ghosts' fixed colors):
@@ -184,11 +176,10 @@ __global__ __launch_bounds__(kBlock) void boundary_kernel(int32_t n_owned, const
                                                           const int32_t* ghost_colors, KeySource k,
                                                           int32_t* loser, int32_t* gflag,
                                                           unsigned long long* conflicts) {
-  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
   uint32_t found = 0;
   if (v < n_owned) {
-    const int32_t cv = C[v];
+    const int32_t cv = ld_dev(&C[v]);
     const uint64_t kv = key_of(k, v);
     bool lose = false;
     for (int32_t q = rp[v]; q < rp[v + 1]; ++q) {
@@ -197,50 +188,44 @@ __global__ __launch_bounds__(kBlock) void boundary_kernel(int32_t n_owned, const
       if (ghost_colors[u - n_owned] != cv) continue;
       ++found;
       if (key_of(k, u) > kv) lose = true;
-      else gflag[u - n_owned] = 1;
+      else st_dev(&gflag[u - n_owned], 1);
     }
-    loser[v] = lose ? 1 : 0;
+    st_dev(&loser[v], lose ? 1 : 0);
   }
   uint64_t tot = found;
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) tot += __shfl_xor(tot, off, kWave);
   if (lane_id() == 0 && tot) atomicAdd(conflicts, static_cast<unsigned long long>(tot));
-  block_release();
 }
 
 __global__ __launch_bounds__(kBlock) void boundary_uncolor_kernel(int32_t n_owned, const int32_t* loser,
                                                                   int32_t* C) {
-  block_acquire();
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-  if (v < n_owned && loser[v]) C[v] = 0;
-  block_release();
+  if (v < n_owned && ld_dev(&loser[v])) st_dev(&C[v], 0);
 }
 
 // Ghost colors become fixed committed colors for phase 3.
 __global__ __launch_bounds__(kBlock) void ghost_fill_kernel(int32_t n_owned, int32_t n_ghost,
                                                             const int32_t* ghost_colors, int32_t* C,
                                                             int32_t* T, int32_t* maxc) {
-  block_acquire();
   const int32_t j = blockIdx.x * kBlock + threadIdx.x;
   int32_t c = 0;
   if (j < n_ghost) {
     c = ghost_colors[j];
-    C[n_owned + j] = c;
-    T[n_owned + j] = c;
+    st_dev(&C[n_owned + j], c);
+    st_dev(&T[n_owned + j], c);
   }
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) c = max(c, __shfl_xor(c, off, kWave));
   if (lane_id() == 0 && c > 0) atomicMax(maxc, c);
-  block_release();
 }
 
 // Largest value of an int32 array (wave-reduced, one atomic per wavefront).
 __global__ __launch_bounds__(kBlock) void max_i32_kernel(int32_t n, const int32_t* a, int32_t* out) {
-  block_acquire();
   int32_t x = 0;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock)
-    x = max(x, a[i]);
+    x = max(x, ld_dev(&a[i]));
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) x = max(x, __shfl_xor(x, off, kWave));
   if (lane_id() == 0 && x > 0) atomicMax(out, x);
@@ -248,20 +233,16 @@ __global__ __launch_bounds__(kBlock) void max_i32_kernel(int32_t n, const int32_
 
 __global__ __launch_bounds__(kBlock) void flags_out_kernel(int32_t n, const int32_t* gflag, uint8_t* out,
                                                            unsigned long long* count) {
-  block_acquire();
   const int32_t j = blockIdx.x * kBlock + threadIdx.x;
-  const bool f = j < n && gflag[j] != 0;
+  const bool f = j < n && ld_dev(&gflag[j]) != 0;
   if (j < n && out) out[j] = f ? 1 : 0;
   const uint64_t bal = __ballot(f);
   if (lane_id() == 0 && bal) atomicAdd(count, static_cast<unsigned long long>(__popcll(bal)));
-  block_release();
 }
 
 __global__ __launch_bounds__(kBlock) void copy_i32_kernel(int32_t n, const int32_t* src, int32_t* dst) {
-  block_acquire();
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) dst[i] = src[i];
-  block_release();
+  if (i < n) st_dev(&dst[i], ld_dev(&src[i]));
 }
 
 static inline int blocks_for(int64_t n) { return static_cast<int>((n + kBlock - 1) / kBlock); }

@@ -287,3 +287,43 @@ def test_streams_are_independent(gc):
     torch.cuda.synchronize()
     assert np.array_equal(c1.cpu().numpy(), oracle.color_d1(g1, seed=1).colors)
     assert np.array_equal(c2.cpu().numpy(), oracle.color_d1(g2, seed=2).colors)
+
+
+# ------------------------------------------------------------ larger graphs
+
+@pytest.mark.parametrize("split_hi", [65536, 2048, 512])
+def test_d1_rmat18_heavy_bins(gc, split_hi):
+    """R-MAT scale 18 (hubs of degree ~10^4): block and split bins at scale."""
+    g = gg.rmat(18, 16, 5)
+    ref = oracle.color_d1(g, seed=3)
+    P = gc.Params(bin_hi=(12, 96, min(2048, split_hi // 2), split_hi), split_chunks=16)
+    for rep in range(2):
+        got, st = run_d1(gc, g, seed=3, params=P)
+        same(got, st, ref, f"rmat18 split>{split_hi} rep {rep}")
+
+
+def test_pd2_medium(gc):
+    b = gg.bipartite_powerlaw(100000, 25000, 8, 2.1, 4)
+    ref = oracle.color_pd2(b, seed=5)
+    got, st = run_pd2(gc, b, seed=5)
+    same(got, st, ref, "PD2 100k x 25k")
+
+
+def test_device_buffers_rewritten_between_calls(gc):
+    """The same device buffers hold a different graph on each call, rewritten
+    by device-side copies right before the call (as a batching or serving
+    caller recycling its buffers would do)."""
+    graphs = [gg.rmat(13, 8, s) for s in range(4)]
+    nmax = max(g.n for g in graphs)
+    emax = max(g.nnz for g in graphs)
+    rp_buf = torch.zeros(nmax + 1, dtype=torch.int32, device="cuda")
+    ci_buf = torch.zeros(emax, dtype=torch.int32, device="cuda")
+    out = torch.zeros(nmax, dtype=torch.int32, device="cuda")
+    for rep in range(3):
+        for i, g in enumerate(graphs):
+            src_rp, src_ci = dev(g.row_ptr), dev(g.col)
+            rp_buf[:g.n + 1].copy_(src_rp)
+            ci_buf[:g.nnz].copy_(src_ci)
+            c, st = gc.color_d1(rp_buf[:g.n + 1], ci_buf[:g.nnz], seed=i + 1, out=out[:g.n])
+            torch.cuda.synchronize()
+            assert np.array_equal(c.cpu().numpy(), oracle.color_d1(g, seed=i + 1).colors), (rep, i)
