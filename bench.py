@@ -134,21 +134,30 @@ def main():
     nnz_total = sum(g.nnz for _, g, *_ in graphs)
     value = nnz_total / (t_all / args.steps)
 
-    # roofline of the dominant kernel over the timed steps
-    kern = {"color_round_kernel<D1>": [0, 0, 0], "detect_round_kernel<D1>": [0, 0, 0]}
+    # roofline of the dominant kernel over the timed steps.  Pull engine: the
+    # algorithmic bytes follow from the visit counters (d1_kernel_bytes);
+    # incremental engine: its kernels count their own algorithmic bytes.
+    kern = {}
     per_graph = {}
     for s_list in stats:
         for (name, g, *_), st in zip(graphs, s_list):
-            cb, db = d1_kernel_bytes(st)
-            kern["color_round_kernel<D1>"][0] += cb
-            kern["color_round_kernel<D1>"][1] += st.color_kernel_ns
-            kern["color_round_kernel<D1>"][2] += st.color_launches
-            kern["detect_round_kernel<D1>"][0] += db
-            kern["detect_round_kernel<D1>"][1] += st.detect_kernel_ns
-            kern["detect_round_kernel<D1>"][2] += st.detect_launches
+            if st.engine == gc.ENGINE_INCREMENTAL:
+                names = ("inc_color_kernel", "inc_detect_kernel")
+                cb, db = st.color_bytes, st.detect_bytes
+            else:
+                names = ("color_round_kernel<D1>", "detect_round_kernel<D1>")
+                cb, db = d1_kernel_bytes(st)
+            for kname, byts, ns, nl in ((names[0], cb, st.color_kernel_ns, st.color_launches),
+                                        (names[1], db, st.detect_kernel_ns, st.detect_launches)):
+                acc = kern.setdefault(kname, [0, 0, 0])
+                acc[0] += byts
+                acc[1] += ns
+                acc[2] += nl
             pg = per_graph.setdefault(name, {"nnz": g.nnz, "n": g.n, "colors": st.num_colors,
                                              "rounds": st.rounds, "edge_visits": st.edge_visits,
-                                             "vertex_visits": st.vertex_visits, "kernel_ms": 0.0})
+                                             "vertex_visits": st.vertex_visits, "kernel_ms": 0.0,
+                                             "engine": {1: "pull", 2: "incremental"}.get(st.engine, "?"),
+                                             "list_visits": st.list_visits})
             pg["kernel_ms"] += (st.color_kernel_ns + st.detect_kernel_ns) / 1e6 / args.steps
     dom = max(kern, key=lambda k: kern[k][1])
     b, ns, launches = kern[dom]

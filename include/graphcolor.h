@@ -90,6 +90,12 @@ typedef struct color_stats {
     int64_t detect_kernel_ns;
     int32_t color_launches;
     int32_t detect_launches;
+    int32_t engine;              /* COLOR_ENGINE_* that ran */
+    int32_t reserved_;
+    int64_t list_visits;         /* INCREMENTAL: active-list entries scanned by the detect kernels */
+    int64_t pushes;              /* INCREMENTAL: forbidden-color bits pushed */
+    int64_t color_bytes;         /* algorithmic bytes of the color kernels (INCREMENTAL; PULL: 0) */
+    int64_t detect_bytes;        /* algorithmic bytes of the detect kernels (INCREMENTAL; PULL: 0) */
 } color_stats;
 
 /* Tuning knobs (HOST struct, nullable = library defaults / autotuned).  None
@@ -104,7 +110,19 @@ typedef struct color_params {
     int32_t tail_threshold; /* worklist size below which the tail kernel finishes the call */
     int32_t max_workgroups; /* cap on the grid of the round kernels */
     uint32_t flags;         /* COLOR_FLAG_* */
+    int32_t engine;         /* COLOR_ENGINE_*: 0 = library choice */
 } color_params;
+
+/* Engines (identical colorings).  PULL re-reads every worklist vertex's full
+ * neighbourhood in both kernels of a round.  INCREMENTAL keeps per-vertex
+ * forbidden-color bitsets that committing neighbours push into, and per-vertex
+ * active-neighbour lists compacted as neighbours commit; it needs extra
+ * device memory of about 8 bytes per list entry (D1: per adjacency entry;
+ * D2/PD2: per two-hop walk entry) and falls back to PULL when the lists do
+ * not fit int32 offsets. */
+#define COLOR_ENGINE_AUTO        0
+#define COLOR_ENGINE_PULL        1
+#define COLOR_ENGINE_INCREMENTAL 2
 
 /* Distance-1 coloring (Section 2.1; Section 3.2).
  *   n            vertices (>= 0)

@@ -14,13 +14,13 @@ import ctypes
 from ._binding import (COLOR_E2BIG, COLOR_EGRAPH, COLOR_EINVAL, COLOR_ENOCONVERGE, COLOR_EPENDING,
                        COLOR_EQUEUED, COLOR_FLAG_KERNEL_TIMING, COLOR_FLAG_NO_TAIL, COLOR_FLAG_VALIDATE,
                        COLOR_OK, EXPORTED,
-                       KIND_D1, KIND_D2, KIND_PD2, CHostJob, CJob, ColorError, CStats, Params, Stats,
+                       KIND_D1, KIND_D2, KIND_PD2, ENGINE_AUTO, ENGINE_PULL, ENGINE_INCREMENTAL, CHostJob, CJob, ColorError, CStats, Params, Stats,
                        lib, strerror)
 
 __all__ = [
     "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_priority", "color_batch",
     "ColorServer", "Params", "Stats", "ColorError", "lib", "strerror", "EXPORTED",
-    "COLOR_FLAG_VALIDATE", "COLOR_FLAG_NO_TAIL", "COLOR_FLAG_KERNEL_TIMING", "KIND_D1", "KIND_D2", "KIND_PD2",
+    "COLOR_FLAG_VALIDATE", "COLOR_FLAG_NO_TAIL", "COLOR_FLAG_KERNEL_TIMING", "ENGINE_AUTO", "ENGINE_PULL", "ENGINE_INCREMENTAL", "KIND_D1", "KIND_D2", "KIND_PD2",
 ]
 
 
@@ -76,7 +76,8 @@ def _stats(trace_cap):
 def _to_stats(st, buf) -> Stats:
     out = Stats(st.num_colors, st.rounds, st.vertex_visits, st.edge_visits, st.boundary_conflicts,
                 st.remote_losers, st.kernel_launches, st.color_kernel_ns, st.detect_kernel_ns,
-                st.color_launches, st.detect_launches)
+                st.color_launches, st.detect_launches, st.engine, st.list_visits, st.pushes,
+                st.color_bytes, st.detect_bytes)
     if buf is not None:
         out.worklist = list(buf[:min(st.rounds, len(buf))])
     return out

@@ -30,6 +30,7 @@ COLOR_FLAG_NO_TAIL = 0x2
 COLOR_FLAG_KERNEL_TIMING = 0x4
 
 KIND_D1, KIND_D2, KIND_PD2 = 1, 2, 3
+ENGINE_AUTO, ENGINE_PULL, ENGINE_INCREMENTAL = 0, 1, 2
 
 EXPORTED = [
     "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_priority",
@@ -51,14 +52,18 @@ class CStats(ctypes.Structure):
                 ("worklist_trace", ctypes.POINTER(ctypes.c_int64)), ("trace_cap", ctypes.c_int32),
                 ("kernel_launches", ctypes.c_int32), ("color_kernel_ns", ctypes.c_int64),
                 ("detect_kernel_ns", ctypes.c_int64), ("color_launches", ctypes.c_int32),
-                ("detect_launches", ctypes.c_int32)]
+                ("detect_launches", ctypes.c_int32), ("engine", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32), ("list_visits", ctypes.c_int64),
+                ("pushes", ctypes.c_int64), ("color_bytes", ctypes.c_int64),
+                ("detect_bytes", ctypes.c_int64)]
 
 
 class CParams(ctypes.Structure):
     _fields_ = [("bin_hi", ctypes.c_int32 * 4), ("lanes", ctypes.c_int32 * 3),
                 ("split_chunks", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("rounds_per_poll", ctypes.c_int32), ("tail_threshold", ctypes.c_int32),
-                ("max_workgroups", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("max_workgroups", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("engine", ctypes.c_int32)]
 
 
 class CJob(ctypes.Structure):
@@ -86,6 +91,11 @@ class Stats:
     detect_kernel_ns: int = 0
     color_launches: int = 0
     detect_launches: int = 0
+    engine: int = 0
+    list_visits: int = 0
+    pushes: int = 0
+    color_bytes: int = 0
+    detect_bytes: int = 0
     converged: bool = True
     worklist: list = field(default_factory=list)
 
@@ -101,6 +111,7 @@ class Params:
     tail_threshold: int = 0
     max_workgroups: int = 0
     flags: int = 0
+    engine: int = 0
 
     def to_c(self) -> CParams:
         p = CParams()
@@ -114,6 +125,7 @@ class Params:
         p.tail_threshold = self.tail_threshold
         p.max_workgroups = self.max_workgroups
         p.flags = self.flags
+        p.engine = self.engine
         return p
 
 

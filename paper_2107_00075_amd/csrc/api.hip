@@ -69,7 +69,8 @@ void Workspace::release() {
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
   events.clear();
   for (DevBuf* b : {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
-                    &split_flag, &split_mask, &aux0, &aux1})
+                    &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
+                    &inc_F, &inc_L0, &inc_L1, &inc_B0, &inc_B1, &scan_tmp})
     b->release();
   if (host) (void)hipHostFree(host);
   host = nullptr;
@@ -155,6 +156,8 @@ int merge_params(int mode, const color_params* user, color_params* out) {
   if (user->rounds_per_poll > 0) out->rounds_per_poll = std::min(user->rounds_per_poll, 1024);
   if (user->max_workgroups > 0) out->max_workgroups = user->max_workgroups;
   if (user->tail_threshold > 0) out->tail_threshold = user->tail_threshold;
+  if (user->engine < 0 || user->engine > COLOR_ENGINE_INCREMENTAL) return COLOR_EINVAL;
+  out->engine = user->engine;
   out->flags = user->flags;
   return COLOR_OK;
 }
@@ -237,6 +240,12 @@ int setup_bins(Call& c, const GraphView& g, const int32_t* init, int32_t* C, int
   s.count_unc = S->count_unc;
   s.maxc = &S->maxc;
   s.max_split_work = &S->max_split_work;
+  s.max_work = &S->max_work;
+  int e0;
+  if ((e0 = w->deferred.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n, 1)), false, c.st))) return e0;
+  s.deferred = w->deferred.as<int32_t>();
+  s.deferred_cnt = &S->deferred_cnt;
+  s.deferred_grab = &S->deferred_grab[0];
   s.total_work = &S->total_work;
   launch_bin<MODE>(g, s, c.st);
   c.launches += 1;
@@ -332,6 +341,12 @@ int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc) {
     stats->detect_kernel_ns = 0;
     stats->color_launches = c.color_launches;
     stats->detect_launches = c.detect_launches;
+    stats->engine = c.engine;
+    stats->reserved_ = 0;
+    stats->list_visits = static_cast<int64_t>(c.H->visits[2]);
+    stats->color_bytes = static_cast<int64_t>(c.H->visits[3]);
+    stats->detect_bytes = static_cast<int64_t>(c.H->visits[4]);
+    stats->pushes = static_cast<int64_t>(c.H->visits[5]);
     if (c.timing) {
       // event i opens a kernel of kind event_kind[i] that event i+1 closes
       for (size_t i = 0; i + 1 < c.n_events; ++i) {
@@ -381,6 +396,151 @@ static int read_nnz(Call& c, const int32_t* rp, int32_t n, int32_t* nnz) {
   return COLOR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// incremental engine driver
+// ---------------------------------------------------------------------------
+template <int MODE>
+int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32_t* init, int32_t* colors,
+                    BinLayout& L, int32_t known[kBins], int* fell_back) {
+  Workspace* w = c.ws;
+  Scalars* S = c.S;
+  Scalars* H = c.H;
+  const int32_t n = g.n;
+  int e;
+  *fell_back = 0;
+  const size_t n1 = static_cast<size_t>(n) + 1;
+  if ((e = w->inc_len.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
+  if ((e = w->inc_words.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
+  if ((e = w->inc_fwoff.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
+  if ((e = w->inc_L0.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
+  if ((e = w->inc_L1.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
+  int32_t* len = w->inc_len.as<int32_t>();
+  int32_t* words = w->inc_words.as<int32_t>();
+  if (hipMemsetAsync(len + n, 0, sizeof(int32_t), c.st) != hipSuccess) return COLOR_EHIP;
+  if (hipMemsetAsync(words + n, 0, sizeof(int32_t), c.st) != hipSuccess) return COLOR_EHIP;
+  launch_inc_sizes<MODE>(g, w->work.as<int32_t>(), len, words, w->inc_L0.as<int32_t>(), &S->list_total, c.st);
+  c.launches += 1;
+  if (hipMemcpyAsync(&H->list_total, &S->list_total, sizeof(unsigned long long), hipMemcpyDeviceToHost, c.st) !=
+      hipSuccess)
+    return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  const unsigned long long total_list = H->list_total;
+  if (total_list >= static_cast<unsigned long long>(INT_MAX)) {
+    *fell_back = 1;
+    return COLOR_OK;
+  }
+  size_t tmp_bytes = 0;
+  if (exclusive_scan_i32(words, w->inc_fwoff.as<int32_t>(), n + 1, nullptr, &tmp_bytes, c.st)) return COLOR_EHIP;
+  if ((e = w->scan_tmp.ensure(tmp_bytes, false, c.st))) return e;
+  if (exclusive_scan_i32(words, w->inc_fwoff.as<int32_t>(), n + 1, w->scan_tmp.p, &tmp_bytes, c.st))
+    return COLOR_EHIP;
+  const int32_t* aoff = g.rp;
+  if (MODE != kD1) {
+    if ((e = w->inc_aoff.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
+    size_t tb2 = 0;
+    if (exclusive_scan_i32(len, w->inc_aoff.as<int32_t>(), n + 1, nullptr, &tb2, c.st)) return COLOR_EHIP;
+    if (tb2 > tmp_bytes && (e = w->scan_tmp.ensure(tb2, false, c.st))) return e;
+    tb2 = std::max(tb2, tmp_bytes);
+    if (exclusive_scan_i32(len, w->inc_aoff.as<int32_t>(), n + 1, w->scan_tmp.p, &tb2, c.st)) return COLOR_EHIP;
+    aoff = w->inc_aoff.as<int32_t>();
+  }
+  int32_t fw_total = 0;
+  if (hipMemcpyAsync(&fw_total, w->inc_fwoff.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) !=
+      hipSuccess)
+    return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  const size_t list_entries = std::max<size_t>(1, total_list);
+  if ((e = w->inc_F.ensure(sizeof(uint32_t) * static_cast<size_t>(std::max(fw_total, 1)), false, c.st))) return e;
+  if ((e = w->inc_B0.ensure(sizeof(int32_t) * list_entries, false, c.st))) return e;
+  if ((e = w->inc_B1.ensure(sizeof(int32_t) * list_entries, false, c.st))) return e;
+  if (hipMemsetAsync(w->inc_F.p, 0, sizeof(uint32_t) * static_cast<size_t>(std::max(fw_total, 1)), c.st) !=
+      hipSuccess)
+    return COLOR_EHIP;
+  int32_t* B[2] = {w->inc_B0.as<int32_t>(), w->inc_B1.as<int32_t>()};
+  int32_t* Lb[2] = {w->inc_L0.as<int32_t>(), w->inc_L1.as<int32_t>()};
+  const int32_t* A0 = g.ci;  // D1: round 1 reads the adjacency itself
+  if (MODE != kD1) {
+    launch_inc_fill<MODE>(g, aoff, len, B[0], w->deferred.as<int32_t>(), &S->deferred_cnt, &S->deferred_grab[1],
+                          c.st);
+    c.launches += 2;
+    A0 = B[0];
+  }
+  IncBufs ib;
+  ib.C = colors;
+  ib.T = w->T.as<int32_t>();
+  ib.work = w->work.as<int32_t>();
+  ib.tile_ctr = S->tile_ctr;
+  ib.aoff = aoff;
+  ib.fw_off = w->inc_fwoff.as<int32_t>();
+  ib.F = w->inc_F.as<uint32_t>();
+  ib.maxc = &S->maxc;
+  ib.acc = S->visits;
+  ib.trace = w->trace.as<int32_t>();
+  ib.trace_cap = c.trace_cap;
+  ib.rounds_done = &S->rounds_done;
+  if (init) {
+    IncBufs pb = ib;
+    pb.alen_in = Lb[0];
+    launch_inc_init_push(pb, n, A0, c.st);
+    c.launches += 1;
+  }
+  if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
+  const int resident = std::min(resident_inc_blocks(), std::max(8, c.P.max_workgroups));
+  const int max_rounds = c.P.max_rounds;
+  int local = 0;
+  int R = std::max(1, c.P.rounds_per_poll);
+  while (true) {
+    int64_t total = 0;
+    for (int i = 0; i < kBins; ++i) total += known[i];
+    if (total == 0) break;
+    if (max_rounds > 0 && local >= max_rounds) return COLOR_ENOCONVERGE;
+    int64_t gc = std::min<int64_t>((total + kBlock - 1) / kBlock, resident);
+    if (gc >= 8) gc = gc / 8 * 8;
+    int64_t gd = std::min<int64_t>(round_units(known, L), resident);
+    if (gd >= 8) gd = gd / 8 * 8;
+    const int grid_c = static_cast<int>(std::max<int64_t>(1, gc));
+    const int grid_d = static_cast<int>(std::max<int64_t>(1, gd));
+    int n_launch = R;
+    if (max_rounds > 0) n_launch = std::min(n_launch, max_rounds - local);
+    for (int i = 0; i < n_launch; ++i) {
+      ++local;
+      IncBufs b = ib;
+      const int pin = (local - 1) & 1, pout = local & 1;
+      b.wl_in = c.wl[pin];
+      b.wl_out = c.wl[pout];
+      b.cnt_in = S->cnt[pin];
+      b.cnt_out = S->cnt[pout];
+      b.A_in = local == 1 ? A0 : B[pin];
+      b.A_out = B[pout];
+      b.alen_in = Lb[pin];
+      b.alen_out = Lb[pout];
+      if (c.timing && c.record_event(0)) return COLOR_EHIP;
+      launch_inc_color(b, L, local, grid_c, c.st);
+      if (c.timing && c.record_event(1)) return COLOR_EHIP;
+      launch_inc_detect(k, b, L, local, grid_d, c.st);
+      if (c.timing && c.record_event(-1)) return COLOR_EHIP;
+      c.launches += 2;
+      c.color_launches += 1;
+      c.detect_launches += 1;
+    }
+    if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
+    if (hipMemcpyAsync(H->cnt[local & 1], S->cnt[local & 1], sizeof(int32_t) * 8, hipMemcpyDeviceToHost, c.st) !=
+        hipSuccess)
+      return COLOR_EHIP;
+    if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+    for (int i = 0; i < kBins; ++i) known[i] = H->cnt[local & 1][i];
+    R = std::min(R * 2, 64);
+  }
+  return COLOR_OK;
+}
+
+template int run_incremental<kD1>(Call&, const GraphView&, const KeySource&, const int32_t*, int32_t*,
+                                  BinLayout&, int32_t*, int*);
+template int run_incremental<kD2>(Call&, const GraphView&, const KeySource&, const int32_t*, int32_t*,
+                                  BinLayout&, int32_t*, int*);
+template int run_incremental<kPD2>(Call&, const GraphView&, const KeySource&, const int32_t*, int32_t*,
+                                   BinLayout&, int32_t*, int*);
+
 template <int MODE>
 static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32_t* ci, const int32_t* rp2,
                        const int32_t* ci2, uint32_t seed, const uint32_t* prio, const int32_t* init,
@@ -423,7 +583,32 @@ static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32
   BinLayout L;
   RoundBufs rb;
   int32_t known[kBins];
-  if ((e = setup_bins<MODE>(c, g, init, colors, n, L, rb, known))) return e;
+  if (c.P.engine != COLOR_ENGINE_PULL) {
+    // bins without split units (the incremental engine has none; the pull
+    // engine only runs on them here for graphs without heavy vertices)
+    color_params saved = c.P;
+    c.P.bin_hi[3] = INT_MAX;
+    e = setup_bins<MODE>(c, g, init, colors, n, L, rb, known);
+    c.P = saved;
+    if (e) return e;
+    // library choice: the incremental engine pays off when the work is
+    // concentrated in a few vertices that would be rescanned every round
+    const double avg = static_cast<double>(c.H->total_work) / std::max<int64_t>(1, n);
+    const bool skewed = c.H->max_work > 64 && c.H->max_work > 16.0 * std::max(1.0, avg);
+    if (c.P.engine == COLOR_ENGINE_INCREMENTAL || skewed) {
+      int fell_back = 0;
+      const int rc = run_incremental<MODE>(c, g, k, init, colors, L, known, &fell_back);
+      if (!fell_back) {
+        if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
+        c.engine = COLOR_ENGINE_INCREMENTAL;
+        return finish_call(c, stats, -1, rc);
+      }
+      // lists too large for int32 offsets: pull on the same worklists
+    }
+  } else {
+    if ((e = setup_bins<MODE>(c, g, init, colors, n, L, rb, known))) return e;
+  }
+  c.engine = COLOR_ENGINE_PULL;
   const int rc = run_phase<MODE>(c, g, k, L, rb, known, 0, c.P.max_rounds);
   if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
   return finish_call(c, stats, -1, rc);

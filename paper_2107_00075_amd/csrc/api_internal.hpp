@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "graphcolor.h"
+#include "inc.hpp"
 #include "setup.hpp"
 
 namespace gcol {
@@ -33,7 +34,13 @@ struct Scalars {
   int32_t pad_;
   int32_t count_all[8];
   int32_t count_unc[8];
-  unsigned long long visits[2]; // sum |W_r|, sum work(W_r)
+  unsigned long long visits[8]; // [0] sum |W_r|, [1] sum work(W_r), [2] list entries, [3] color bytes,
+                                // [4] detect bytes, [5] pushes
+  unsigned long long list_total; // incremental engine: entries of all lists
+  int32_t max_work;              // largest work of an uncolored vertex
+  int32_t deferred_cnt;          // heavy D2/PD2 vertices set up by workgroups
+  int32_t deferred_grab[2];      // their work counters (work, list fill)
+  int32_t pad3_[2];
   unsigned long long total_work;
   unsigned long long conflicts; // ghost phase-2 conflicts
   unsigned long long remote;    // ghost remote losers
@@ -44,6 +51,7 @@ struct Workspace {
   int device = 0;
   std::mutex mu;
   DevBuf T, C, work, bin, wl0, wl1, small, trace, split_vertex, split_ctr, split_flag, split_mask, aux0, aux1;
+  DevBuf deferred, inc_len, inc_words, inc_fwoff, inc_aoff, inc_F, inc_L0, inc_L1, inc_B0, inc_B1, scan_tmp;
   Scalars* host = nullptr;  // pinned staging for read-backs
   std::vector<hipEvent_t> events;  // pool for COLOR_FLAG_KERNEL_TIMING
   ~Workspace();
@@ -68,6 +76,7 @@ struct Call {
   size_t n_events = 0;
   std::vector<int> event_kind;  // per event pair start index: 0 color, 1 detect
   int color_launches = 0, detect_launches = 0;
+  int engine = 1;
   int record_event(int kind_of_next);  // records the next pool event on st
 };
 
@@ -80,6 +89,9 @@ int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc);
 template <int MODE>
 int setup_bins(Call& c, const GraphView& g, const int32_t* init, int32_t* C, int32_t n_total, BinLayout& L,
                RoundBufs& rb, int32_t known[kBins]);
+template <int MODE>
+int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32_t* init, int32_t* colors,
+                    BinLayout& L, int32_t known[kBins], int* fell_back);
 template <int MODE>
 int run_phase(Call& c, const GraphView& g, const KeySource& k, const BinLayout& L, const RoundBufs& base,
               int32_t known[kBins], int round0, int max_rounds);

@@ -1,0 +1,561 @@
+// Incremental engine: the same synchronous rounds as the pull kernels
+// (rounds.hip), computed with less memory traffic.
+//
+// Two facts of the synchronous rounds make this exact:
+//  * committed colors never change, so the set of colors a worklist vertex
+//    must avoid only grows.  Each vertex keeps it as a bitset F[v] (bit c-1
+//    for color c).  A vertex that commits color c pushes bit c-1 into F of its
+//    still-uncolored neighbours during the detect kernel; the next round's
+//    color kernel reads only F[v] (T[v] = first zero bit + 1, a scan of at
+//    most maxc/32 + 1 words) instead of re-reading the adjacency.  Pushes of
+//    round r complete before round r+1 starts, so F[v] holds exactly the
+//    colors committed before the round: the snapshot the method requires.
+//  * only worklist neighbours can conflict (a committed neighbour's
+//    tentative color equals its committed one, which T[v] avoids).  Each
+//    vertex keeps an active list A(v) of neighbours that may still be
+//    uncolored; the detect kernel scans A(v) and, when v loses, compacts it
+//    to the neighbours not yet committed.  A neighbour that commits in the
+//    same round may or may not be dropped (its C is written concurrently);
+//    either way the conflict test already used its tentative color, and its
+//    commit pushes its color into F[v].
+// For distance-2 and partial distance-2 the lists are the materialized
+// two-hop neighbourhoods (Section 2.1; Section 3.5/3.6), built once per call.
+#include <algorithm>
+#include <climits>
+
+#include <hipcub/hipcub.hpp>
+
+#include "inc.hpp"
+#include "setup.hpp"
+
+namespace gcol {
+
+namespace {
+
+struct IncMap {
+  int32_t cnt[kBins];
+  int32_t chunks[3];
+  int32_t light_total;
+  int32_t heavy_total;  // one unit per bin-3/bin-4 vertex (the incremental engine has no split units)
+  int32_t total;        // all worklist entries
+};
+
+__device__ __forceinline__ void make_inc_map(const IncBufs& b, IncMap& m) {
+  int32_t lt = 0, tot = 0;
+  for (int i = 0; i < kBins; ++i) {
+    m.cnt[i] = ld_dev(&b.cnt_in[i]);
+    tot += m.cnt[i];
+  }
+  for (int i = 0; i < 3; ++i) {
+    m.chunks[i] = (m.cnt[i] + kBlock - 1) / kBlock;
+    lt += m.chunks[i];
+  }
+  m.light_total = lt;
+  m.heavy_total = m.cnt[kBlockBin] + m.cnt[kSplitBin];
+  m.total = tot;
+}
+
+__device__ __forceinline__ int32_t xcd_block() {
+  const int32_t nb = gridDim.x;
+  const int32_t per = nb / 8;
+  const int32_t i = blockIdx.x;
+  if (per == 0 || (nb & 7) != 0) return i;
+  return (i & 7) * per + (i >> 3);
+}
+
+__device__ __forceinline__ uint64_t wsum(uint64_t x) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) x += __shfl_xor(x, off, kWave);
+  return x;
+}
+
+// Sets bit c-1 of F[x] unless it is already set (read first: most pushes
+// repeat a small color that an earlier neighbour already pushed).
+__device__ __forceinline__ void push_color(const IncBufs& b, int32_t x, int32_t c, uint64_t& pushes) {
+  const int32_t w0 = ld_dev(&b.fw_off[x]);
+  const int32_t nw = ld_dev(&b.fw_off[x + 1]) - w0;
+  const int32_t w = (c - 1) >> 5;
+  if (w >= nw) return;  // beyond any color x can take: irrelevant to its first fit
+  uint32_t* p = b.F + w0 + w;
+  const uint32_t bit = 1u << ((c - 1) & 31);
+  if (!(ld_dev(p) & bit)) {
+    atomicOr(p, bit);
+    ++pushes;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// color: T[v] = first zero bit of F[v] + 1, one thread per worklist vertex
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void inc_color_kernel(IncBufs b, BinLayout L, int round) {
+  __shared__ IncMap M;
+  __shared__ unsigned long long s_acc[3];
+  if (threadIdx.x == 0) {
+    make_inc_map(b, M);
+    s_acc[0] = s_acc[1] = s_acc[2] = 0ull;
+    if (blockIdx.x == 0) {
+      for (int i = 0; i < kBins; ++i) atomic_reset_i32(&b.cnt_out[i]);
+      atomic_reset_i32(&b.tile_ctr[1]);
+      if (M.total > 0) {
+        atomicMax(b.rounds_done, round);
+        if (b.trace && round <= b.trace_cap) st_dev(&b.trace[round - 1], M.total);
+        atomicAdd(&b.acc[0], static_cast<unsigned long long>(M.total));
+      }
+    }
+  }
+  __syncthreads();
+  const int32_t mc = ld_dev(b.maxc);
+  const int32_t wmax = mc / 32 + 1;  // words that can hold a committed color
+  uint64_t work = 0, lists = 0, bytes = 0;
+  const int32_t stride = gridDim.x * kBlock;
+  for (int32_t i = xcd_block() * kBlock + threadIdx.x; i < M.total; i += stride) {
+    int bin = 0;
+    int32_t j = i;
+    while (bin < kBins - 1 && j >= M.cnt[bin]) {
+      j -= M.cnt[bin];
+      ++bin;
+    }
+    const int32_t v = ld_dev(&b.wl_in[L.off[bin] + j]);
+    const int32_t w0 = ld_dev(&b.fw_off[v]);
+    const int32_t nw = min(ld_dev(&b.fw_off[v + 1]) - w0, wmax);
+    int32_t t = 32 * nw + 1;
+    int32_t w = 0;
+    for (; w < nw; ++w) {
+      const uint32_t x = ld_dev(&b.F[w0 + w]);
+      if (x != ~0u) {
+        t = 32 * w + __builtin_ctz(~x) + 1;
+        break;
+      }
+    }
+    st_dev(&b.T[v], t);
+    work += static_cast<uint64_t>(ld_dev(&b.work[v]));
+    lists += static_cast<uint64_t>(ld_dev(&b.alen_in[v]));
+    // worklist id, two bitset offsets, the words scanned, static work, T write
+    bytes += 4 + 8 + 4 * static_cast<uint64_t>(min(w + 1, max(nw, 1))) + 4 + 4;
+  }
+  work = wsum(work);
+  lists = wsum(lists);
+  bytes = wsum(bytes);
+  if (lane_id() == 0) {
+    if (work) atomicAdd(&s_acc[0], static_cast<unsigned long long>(work));
+    if (lists) atomicAdd(&s_acc[1], static_cast<unsigned long long>(lists));
+    if (bytes) atomicAdd(&s_acc[2], static_cast<unsigned long long>(bytes));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_acc[0]) atomicAdd(&b.acc[1], s_acc[0]);
+    if (s_acc[1]) atomicAdd(&b.acc[2], s_acc[1]);
+    if (s_acc[2]) atomicAdd(&b.acc[3], s_acc[2]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// detect + commit/push or compact, group of G lanes per vertex
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int bin, const int32_t* wl,
+                                 int32_t count, int32_t off_out, int32_t* s_ent, int32_t* s_wc,
+                                 int32_t& maxc_acc, uint64_t& bytes, uint64_t& pushes) {
+  constexpr int per_pass = kBlock / G;
+  const int gi = threadIdx.x / G;
+  const int sub = threadIdx.x % G;
+  const int first = lane_id() & ~(G - 1);
+  const uint64_t gm = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  for (int32_t idx = gi; idx < count; idx += per_pass) {
+    const int32_t v = ld_dev(&wl[idx]);
+    const int32_t tv = ld_dev(&b.T[v]);
+    const uint64_t kv = key_of(k, v);
+    const int32_t base = ld_dev(&b.aoff[v]);
+    const int32_t len = ld_dev(&b.alen_in[v]);
+    const int32_t* A = b.A_in + base;
+    bool lose = false;
+    for (int32_t e = sub; e < len; e += G) {
+      const int32_t u = ld_dev(&A[e]);
+      if (ld_dev(&b.T[u]) == tv && key_of(k, u) > kv) {
+        lose = true;
+        break;
+      }
+    }
+    lose = group_any<G>(lose);
+    if (lose) {
+      // keep the neighbours that are not committed (yet)
+      int32_t kept = 0;
+      for (int32_t e0 = 0; e0 < len; e0 += G) {
+        const int32_t e = e0 + sub;
+        int32_t u = -1;
+        bool keep = false;
+        if (e < len) {
+          u = ld_dev(&A[e]);
+          keep = ld_dev(&b.C[u]) == 0;
+        }
+        const uint64_t bal = (__ballot(keep) >> first) & gm;
+        if (keep) {
+          const int32_t pos = kept + __popcll(bal & ((1ull << sub) - 1ull));
+          st_dev(&b.A_out[base + pos], u);
+        }
+        kept += __popcll(bal);
+      }
+      if (sub == 0) {
+        st_dev(&b.alen_out[v], kept);
+        s_ent[idx] = v;
+        bytes += 16 + 12ull * static_cast<uint64_t>(len) + 4;
+      }
+    } else {
+      for (int32_t e = sub; e < len; e += G) {
+        const int32_t x = ld_dev(&A[e]);
+        if (ld_dev(&b.C[x]) == 0) push_color(b, x, tv, pushes);
+      }
+      if (sub == 0) {
+        st_dev(&b.C[v], tv);
+        maxc_acc = max(maxc_acc, tv);
+        s_ent[idx] = -1;
+        bytes += 16 + 16ull * static_cast<uint64_t>(len) + 4;
+      }
+    }
+  }
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int32_t x = tid < count ? s_ent[tid] : -1;
+  const uint64_t bal = __ballot(x >= 0);
+  if (lane_id() == 0) s_wc[wave] = static_cast<int32_t>(__popcll(bal));
+  __syncthreads();
+  if (tid == 0) {
+    int32_t tot = 0;
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+      const int32_t c = s_wc[w];
+      s_wc[w] = tot;
+      tot += c;
+    }
+    s_wc[kWavesPerBlock] = tot ? atomicAdd(&b.cnt_out[bin], tot) : 0;
+  }
+  __syncthreads();
+  if (x >= 0)
+    st_dev(&b.wl_out[off_out + s_wc[kWavesPerBlock] + s_wc[wave] + static_cast<int32_t>(lanes_below(bal))], x);
+  __syncthreads();
+}
+
+// One workgroup per heavy vertex.
+__device__ void inc_detect_block(const KeySource& k, const IncBufs& b, int32_t v, int bin, int32_t off,
+                                 int32_t* s_wc, int32_t& maxc_acc, uint64_t& bytes, uint64_t& pushes) {
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int32_t tv = ld_dev(&b.T[v]);
+  const uint64_t kv = key_of(k, v);
+  const int32_t base = ld_dev(&b.aoff[v]);
+  const int32_t len = ld_dev(&b.alen_in[v]);
+  const int32_t* A = b.A_in + base;
+  bool lose = false;
+  for (int32_t e0 = 0; e0 < len; e0 += kBlock) {
+    const int32_t e = e0 + tid;
+    if (e < len) {
+      const int32_t u = ld_dev(&A[e]);
+      if (ld_dev(&b.T[u]) == tv && key_of(k, u) > kv) lose = true;
+    }
+    if (__syncthreads_or(lose)) {
+      lose = true;
+      break;
+    }
+  }
+  lose = __syncthreads_or(lose);
+  if (lose) {
+    int32_t kept = 0;
+    for (int32_t e0 = 0; e0 < len; e0 += kBlock) {
+      const int32_t e = e0 + tid;
+      int32_t u = -1;
+      bool keep = false;
+      if (e < len) {
+        u = ld_dev(&A[e]);
+        keep = ld_dev(&b.C[u]) == 0;
+      }
+      const uint64_t bal = __ballot(keep);
+      if (lane_id() == 0) s_wc[wave] = static_cast<int32_t>(__popcll(bal));
+      __syncthreads();
+      int32_t wbase = kept;
+      int32_t tot = 0;
+      for (int w = 0; w < kWavesPerBlock; ++w) {
+        if (w < wave) wbase += s_wc[w];
+        tot += s_wc[w];
+      }
+      if (keep) st_dev(&b.A_out[base + wbase + static_cast<int32_t>(lanes_below(bal))], u);
+      kept += tot;
+      __syncthreads();
+    }
+    if (tid == 0) {
+      st_dev(&b.alen_out[v], kept);
+      const int32_t pos = atomicAdd(&b.cnt_out[bin], 1);
+      st_dev(&b.wl_out[off + pos], v);
+      bytes += 16 + 12ull * static_cast<uint64_t>(len) + 8;
+    }
+  } else {
+    for (int32_t e = tid; e < len; e += kBlock) {
+      const int32_t x = ld_dev(&A[e]);
+      if (ld_dev(&b.C[x]) == 0) push_color(b, x, tv, pushes);
+    }
+    if (tid == 0) {
+      st_dev(&b.C[v], tv);
+      maxc_acc = max(maxc_acc, tv);
+      bytes += 16 + 16ull * static_cast<uint64_t>(len) + 4;
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void inc_detect_kernel(KeySource k, IncBufs b, BinLayout L, int round) {
+  __shared__ int32_t s_unit;
+  __shared__ int32_t s_max;
+  __shared__ int32_t s_ent[kBlock];
+  __shared__ int32_t s_wc[kWavesPerBlock + 1];
+  __shared__ unsigned long long s_acc[2];
+  __shared__ IncMap M;
+  (void)round;
+  if (threadIdx.x == 0) {
+    make_inc_map(b, M);
+    s_max = 0;
+    s_acc[0] = s_acc[1] = 0ull;
+  }
+  __syncthreads();
+  int32_t maxc_acc = 0;
+  uint64_t bytes = 0, pushes = 0;
+  const int32_t lb = xcd_block();
+  const int32_t c0 = static_cast<int32_t>(static_cast<int64_t>(lb) * M.light_total / gridDim.x);
+  const int32_t c1 = static_cast<int32_t>(static_cast<int64_t>(lb + 1) * M.light_total / gridDim.x);
+  for (int32_t c = c0; c < c1; ++c) {
+    int bin = 0;
+    int32_t cc = c;
+    while (bin < 2 && cc >= M.chunks[bin]) {
+      cc -= M.chunks[bin];
+      ++bin;
+    }
+    const int32_t firstc = cc * kBlock;
+    const int32_t count = min(kBlock, M.cnt[bin] - firstc);
+    const int32_t* wl = b.wl_in + L.off[bin] + firstc;
+    const int32_t oo = L.off[bin];
+    switch (L.lanes[bin]) {
+      case 1: inc_detect_chunk<1>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 2: inc_detect_chunk<2>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 4: inc_detect_chunk<4>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 8: inc_detect_chunk<8>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 16: inc_detect_chunk<16>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 32: inc_detect_chunk<32>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      default: inc_detect_chunk<64>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+    }
+  }
+  if (M.heavy_total > 0) {
+    while (true) {
+      if (threadIdx.x == 0) s_unit = atomicAdd(&b.tile_ctr[1], 1);
+      __syncthreads();
+      const int32_t u = s_unit;
+      __syncthreads();
+      if (u >= M.heavy_total) break;
+      const int bin = u < M.cnt[kBlockBin] ? kBlockBin : kSplitBin;
+      const int32_t j = bin == kBlockBin ? u : u - M.cnt[kBlockBin];
+      const int32_t v = ld_dev(&b.wl_in[L.off[bin] + j]);
+      inc_detect_block(k, b, v, bin, L.off[bin], s_wc, maxc_acc, bytes, pushes);
+    }
+  }
+  maxc_acc = [&] {
+    int32_t x = maxc_acc;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) x = max(x, __shfl_xor(x, off, kWave));
+    return x;
+  }();
+  bytes = wsum(bytes);
+  pushes = wsum(pushes);
+  if (lane_id() == 0) {
+    if (maxc_acc > 0) atomicMax(&s_max, maxc_acc);
+    if (bytes) atomicAdd(&s_acc[0], static_cast<unsigned long long>(bytes));
+    if (pushes) atomicAdd(&s_acc[1], static_cast<unsigned long long>(pushes));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_max > 0) atomicMax(b.maxc, s_max);
+    if (s_acc[0]) atomicAdd(&b.acc[4], s_acc[0]);
+    if (s_acc[1]) atomicAdd(&b.acc[5], s_acc[1]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// setup: list lengths, bitset sizes, list materialization, initial pushes
+// ---------------------------------------------------------------------------
+
+// len(v): entries of v's list.  D1: deg(v).  D2: the two-hop walk without v
+// itself, sum over u in N(v) of deg(u) = work(v) - deg(v) (v appears once in
+// each neighbour's row).  PD2: sum over the rows of column v of deg(row) - 1
+// = work(v) - (rows of v).  words(v): bitset words covering colors
+// 1..min(len, n)+1, the largest first fit v can ever take.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void inc_sizes_kernel(GraphView g, const int32_t* work, int32_t* len,
+                                                           int32_t* words, int32_t* alen0,
+                                                           unsigned long long* total) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  int64_t l = 0;
+  if (v < g.n) {
+    const int64_t d1 = g.rp[v + 1] - g.rp[v];
+    l = MODE == kD1 ? d1 : static_cast<int64_t>(ld_dev(&work[v])) - d1;
+    if (l < 0) l = 0;
+  }
+  uint64_t t = wsum(static_cast<uint64_t>(l));
+  if (lane_id() == 0 && t) atomicAdd(total, static_cast<unsigned long long>(t));
+  if (v >= g.n) return;
+  const int32_t lc = static_cast<int32_t>(l > INT_MAX ? INT_MAX : l);
+  st_dev(&len[v], lc);
+  st_dev(&alen0[v], lc);
+  st_dev(&words[v], static_cast<int32_t>(min<int64_t>(l, g.n) / 32 + 1));
+}
+
+// Materializes the two-hop list of a vertex with a short first hop (one
+// thread).  At most len(v) entries are written.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void inc_fill_kernel(GraphView g, const int32_t* aoff, const int32_t* len,
+                                                          int32_t* A) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= g.n || g.rp[v + 1] - g.rp[v] > kSetupHeavy) return;
+  int32_t o = ld_dev(&aoff[v]);
+  const int32_t end = o + ld_dev(&len[v]);
+  for (int32_t q = g.rp[v]; q < g.rp[v + 1]; ++q) {
+    const int32_t u = g.ci[q];
+    if (MODE == kD2 && o < end) st_dev(&A[o++], u);
+    for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
+      const int32_t x = g.ci2[p];
+      if (x != v && o < end) st_dev(&A[o++], x);
+    }
+  }
+}
+
+// Two-hop lists of the heavy (deferred) vertices: a workgroup per vertex;
+// each pass takes kBlock first-hop entries, scans their entry counts across
+// the workgroup and writes them in first-hop order.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void inc_fill_heavy_kernel(GraphView g, const int32_t* aoff,
+                                                                const int32_t* len, int32_t* A,
+                                                                const int32_t* deferred, const int32_t* nd_ptr,
+                                                                int32_t* grab) {
+  __shared__ int32_t s_i;
+  __shared__ int32_t s_wt[kWavesPerBlock];
+  const int32_t nd = ld_dev(nd_ptr);
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  while (true) {
+    if (tid == 0) s_i = atomicAdd(grab, 1);
+    __syncthreads();
+    const int32_t i = s_i;
+    __syncthreads();
+    if (i >= nd) break;
+    const int32_t v = ld_dev(&deferred[i]);
+    const int32_t base = ld_dev(&aoff[v]);
+    const int32_t end = base + ld_dev(&len[v]);
+    int32_t out = base;
+    for (int32_t q0 = g.rp[v]; q0 < g.rp[v + 1]; q0 += kBlock) {
+      const int32_t q = q0 + tid;
+      int32_t u = -1, cnt = 0;
+      if (q < g.rp[v + 1]) {
+        u = g.ci[q];
+        cnt = (MODE == kD2 ? 1 : 0);
+        for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) cnt += g.ci2[p] != v;
+      }
+      // inclusive scan of cnt within the wavefront, then across wavefronts
+      int32_t incl = cnt;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t y = __shfl_up(incl, off, kWave);
+        if (lane_id() >= off) incl += y;
+      }
+      if (lane_id() == kWave - 1) s_wt[wave] = incl;
+      __syncthreads();
+      int32_t wbase = 0, tot = 0;
+      for (int w = 0; w < kWavesPerBlock; ++w) {
+        if (w < wave) wbase += s_wt[w];
+        tot += s_wt[w];
+      }
+      int32_t o = out + wbase + incl - cnt;
+      if (u >= 0) {
+        if (MODE == kD2 && o < end) st_dev(&A[o++], u);
+        for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
+          const int32_t x = g.ci2[p];
+          if (x != v && o < end) st_dev(&A[o++], x);
+        }
+      }
+      out += tot;
+      __syncthreads();
+    }
+  }
+}
+
+// Committed initial colors enter the bitsets of their uncolored neighbours.
+__global__ __launch_bounds__(kBlock) void inc_init_push_kernel(IncBufs b, int32_t n, const int32_t* A0) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n) return;
+  const int32_t c = ld_dev(&b.C[v]);
+  if (c == 0) return;
+  uint64_t pushes = 0;
+  const int32_t base = ld_dev(&b.aoff[v]);
+  const int32_t len = ld_dev(&b.alen_in[v]);
+  for (int32_t e = 0; e < len; ++e) {
+    const int32_t x = ld_dev(&A0[base + e]);
+    if (ld_dev(&b.C[x]) == 0) push_color(b, x, c, pushes);
+  }
+}
+
+static inline int blocks_for(int64_t n) { return static_cast<int>((n + kBlock - 1) / kBlock); }
+
+void launch_inc_color(const IncBufs& b, const BinLayout& L, int round, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(inc_color_kernel, dim3(grid), dim3(kBlock), 0, st, b, L, round);
+}
+void launch_inc_detect(const KeySource& k, const IncBufs& b, const BinLayout& L, int round, int grid,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(inc_detect_kernel, dim3(grid), dim3(kBlock), 0, st, k, b, L, round);
+}
+template <int MODE>
+void launch_inc_sizes(const GraphView& g, const int32_t* work, int32_t* len, int32_t* words, int32_t* alen0,
+                      unsigned long long* total, hipStream_t st) {
+  if (g.n > 0)
+    hipLaunchKernelGGL(inc_sizes_kernel<MODE>, dim3(blocks_for(g.n)), dim3(kBlock), 0, st, g, work, len, words,
+                       alen0, total);
+}
+template <int MODE>
+void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A,
+                     const int32_t* deferred, const int32_t* nd, int32_t* grab, hipStream_t st) {
+  if (g.n <= 0) return;
+  hipLaunchKernelGGL(inc_fill_kernel<MODE>, dim3(blocks_for(g.n)), dim3(kBlock), 0, st, g, aoff, len, A);
+  hipLaunchKernelGGL(inc_fill_heavy_kernel<MODE>, dim3(std::min(blocks_for(g.n), 512)), dim3(kBlock), 0, st, g,
+                     aoff, len, A, deferred, nd, grab);
+}
+void launch_inc_init_push(const IncBufs& b, int32_t n, const int32_t* A0, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(inc_init_push_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, n, A0);
+}
+template void launch_inc_sizes<kD1>(const GraphView&, const int32_t*, int32_t*, int32_t*, int32_t*,
+                                    unsigned long long*, hipStream_t);
+template void launch_inc_sizes<kD2>(const GraphView&, const int32_t*, int32_t*, int32_t*, int32_t*,
+                                    unsigned long long*, hipStream_t);
+template void launch_inc_sizes<kPD2>(const GraphView&, const int32_t*, int32_t*, int32_t*, int32_t*,
+                                     unsigned long long*, hipStream_t);
+template void launch_inc_fill<kD2>(const GraphView&, const int32_t*, const int32_t*, int32_t*, const int32_t*,
+                                   const int32_t*, int32_t*, hipStream_t);
+template void launch_inc_fill<kPD2>(const GraphView&, const int32_t*, const int32_t*, int32_t*, const int32_t*,
+                                    const int32_t*, int32_t*, hipStream_t);
+
+int exclusive_scan_i32(const int32_t* in, int32_t* out, int32_t n_plus_1, void* tmp, size_t* tmp_bytes,
+                       hipStream_t st) {
+  return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, n_plus_1, st) == hipSuccess ? 0 : -1;
+}
+
+int resident_inc_blocks() {
+  static int cache = 0;
+  if (cache == 0) {
+    int dev = 0, cus = 0, a = 0, d = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, inc_color_kernel, kBlock, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, inc_detect_kernel, kBlock, 0) != hipSuccess) {
+      cache = 2048;
+    } else {
+      cache = std::max(8, (std::max(1, std::min(a, d)) * cus) / 8 * 8);
+    }
+  }
+  return cache;
+}
+
+}  // namespace gcol

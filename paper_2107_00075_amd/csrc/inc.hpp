@@ -1,0 +1,49 @@
+// Interface of the incremental engine (inc.hip).
+#pragma once
+
+#include "rounds.hpp"
+
+namespace gcol {
+
+struct IncBufs {
+  int32_t* C;                  // committed colors
+  int32_t* T;                  // tentative colors
+  const int32_t* work;         // static work per vertex (statistics)
+  const int32_t* wl_in;        // worklist W_r (bin regions, vertex ids)
+  int32_t* wl_out;             // worklist W_{r+1}
+  const int32_t* cnt_in;       // |W_r| per bin
+  int32_t* cnt_out;            // |W_{r+1}| per bin
+  int32_t* tile_ctr;           // [1]: heavy-unit counter of the detect kernel
+  const int32_t* aoff;         // list offsets (D1: row_ptr; D2/PD2: prefix of list lengths)
+  const int32_t* A_in;         // active lists of round r
+  int32_t* A_out;              // compacted active lists for round r+1
+  const int32_t* alen_in;      // list lengths of round r
+  int32_t* alen_out;           // list lengths for round r+1
+  const int32_t* fw_off;       // bitset word offsets, n+1 entries
+  uint32_t* F;                 // forbidden-color bitsets (bit c-1 = color c)
+  int32_t* maxc;               // largest committed color
+  unsigned long long* acc;     // [0] sum |W|, [1] sum work, [2] list entries, [3] color bytes,
+                               // [4] detect bytes, [5] pushes
+  int32_t* trace;
+  int32_t trace_cap;
+  int32_t* rounds_done;
+};
+
+void launch_inc_color(const IncBufs& b, const BinLayout& L, int round, int grid, hipStream_t st);
+void launch_inc_detect(const KeySource& k, const IncBufs& b, const BinLayout& L, int round, int grid,
+                       hipStream_t st);
+template <int MODE>
+void launch_inc_sizes(const GraphView& g, const int32_t* work, int32_t* len, int32_t* words, int32_t* alen0,
+                      unsigned long long* total, hipStream_t st);
+template <int MODE>
+void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A,
+                     const int32_t* deferred, const int32_t* nd, int32_t* grab, hipStream_t st);
+void launch_inc_init_push(const IncBufs& b, int32_t n, const int32_t* A0, hipStream_t st);
+int resident_inc_blocks();
+
+// Exclusive prefix sum of n+1 int32 values (the last input is 0, so out[n] is
+// the total), with temporary storage from the caller.
+int exclusive_scan_i32(const int32_t* in, int32_t* out, int32_t n_plus_1, void* tmp, size_t* tmp_bytes,
+                       hipStream_t st);
+
+}  // namespace gcol

@@ -22,15 +22,13 @@ __device__ __forceinline__ int64_t vertex_work(const GraphView& g, int32_t v) {
   return w;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
-  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-  const bool active = v < g.n;
+// Bookkeeping of one vertex once its work is known: work, bin, initial colors,
+// per-bin counts and the maxima the driver needs.  Called by whole wavefronts
+// (wavefront reductions, one atomic per wavefront and quantity).
+__device__ void account_vertex(const BinSetup& s, int32_t v, int64_t w, bool active) {
   int bin = -1;
   int32_t c = 0;
-  int64_t w = 0;
   if (active) {
-    w = vertex_work<MODE>(g, v);
     const int32_t wc = static_cast<int32_t>(w > INT_MAX ? INT_MAX : w);
     st_dev(&s.work[v], wc);
     bin = kBins - 1;
@@ -45,19 +43,21 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
     st_dev(&s.C[v], c);
     st_dev(&s.T[v], c);
   }
-  // wavefront reductions first: one atomic per wavefront and quantity
   int32_t cmax = c;
   int32_t smax = (active && bin == kSplitBin && c == 0) ? static_cast<int32_t>(w > INT_MAX ? INT_MAX : w) : 0;
+  int32_t wmax = (active && c == 0) ? static_cast<int32_t>(w > INT_MAX ? INT_MAX : w) : 0;
   uint64_t wsum = (active && c == 0) ? static_cast<uint64_t>(w) : 0ull;
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
     cmax = max(cmax, __shfl_xor(cmax, off, kWave));
     smax = max(smax, __shfl_xor(smax, off, kWave));
+    wmax = max(wmax, __shfl_xor(wmax, off, kWave));
     wsum += __shfl_xor(wsum, off, kWave);
   }
   if (lane_id() == 0) {
     if (cmax > 0) atomicMax(s.maxc, cmax);
     if (smax > 0) atomicMax(s.max_split_work, smax);
+    if (wmax > 0) atomicMax(s.max_work, wmax);
     if (wsum) atomicAdd(s.total_work, static_cast<unsigned long long>(wsum));
   }
   for (int i = 0; i < kBins; ++i) {
@@ -67,6 +67,56 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
       if (all) atomicAdd(&s.count_all[i], static_cast<int32_t>(__popcll(all)));
       if (unc) atomicAdd(&s.count_unc[i], static_cast<int32_t>(__popcll(unc)));
     }
+  }
+}
+
+// One thread per vertex.  D2/PD2 vertices whose first hop is longer than
+// kSetupHeavy entries are deferred to heavy_work_kernel (a workgroup each).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  bool active = v < g.n;
+  bool defer = false;
+  if (MODE != kD1 && active) defer = g.rp[v + 1] - g.rp[v] > kSetupHeavy;
+  const uint64_t dbal = __ballot(defer);
+  if (dbal) {
+    const int first = __builtin_ctzll(dbal);
+    int32_t base = 0;
+    if (lane_id() == first) base = atomicAdd(s.deferred_cnt, static_cast<int32_t>(__popcll(dbal)));
+    base = __shfl(base, first, kWave);
+    if (defer) st_dev(&s.deferred[base + static_cast<int32_t>(lanes_below(dbal))], v);
+  }
+  active = active && !defer;
+  const int64_t w = active ? vertex_work<MODE>(g, v) : 0;
+  account_vertex(s, v, w, active);
+}
+
+// Deferred heavy vertices: the workgroup sums the first hop's contributions.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void heavy_work_kernel(GraphView g, BinSetup s) {
+  __shared__ int32_t s_i;
+  __shared__ unsigned long long s_sum;
+  const int32_t nd = ld_dev(s.deferred_cnt);
+  while (true) {
+    if (threadIdx.x == 0) {
+      s_i = atomicAdd(s.deferred_grab, 1);
+      s_sum = 0ull;
+    }
+    __syncthreads();
+    const int32_t i = s_i;
+    if (i >= nd) break;
+    const int32_t v = ld_dev(&s.deferred[i]);
+    uint64_t w = 0;
+    for (int32_t q = g.rp[v] + threadIdx.x; q < g.rp[v + 1]; q += kBlock) {
+      const int32_t u = g.ci[q];
+      w += (MODE == kD2 ? 1 : 0) + static_cast<uint64_t>(g.rp2[u + 1] - g.rp2[u]);
+    }
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) w += __shfl_xor(w, off, kWave);
+    if (lane_id() == 0 && w) atomicAdd(&s_sum, static_cast<unsigned long long>(w));
+    __syncthreads();
+    if (threadIdx.x < kWave) account_vertex(s, v, static_cast<int64_t>(s_sum), threadIdx.x == 0);
+    __syncthreads();
   }
 }
 
@@ -249,7 +299,10 @@ static inline int blocks_for(int64_t n) { return static_cast<int>((n + kBlock - 
 
 template <int MODE>
 void launch_bin(const GraphView& g, const BinSetup& s, hipStream_t st) {
-  if (g.n > 0) hipLaunchKernelGGL(bin_kernel<MODE>, dim3(blocks_for(g.n)), dim3(kBlock), 0, st, g, s);
+  if (g.n <= 0) return;
+  hipLaunchKernelGGL(bin_kernel<MODE>, dim3(blocks_for(g.n)), dim3(kBlock), 0, st, g, s);
+  if (MODE != kD1)
+    hipLaunchKernelGGL(heavy_work_kernel<MODE>, dim3(std::min(blocks_for(g.n), 512)), dim3(kBlock), 0, st, g, s);
 }
 template void launch_bin<kD1>(const GraphView&, const BinSetup&, hipStream_t);
 template void launch_bin<kD2>(const GraphView&, const BinSetup&, hipStream_t);

@@ -5,6 +5,10 @@
 
 namespace gcol {
 
+// D2/PD2 vertices with a first hop longer than this are handled by a whole
+// workgroup in the setup kernels.
+constexpr int32_t kSetupHeavy = 1024;
+
 struct BinSetup {
   int32_t bin_hi[kBins - 1];         // work upper bound of bins 0..3
   const int32_t* init;               // nullable initial colors
@@ -16,7 +20,11 @@ struct BinSetup {
   int32_t* count_unc;                // out: uncolored vertices per bin
   int32_t* maxc;                     // out: largest initial color
   int32_t* max_split_work;           // out: largest work among uncolored split vertices
+  int32_t* max_work;                 // out: largest work among uncolored vertices
   unsigned long long* total_work;    // out: work of the initial worklist
+  int32_t* deferred;                 // out: heavy D2/PD2 vertices (workgroup setup)
+  int32_t* deferred_cnt;             // out: their number
+  int32_t* deferred_grab;            // work counter of heavy_work_kernel
 };
 
 template <int MODE>

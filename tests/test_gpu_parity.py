@@ -21,23 +21,46 @@ def gc():
     return m
 
 
+ENGINE = {"id": 0}
+
+
+@pytest.fixture(autouse=True, scope="module", params=[2, 1], ids=["incremental", "pull"])
+def engine(request):
+    """Every parity case runs on both engines (2 = incremental, 1 = pull)."""
+    ENGINE["id"] = request.param
+    yield request.param
+    ENGINE["id"] = 0
+
+
+def with_engine(gc, kw):
+    p = kw.get("params")
+    if p is None:
+        p = gc.Params()
+    p.engine = ENGINE["id"]
+    kw["params"] = p
+    return kw
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
 
 
 def run_d1(gc, g, seed=1, **kw):
+    with_engine(gc, kw)
     colors, st = gc.color_d1(dev(g.row_ptr), dev(g.col), seed=seed, trace_cap=4096, **kw)
     torch.cuda.synchronize()
     return colors.cpu().numpy(), st
 
 
 def run_d2(gc, g, seed=1, **kw):
+    with_engine(gc, kw)
     colors, st = gc.color_d2(dev(g.row_ptr), dev(g.col), seed=seed, trace_cap=4096, **kw)
     torch.cuda.synchronize()
     return colors.cpu().numpy(), st
 
 
 def run_pd2(gc, b, seed=1, **kw):
+    with_engine(gc, kw)
     colors, st = gc.color_pd2(dev(b.row_ptr), dev(b.col_idx), dev(b.col_ptr), dev(b.row_idx), seed=seed,
                               trace_cap=4096, **kw)
     torch.cuda.synchronize()
@@ -88,6 +111,7 @@ def test_d1_er_config(gc):
     ref = oracle.color_d1(g, seed=1)
     same(got, st, ref, "ER 10k")
     assert st.edge_visits == ref.edge_visits
+    assert st.engine == ENGINE["id"]
 
 
 @pytest.mark.parametrize("vi", range(len(BIN_VARIANTS)))
@@ -282,8 +306,9 @@ def test_streams_are_independent(gc):
     g2 = gg.rmat(12, 8, 2)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
-        c1, _ = gc.color_d1(dev(g1.row_ptr), dev(g1.col), seed=1, stream=s)
-    c2, _ = gc.color_d1(dev(g2.row_ptr), dev(g2.col), seed=2)
+        c1, _ = gc.color_d1(dev(g1.row_ptr), dev(g1.col), seed=1, stream=s,
+                            params=gc.Params(engine=ENGINE["id"]))
+    c2, _ = gc.color_d1(dev(g2.row_ptr), dev(g2.col), seed=2, params=gc.Params(engine=ENGINE["id"]))
     torch.cuda.synchronize()
     assert np.array_equal(c1.cpu().numpy(), oracle.color_d1(g1, seed=1).colors)
     assert np.array_equal(c2.cpu().numpy(), oracle.color_d1(g2, seed=2).colors)
@@ -324,6 +349,16 @@ def test_device_buffers_rewritten_between_calls(gc):
             src_rp, src_ci = dev(g.row_ptr), dev(g.col)
             rp_buf[:g.n + 1].copy_(src_rp)
             ci_buf[:g.nnz].copy_(src_ci)
-            c, st = gc.color_d1(rp_buf[:g.n + 1], ci_buf[:g.nnz], seed=i + 1, out=out[:g.n])
+            c, st = gc.color_d1(rp_buf[:g.n + 1], ci_buf[:g.nnz], seed=i + 1, out=out[:g.n],
+                                params=gc.Params(engine=ENGINE["id"]))
             torch.cuda.synchronize()
             assert np.array_equal(c.cpu().numpy(), oracle.color_d1(g, seed=i + 1).colors), (rep, i)
+
+
+def test_library_engine_choice(gc):
+    """The library's own choice: pull on regular meshes, incremental on skewed
+    graphs; both give the oracle's coloring."""
+    for g, want in ((gg.stencil((24, 20, 16), 27), 1), (gg.rmat(14, 16, 2), 2)):
+        colors, st = gc.color_d1(dev(g.row_ptr), dev(g.col), seed=5)
+        assert st.engine == want
+        assert np.array_equal(colors.cpu().numpy(), oracle.color_d1(g, seed=5).colors)
