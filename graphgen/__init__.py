@@ -435,3 +435,55 @@ def ghost_local_graph(g: Graph, owner: np.ndarray, part: int, layers: int,
     n_g = gid.size - n_o
     return LocalGraph(n_o, int(n_g), int(g1.size), layers, row_ptr.astype(np.int32), lcol,
                       gid.astype(np.int32), global_colors[gid[n_o:]].astype(np.int32))
+
+
+# ---------------------------------------------------------------------------
+# Stream of jobs for the batched and served forms
+# ---------------------------------------------------------------------------
+
+@dataclass
+class JobSpec:
+    """One job of a batch or served stream.  kind 1 = D1, 2 = D2, 3 = PD2
+    (graph adjacency used as a square pattern); arrival in seconds."""
+    kind: int
+    family: str
+    graph: Graph
+    pattern: Bipartite | None
+    seed: int
+    arrival: float = 0.0
+
+
+def job_stream(count: int, seed: int, n_min: int = 1_000, n_max: int = 1_000_000,
+               rate: float | None = None) -> list:
+    """count jobs.  n ~ log-uniform [n_min, n_max]; family in {ER (mean degree
+    U{8..64}), stencil (2D 5/9-point or 3D 7/27-point, side = round(n^(1/dim))),
+    R-MAT (scale = round(log2 n), edge factor U{8..16})} with equal
+    probability; kind D1/D2/PD2 with probability 0.7/0.2/0.1, D2 and PD2 only
+    over the ER and stencil families (a D2 coloring of a power-law graph needs
+    at least max-degree + 1 rounds).  rate: Poisson arrivals (jobs/s), else
+    all arrive at 0."""
+    rng = np.random.default_rng(seed)
+    jobs = []
+    t = 0.0
+    for i in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        fam = ("er", "stencil", "rmat")[int(rng.integers(0, 3))]
+        u = rng.uniform()
+        kind = 1 if u < 0.7 else (2 if u < 0.9 else 3)
+        if fam == "rmat":
+            kind = 1
+        gseed = int(rng.integers(0, 2**31 - 1))
+        if fam == "er":
+            g = erdos_renyi(n, float(rng.integers(8, 65)), gseed)
+        elif fam == "stencil":
+            pts = (5, 9, 7, 27)[int(rng.integers(0, 4))]
+            dim = 2 if pts in (5, 9) else 3
+            side = max(2, int(round(n ** (1.0 / dim))))
+            g = stencil((side,) * dim, pts)
+        else:
+            g = rmat(max(4, int(round(math.log2(n)))), int(rng.integers(8, 17)), gseed)
+        pat = square_pattern_bipartite(g) if kind == 3 else None
+        if rate:
+            t += float(rng.exponential(1.0 / rate))
+        jobs.append(JobSpec(kind, fam, g, pat, seed=i + 1, arrival=t))
+    return jobs

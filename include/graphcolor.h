@@ -64,6 +64,7 @@ extern "C" {
 #define COLOR_EHIP         -5   /* a HIP runtime call failed */
 #define COLOR_ENOCONVERGE  -6   /* params->max_rounds reached: outputs hold the partial state */
 #define COLOR_E2BIG        -7   /* server: the job can never fit the HBM budget */
+#define COLOR_EMISMATCH    -8   /* autotune: two mappings gave different colorings (a library defect) */
 #define COLOR_EQUEUED       1   /* server: job accepted, waiting for memory/slots */
 #define COLOR_EPENDING      2   /* server: job not finished yet */
 
@@ -123,6 +124,7 @@ typedef struct color_params {
 #define COLOR_ENGINE_AUTO        0
 #define COLOR_ENGINE_PULL        1
 #define COLOR_ENGINE_INCREMENTAL 2
+#define COLOR_ENGINE_BATCH       3   /* stats only: the batched persistent engine ran the job */
 
 /* Distance-1 coloring (Section 2.1; Section 3.2).
  *   n            vertices (>= 0)
@@ -215,13 +217,43 @@ typedef struct color_job {
     int32_t* colors;
 } color_job;
 
-/* Colors num_jobs independent graphs in one persistent launch whose
- * workgroups pull (job, round, phase, tile) items from a device queue; each
- * job's coloring is identical to the single-graph call of its kind.
- * jobs: HOST array of device-pointer descriptors; per_job: nullable HOST
- * array of num_jobs stats.  Returns the first error met. */
+/* Colors num_jobs independent graphs in one persistent launch (no grid-wide
+ * barrier): every job advances through its own synchronous rounds, phase by
+ * phase, and the launch's workgroups take (job, phase, chunk) units of any
+ * open phase from per-job phase words; the workgroup that completes a
+ * phase's last unit opens the job's next phase.  Each job's coloring,
+ * rounds, vertex_visits, edge_visits and num_colors equal those of the
+ * single-graph call of its kind (color_d1 / color_d2 / color_pd2 with the
+ * job's seed, prio and init_colors NULL).
+ *   jobs     HOST array of num_jobs descriptors (device pointers inside);
+ *            n <= 2^23 per job (larger graphs: the single-graph calls)
+ *   per_job  nullable HOST array of num_jobs stats (engine =
+ *            COLOR_ENGINE_BATCH, kernel_launches = 1)
+ *   params   nullable; honoured: max_rounds (capped at 32000),
+ *            max_workgroups, flags & COLOR_FLAG_VALIDATE (every job is
+ *            validated first).  Bins and lanes come from the autotuner's
+ *            per-device record for the job's kind and average degree class
+ *            (library defaults until color_autotune has run).
+ * The library allocates 16 bytes per vertex of workspace (grow-only, per
+ * device).  Returns COLOR_OK, COLOR_EINVAL, COLOR_EOVERFLOW, COLOR_EGRAPH,
+ * COLOR_ENOMEM, COLOR_EHIP or the first job's COLOR_ENOCONVERGE. */
 int color_batch(int32_t num_jobs, const color_job* jobs, color_stats* per_job,
                 const color_params* params, void* stream);
+
+/* Autotuner of the batched and served forms.  Runs `job` alone through the
+ * batched engine once per candidate mapping (lanes per vertex of bins 0..2
+ * and bin bounds scaled around the library defaults), `reps` times each
+ * (>= 1), keeps the fastest by wall time, and records it for the job's kind
+ * and average-degree class floor(log2(nnz / n)) on the current device; later
+ * color_batch calls and servers created afterwards use the record.  Every
+ * candidate's colors are compared with the first's: a difference returns
+ * COLOR_EMISMATCH (no mapping may change a coloring).  best (nullable, HOST)
+ * receives the chosen bin_hi[0..2] and lanes.  Returns COLOR_OK, COLOR_EINVAL,
+ * COLOR_EOVERFLOW, COLOR_ENOMEM, COLOR_EHIP or COLOR_EMISMATCH. */
+int color_autotune(const color_job* job, int32_t reps, color_params* best, void* stream);
+
+/* Forgets every autotuner record of the current device. */
+int color_autotune_reset(void);
 
 /* ----------------------------------------------------------------------- */
 /* Served form: continuous batching with HBM-footprint admission.          */

@@ -11,16 +11,17 @@ from __future__ import annotations
 
 import ctypes
 
-from ._binding import (COLOR_E2BIG, COLOR_EGRAPH, COLOR_EINVAL, COLOR_ENOCONVERGE, COLOR_EPENDING,
-                       COLOR_EQUEUED, COLOR_FLAG_KERNEL_TIMING, COLOR_FLAG_NO_TAIL, COLOR_FLAG_VALIDATE,
-                       COLOR_OK, EXPORTED,
-                       KIND_D1, KIND_D2, KIND_PD2, ENGINE_AUTO, ENGINE_PULL, ENGINE_INCREMENTAL, CHostJob, CJob, ColorError, CStats, Params, Stats,
-                       lib, strerror)
+from ._binding import (COLOR_E2BIG, COLOR_EGRAPH, COLOR_EINVAL, COLOR_EMISMATCH, COLOR_ENOCONVERGE,
+                       COLOR_EPENDING, COLOR_EQUEUED, COLOR_FLAG_KERNEL_TIMING, COLOR_FLAG_NO_TAIL,
+                       COLOR_FLAG_VALIDATE, COLOR_OK, ENGINE_AUTO, ENGINE_BATCH, ENGINE_INCREMENTAL, ENGINE_PULL,
+                       EXPORTED, KIND_D1, KIND_D2, KIND_PD2, CHostJob, CJob, ColorError, CParams, CStats, Params,
+                       Stats, lib, strerror)
 
 __all__ = [
     "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_priority", "color_batch",
-    "ColorServer", "Params", "Stats", "ColorError", "lib", "strerror", "EXPORTED",
-    "COLOR_FLAG_VALIDATE", "COLOR_FLAG_NO_TAIL", "COLOR_FLAG_KERNEL_TIMING", "ENGINE_AUTO", "ENGINE_PULL", "ENGINE_INCREMENTAL", "KIND_D1", "KIND_D2", "KIND_PD2",
+    "color_autotune", "color_autotune_reset", "ColorServer", "Params", "Stats", "ColorError", "lib",
+    "strerror", "EXPORTED", "COLOR_FLAG_VALIDATE", "COLOR_FLAG_NO_TAIL", "COLOR_FLAG_KERNEL_TIMING",
+    "ENGINE_AUTO", "ENGINE_PULL", "ENGINE_INCREMENTAL", "ENGINE_BATCH", "KIND_D1", "KIND_D2", "KIND_PD2",
 ]
 
 
@@ -191,10 +192,7 @@ def color_priority(n, seed=1, gid=None, device="cuda", stream=None):
     return out[:n]
 
 
-def color_batch(jobs, params=None, stream=None):
-    """Colors many graphs in one persistent launch.  jobs: list of dicts with
-    kind (KIND_*), and device tensors row_ptr, col_idx (+ col_ptr, row_idx for
-    PD2), seed.  Returns (list of color tensors, list of Stats)."""
+def _job_structs(jobs):
     torch = _torch()
     n_jobs = len(jobs)
     arr = (CJob * max(n_jobs, 1))()
@@ -208,7 +206,9 @@ def color_batch(jobs, params=None, stream=None):
         else:
             n = j["row_ptr"].numel() - 1
             n_rows = n
-        o = torch.empty(max(n, 1), dtype=i32, device=j["row_ptr"].device)
+        o = j.get("out")
+        if o is None:
+            o = torch.empty(max(n, 1), dtype=i32, device=j["row_ptr"].device)
         outs.append(o[:n])
         arr[i].kind = kind
         arr[i].n = n
@@ -218,11 +218,35 @@ def color_batch(jobs, params=None, stream=None):
         arr[i].col_idx = _dev_ptr(j["col_idx"], "col_idx", i32)
         arr[i].col_ptr = _dev_ptr(j.get("col_ptr"), "col_ptr", i32)
         arr[i].row_idx = _dev_ptr(j.get("row_idx"), "row_idx", i32)
-        arr[i].colors = ctypes.c_void_p(o.data_ptr())
+        arr[i].colors = _dev_ptr(o, "colors", i32)
+    return arr, outs
+
+
+def color_batch(jobs, params=None, stream=None):
+    """Colors many graphs in one persistent launch.  jobs: list of dicts with
+    kind (KIND_*), and device tensors row_ptr, col_idx (+ col_ptr, row_idx for
+    PD2), seed, optional out.  Returns (list of color tensors, list of Stats)."""
+    n_jobs = len(jobs)
+    arr, outs = _job_structs(jobs)
     stats = (CStats * max(n_jobs, 1))()
     rc = lib().color_batch(n_jobs, arr, stats, _params(params), _stream(stream))
     _check(rc, "color_batch")
     return outs, [_to_stats(stats[i], None) for i in range(n_jobs)]
+
+
+def color_autotune(job, reps=2, stream=None):
+    """Times candidate mappings of `job` (a color_batch job dict) in the
+    batched engine and records the fastest for its kind and degree class.
+    Returns the chosen Params (bin_hi, lanes)."""
+    arr, _ = _job_structs([job])
+    best = CParams()
+    rc = lib().color_autotune(arr, int(reps), ctypes.byref(best), _stream(stream))
+    _check(rc, "color_autotune")
+    return Params(bin_hi=tuple(best.bin_hi), lanes=tuple(best.lanes))
+
+
+def color_autotune_reset():
+    _check(lib().color_autotune_reset(), "color_autotune_reset")
 
 
 class ColorServer:

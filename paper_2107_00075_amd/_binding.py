@@ -22,6 +22,7 @@ COLOR_ENOMEM = -4
 COLOR_EHIP = -5
 COLOR_ENOCONVERGE = -6
 COLOR_E2BIG = -7
+COLOR_EMISMATCH = -8
 COLOR_EQUEUED = 1
 COLOR_EPENDING = 2
 
@@ -30,12 +31,13 @@ COLOR_FLAG_NO_TAIL = 0x2
 COLOR_FLAG_KERNEL_TIMING = 0x4
 
 KIND_D1, KIND_D2, KIND_PD2 = 1, 2, 3
-ENGINE_AUTO, ENGINE_PULL, ENGINE_INCREMENTAL = 0, 1, 2
+ENGINE_AUTO, ENGINE_PULL, ENGINE_INCREMENTAL, ENGINE_BATCH = 0, 1, 2, 3
 
 EXPORTED = [
     "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_priority",
     "color_batch", "color_server_create", "color_server_submit", "color_server_poll",
     "color_server_drain", "color_server_destroy", "color_release_workspace", "color_strerror",
+    "color_autotune", "color_autotune_reset",
 ]
 
 
@@ -165,6 +167,10 @@ def lib():
         l.color_server_drain.argtypes = [P]
         l.color_server_destroy.restype = ctypes.c_int
         l.color_server_destroy.argtypes = [P]
+        l.color_autotune.restype = ctypes.c_int
+        l.color_autotune.argtypes = [ctypes.POINTER(CJob), I32, PP, P]
+        l.color_autotune_reset.restype = ctypes.c_int
+        l.color_autotune_reset.argtypes = []
         l.color_release_workspace.restype = ctypes.c_int
         l.color_release_workspace.argtypes = []
         l.color_strerror.restype = ctypes.c_char_p

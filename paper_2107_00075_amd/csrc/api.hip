@@ -14,6 +14,7 @@
 #include <mutex>
 
 #include "api_internal.hpp"
+#include "batch.hpp"
 
 namespace gcol {
 
@@ -541,6 +542,40 @@ template int run_incremental<kD2>(Call&, const GraphView&, const KeySource&, con
 template int run_incremental<kPD2>(Call&, const GraphView&, const KeySource&, const int32_t*, int32_t*,
                                    BinLayout&, int32_t*, int*);
 
+// The input contract (COLOR_FLAG_VALIDATE), checked on the device: row
+// offsets, ranges, self-loops, duplicates and symmetry (D1/D2), or that the
+// CSC is the transpose of the CSR (PD2).  hop 1 = (rp, ci), hop 2 = (rp2, ci2).
+template <int MODE>
+static int validate_graph(Call& c, int32_t n, int32_t n_rows, const int32_t* rp, const int32_t* ci,
+                          const int32_t* rp2, const int32_t* ci2) {
+  int e;
+  int32_t nnz = 0;
+  if ((e = read_nnz(c, rp, n, &nnz))) return e;
+  if (nnz < 0) return COLOR_EGRAPH;
+  if (MODE == kPD2) {
+    int32_t nnz2 = 0;
+    if ((e = read_nnz(c, rp2, n_rows, &nnz2))) return e;
+    if (nnz2 != nnz) return COLOR_EGRAPH;
+    // CSC (column -> rows) against CSR (row -> columns), both directions
+    if ((e = check_rowptr_graph(c, n, n_rows, rp, ci, rp2, ci2, 0))) return e;
+    if ((e = check_rowptr_graph(c, n_rows, n, rp2, ci2, rp, ci, 0))) return e;
+  } else {
+    if ((e = check_rowptr_graph(c, n, n, rp, ci, rp, ci, 1))) return e;
+  }
+  return COLOR_OK;
+}
+
+int validate_job(const color_job& j, void* stream) {
+  if (j.n == 0) return COLOR_OK;
+  Call c;
+  int e = begin_call(c, j.kind, nullptr, nullptr, stream, 1, 1);
+  if (e) return e;
+  std::unique_lock<std::mutex> lk(c.ws->mu);
+  if (j.kind == COLOR_KIND_D1) return validate_graph<kD1>(c, j.n, j.n, j.row_ptr, j.col_idx, j.row_ptr, j.col_idx);
+  if (j.kind == COLOR_KIND_D2) return validate_graph<kD2>(c, j.n, j.n, j.row_ptr, j.col_idx, j.row_ptr, j.col_idx);
+  return validate_graph<kPD2>(c, j.n, j.n_rows, j.col_ptr, j.row_idx, j.row_ptr, j.col_idx);
+}
+
 template <int MODE>
 static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32_t* ci, const int32_t* rp2,
                        const int32_t* ci2, uint32_t seed, const uint32_t* prio, const int32_t* init,
@@ -555,24 +590,7 @@ static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32
   std::unique_lock<std::mutex> lk(c.ws->mu);
   if (n == 0) return finish_call(c, stats, 0, COLOR_OK);
   if (c.P.flags & COLOR_FLAG_VALIDATE) {
-    int32_t nnz = 0;
-    if ((e = read_nnz(c, rp, n, &nnz))) return e;
-    if (nnz < 0) return COLOR_EGRAPH;
-    if (MODE == kPD2) {
-      int32_t nnz2 = 0;
-      if ((e = read_nnz(c, rp2, n_rows, &nnz2))) return e;
-      if (nnz2 != nnz) return COLOR_EGRAPH;
-      // CSC (column -> rows) against CSR (row -> columns), both directions
-      if ((e = check_rowptr_graph(c, n, n_rows, rp, ci, rp2, ci2, 0))) return e;
-      if ((e = check_rowptr_graph(c, n_rows, n, rp2, ci2, rp, ci, 0))) return e;
-    } else {
-      if ((e = check_rowptr_graph(c, n, n, rp, ci, rp, ci, 1))) return e;
-    }
-    if (init) {
-      // init colors must be a proper partial coloring: validated on the host
-      // side is too costly for large graphs; the device check below covers
-      // the D1 case, the D2/PD2 cases rely on the caller.
-    }
+    if ((e = validate_graph<MODE>(c, n, n_rows, rp, ci, rp2, ci2))) return e;
   }
   GraphView g{n, n, rp, ci, MODE == kD1 ? rp : rp2, MODE == kD1 ? ci : ci2};
   if (MODE == kD2) {
@@ -729,6 +747,7 @@ int color_priority(int32_t n, const int32_t* gid, uint32_t seed, uint32_t* out, 
 }
 
 int color_release_workspace(void) {
+  release_batch_workspaces();
   std::lock_guard<std::mutex> lk(g_ws_mu);
   for (auto& kv : g_ws) {
     std::lock_guard<std::mutex> lk2(kv.second->mu);
@@ -750,6 +769,7 @@ const char* color_strerror(int code) {
     case COLOR_EHIP: return "HIP runtime error";
     case COLOR_ENOCONVERGE: return "round limit reached (partial coloring returned)";
     case COLOR_E2BIG: return "job exceeds the server's memory budget";
+    case COLOR_EMISMATCH: return "two work mappings gave different colorings";
     case COLOR_EQUEUED: return "job queued";
     case COLOR_EPENDING: return "job pending";
     default: return "unknown error";

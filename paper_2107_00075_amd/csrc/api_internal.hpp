@@ -81,6 +81,7 @@ struct Call {
 };
 
 void default_params(int mode, color_params* p);
+int validate_job(const color_job& j, void* stream);
 int merge_params(int mode, const color_params* user, color_params* out);
 int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, void* stream, int32_t n,
                int32_t n_total);

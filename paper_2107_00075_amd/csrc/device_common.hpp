@@ -54,6 +54,15 @@ __device__ __forceinline__ uint64_t key_of(const KeySource& k, int32_t v) {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs; this renumbering
+// gives every XCD a contiguous range of logical ids (grids that are a
+// multiple of 8), so each XCD's L2 sees a contiguous range of the work.
+__device__ __forceinline__ int32_t xcd_logical_block_of(int32_t nb, int32_t i) {
+  const int32_t per = nb / 8;
+  if (per == 0 || (nb & 7) != 0) return i;
+  return (i & 7) * per + (i >> 3);
+}
+
 // Number of set bits of `mask` in lanes below the calling lane.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),

@@ -384,7 +384,8 @@ __global__ __launch_bounds__(kBlock) void inc_detect_kernel(KeySource k, IncBufs
 // len(v): entries of v's list.  D1: deg(v).  D2: the two-hop walk without v
 // itself, sum over u in N(v) of deg(u) = work(v) - deg(v) (v appears once in
 // each neighbour's row).  PD2: sum over the rows of column v of deg(row) - 1
-// = work(v) - (rows of v).  words(v): bitset words covering colors
+// = work(v) - 2 (rows of v), work counting each row entry and the row's
+// columns.  words(v): bitset words covering colors
 // 1..min(len, n)+1, the largest first fit v can ever take.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void inc_sizes_kernel(GraphView g, const int32_t* work, int32_t* len,
@@ -394,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void inc_sizes_kernel(GraphView g, const in
   int64_t l = 0;
   if (v < g.n) {
     const int64_t d1 = g.rp[v + 1] - g.rp[v];
-    l = MODE == kD1 ? d1 : static_cast<int64_t>(ld_dev(&work[v])) - d1;
+    l = MODE == kD1 ? d1 : static_cast<int64_t>(ld_dev(&work[v])) - (MODE == kPD2 ? 2 : 1) * d1;
     if (l < 0) l = 0;
   }
   uint64_t t = wsum(static_cast<uint64_t>(l));

@@ -9,7 +9,8 @@
 namespace gcol {
 
 // Adjacency entries one visit of v reads: D1 deg(v); D2 sum over u in N(v)
-// of 1 + deg(u); PD2 sum over the rows r of column v of deg(r).
+// of 1 + deg(u); PD2 sum over the rows r of column v of 1 + deg(r) (the
+// row entry of the CSC, then the row's columns in the CSR).
 template <int MODE>
 __device__ __forceinline__ int64_t vertex_work(const GraphView& g, int32_t v) {
   const int32_t b = g.rp[v], e = g.rp[v + 1];
@@ -17,7 +18,7 @@ __device__ __forceinline__ int64_t vertex_work(const GraphView& g, int32_t v) {
   int64_t w = 0;
   for (int32_t q = b; q < e; ++q) {
     const int32_t u = g.ci[q];
-    w += (MODE == kD2 ? 1 : 0) + (g.rp2[u + 1] - g.rp2[u]);
+    w += 1 + (g.rp2[u + 1] - g.rp2[u]);
   }
   return w;
 }
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void heavy_work_kernel(GraphView g, BinSetu
     uint64_t w = 0;
     for (int32_t q = g.rp[v] + threadIdx.x; q < g.rp[v + 1]; q += kBlock) {
       const int32_t u = g.ci[q];
-      w += (MODE == kD2 ? 1 : 0) + static_cast<uint64_t>(g.rp2[u + 1] - g.rp2[u]);
+      w += 1 + static_cast<uint64_t>(g.rp2[u + 1] - g.rp2[u]);
     }
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) w += __shfl_xor(w, off, kWave);

@@ -60,3 +60,38 @@ def test_bad_arguments_rejected_on_host(lib):
     assert lib.color_d1_ghost(4, 2, 1, 5, None, None, None, None, 1, None, None, None, None, None) == b.COLOR_EINVAL
     assert lib.color_priority(-1, None, 1, None, None) == b.COLOR_EINVAL
     assert lib.color_batch(-1, None, None, None, None) == b.COLOR_EINVAL
+
+
+def test_batch_and_server_arguments_rejected_on_host(lib):
+    from paper_2107_00075_amd import _binding as b
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the checks come first
+    jobs = (b.CJob * 2)()
+    for j in jobs:
+        j.kind, j.n, j.n_rows, j.seed = 1, 10, 10, 1
+        j.row_ptr = j.col_idx = j.colors = fake
+    jobs[1].kind = 7
+    assert lib.color_batch(2, jobs, None, None, None) == b.COLOR_EINVAL
+    jobs[1].kind = 1
+    jobs[1].n = (1 << 23) + 1
+    assert lib.color_batch(2, jobs, None, None, None) == b.COLOR_EOVERFLOW
+    jobs[1].n = 5
+    jobs[1].colors = None
+    assert lib.color_batch(2, jobs, None, None, None) == b.COLOR_EINVAL
+    jobs[1].colors = fake
+    jobs[1].kind = 3  # PD2 without the CSC arrays
+    assert lib.color_batch(2, jobs, None, None, None) == b.COLOR_EINVAL
+    assert lib.color_batch(-1, jobs, None, None, None) == b.COLOR_EINVAL
+    assert lib.color_batch(0, None, None, None, None) == b.COLOR_OK
+    assert lib.color_autotune(None, 1, None, None) == b.COLOR_EINVAL
+    jobs[0].n = 0
+    assert lib.color_autotune(jobs, 1, None, None) == b.COLOR_EINVAL
+    err = ctypes.c_int(0)
+    assert not lib.color_server_create(0, 4, ctypes.byref(err))
+    assert err.value == b.COLOR_EINVAL
+    assert not lib.color_server_create(1 << 20, 0, ctypes.byref(err))
+    assert err.value == b.COLOR_EINVAL
+    assert lib.color_server_submit(None, None, None) == b.COLOR_EINVAL
+    assert lib.color_server_poll(None, 1, None, None) == b.COLOR_EINVAL
+    assert lib.color_server_drain(None) == b.COLOR_EINVAL
+    assert lib.color_server_destroy(None) == b.COLOR_OK
+    assert lib.color_strerror(b.COLOR_EMISMATCH)

@@ -75,6 +75,7 @@ def same(got, st, ref, what=""):
     assert st.rounds == ref.rounds, f"{what}: rounds {st.rounds} vs {ref.rounds}"
     assert st.worklist == ref.worklist[:len(st.worklist)], what
     assert st.vertex_visits == ref.vertex_visits, what
+    assert st.edge_visits == ref.edge_visits, f"{what}: edge visits {st.edge_visits} vs {ref.edge_visits}"
     assert st.num_colors == ref.num_colors, what
 
 
