@@ -1,22 +1,40 @@
 #!/usr/bin/env python3
 """Benchmark: speculative graph coloring on one MI355X.
 
-A step colors the distance-1 workload of the paper's on-node hot path once:
-the 3D 27-point stencil mesh 128^3 (2,097,152 vertices, 53,645,816 directed
-edges; a PDE mesh like the paper's hexahedral and SuiteSparse PDE graphs) and
-the R-MAT scale-22 edge-factor-16 graph (a power-law graph like the paper's
-kron_g500 and social networks), each with color_d1 through the C-ABI.
-Inputs are generated (seeded), uploaded and resident in HBM before timing.
+Default workload (d1): a step colors the distance-1 workload of the paper's
+on-node hot path once: the 3D 27-point stencil mesh 128^3 (2,097,152
+vertices, 53,645,816 directed edges; a PDE mesh like the paper's hexahedral
+and SuiteSparse PDE graphs) and the R-MAT scale-22 edge-factor-16 graph (a
+power-law graph like the paper's kron_g500 and social networks), each with
+color_d1 through the C-ABI.  Inputs are generated (seeded), uploaded and
+resident in HBM before timing.
 
-value  = (nnz_mesh + nnz_rmat) / seconds per step   [edges colored / s]
-roofline: the dominant round kernel's algorithmic bytes / its HIP-event time.
-cpu_baseline: the CPU oracle on a bounded sample of the same workload.
+    value  = (nnz_mesh + nnz_rmat) / seconds per step   [edges colored / s]
+    roofline: the dominant kernel's algorithmic bytes / its HIP-event time;
+              traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE and
+              WRITE_SIZE runs (profiles/pmc_traffic.json, taken on the same
+              library sources, scaled by a plain copy's counters), else null.
+    cpu_baseline: the CPU oracle on a bounded sample of the same workload.
+
+Other workloads (one JSON line each, same keys):
+    --workload batch   a seeded stream of mixed D1/D2/PD2 jobs: color_batch
+                       (one persistent launch) against one single-graph call
+                       per job; value = graphs/s of the batched form
+    --workload serve   the same stream through the continuous-batching
+                       server with Poisson arrivals; reports p50/p99 latency
+
+Profiling helpers (no GPU):
+    --summarize-pmc FETCH_DIR WRITE_DIR   turns two rocprofv3 --pmc runs
+                       (FETCH_SIZE, WRITE_SIZE) of `bench.py --copy-calibration`
+                       into profiles/pmc_traffic.json
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import json
 import os
 import sys
@@ -26,6 +44,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+COPY_BYTES = 1 << 30    # the calibration copy: 1 GiB read + 1 GiB written
 
 
 def log(*a):
@@ -33,24 +53,14 @@ def log(*a):
 
 
 def d1_kernel_bytes(st):
-    """Algorithmic bytes of the D1 color kernel and of the detect kernel over a
-    call.  Per worklist vertex: worklist id, two row offsets, the static work
-    value / T[v], and one 4-byte write (T[v], or C[v] / the next worklist
-    slot); per adjacency entry: the neighbour id and the neighbour's color."""
+    """Algorithmic bytes of the pull engine's D1 color kernel and detect kernel
+    over a call.  Per worklist vertex: worklist id, two row offsets, the
+    static work value / T[v], and one 4-byte write (T[v], or C[v] / the next
+    worklist slot); per adjacency entry: the neighbour id and the neighbour's
+    color."""
     color = 20 * st.vertex_visits + 8 * st.edge_visits
     detect = 20 * st.vertex_visits + 8 * st.edge_visits
     return color, detect
-
-
-def d2_kernel_bytes(st, two_hop_frac):
-    """D2/PD2: per worklist vertex 20 bytes; per hop-1 entry its id and the
-    two row offsets of the hop-2 list (12 bytes, plus the color for D2); per
-    hop-2 entry its id and color (8 bytes).  edge_visits counts hop-1 (D2
-    only) plus hop-2 entries; two_hop_frac is the hop-2 share."""
-    e2 = st.edge_visits * two_hop_frac
-    e1 = st.edge_visits - e2
-    b = 20 * st.vertex_visits + 16 * e1 + 8 * e2
-    return b, b
 
 
 def make_d1_workload():
@@ -79,34 +89,42 @@ def cpu_baseline(sample):
     return tot_e / tot_t, tot_t
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="d1", choices=["d1"])
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design, not an implementation)", file=sys.stderr)
-        sys.exit(2)
+def load_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the current library sources."""
+    try:
+        from paper_2107_00075_amd.build import source_hash
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        if t.get("source_hash") != source_hash():
+            return None
+        k = t["kernels"].get(kernel)
+        return None if k is None else int(k["hbm_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
 
-    import numpy as np
-    import torch
 
-    import paper_2107_00075_amd as gc
+def copy_calibration(torch, dev):
+    """One plain device copy of COPY_BYTES (its counters scale FETCH_SIZE and
+    WRITE_SIZE to bytes)."""
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
-    if not torch.cuda.is_available():
-        print("bench.py: no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    dev = torch.device("cuda:0")
+
+def bench_d1(args, torch, gc, dev):
     work = make_d1_workload()
     graphs = []
     for name, g in work:
         graphs.append((name, g, torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev),
                        torch.empty(g.n, dtype=torch.int32, device=dev)))
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
     params = gc.Params(flags=gc.COLOR_FLAG_KERNEL_TIMING)
 
     def step():
@@ -162,12 +180,13 @@ def main():
     dom = max(kern, key=lambda k: kern[k][1])
     b, ns, launches = kern[dom]
     achieved = b / ns if ns else 0.0   # bytes per ns == GB/s
+    traffic = load_traffic(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "avg_launch_us": round(ns / max(launches, 1) / 1e3, 3),
-                "alg_bytes_per_launch": int(b / max(launches, 1))}
+                "alg_bytes_per_launch": int(b / max(launches, 1)),
+                "launches_per_step": launches // max(args.steps, 1)}
     for name, pg in per_graph.items():
-        run_s = sum(per_step) / args.steps
         pg["edges_per_s_kernels_only"] = round(pg["nnz"] / (pg["kernel_ms"] / 1e3), 1) if pg["kernel_ms"] else None
 
     cpu = None
@@ -179,7 +198,7 @@ def main():
                "sample": f"27-pt stencil 128^3 (full) + R-MAT scale 19 ef16 (1/8 of the R-MAT leg), "
                          f"single-threaded C oracle, {secs:.1f}s"}
 
-    out = {
+    return {
         "metric": "edges colored/s (D1)",
         "value": round(value, 1),
         "unit": "edges/s",
@@ -198,6 +217,274 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+
+
+# ---------------------------------------------------------------------------
+# batched and served forms
+# ---------------------------------------------------------------------------
+
+def _stream(args):
+    import graphgen as gg
+    t = time.time()
+    specs = gg.job_stream(args.jobs, seed=args.stream_seed, n_min=1_000, n_max=args.n_max)
+    kinds = [s.kind for s in specs]
+    log(f"[bench] {len(specs)} jobs (D1 {kinds.count(1)}, D2 {kinds.count(2)}, PD2 {kinds.count(3)}), "
+        f"sum n {sum(s.graph.n for s in specs)}, sum nnz {sum(s.graph.nnz for s in specs)} "
+        f"({time.time() - t:.1f}s)")
+    return specs
+
+
+def _nnz_of(s):
+    return s.pattern.nnz if s.kind == 3 else s.graph.nnz
+
+
+def bench_batch(args, torch, gc, dev):
+    specs = _stream(args)
+
+    def d(a):
+        return torch.from_numpy(a).to(dev)
+
+    jobs = []
+    for s in specs:
+        if s.kind == 3:
+            b = s.pattern
+            jobs.append({"kind": 3, "row_ptr": d(b.row_ptr), "col_idx": d(b.col_idx), "col_ptr": d(b.col_ptr),
+                         "row_idx": d(b.row_idx), "seed": s.seed})
+        else:
+            jobs.append({"kind": s.kind, "row_ptr": d(s.graph.row_ptr), "col_idx": d(s.graph.col), "seed": s.seed})
+        n = (jobs[-1]["col_ptr"] if s.kind == 3 else jobs[-1]["row_ptr"]).numel() - 1
+        jobs[-1]["out"] = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    plain_out = [torch.empty_like(j["out"]) for j in jobs]
+    torch.cuda.synchronize()
+
+    def plain():
+        for j, o in zip(jobs, plain_out):
+            if j["kind"] == 3:
+                gc.color_pd2(j["row_ptr"], j["col_idx"], j["col_ptr"], j["row_idx"], seed=j["seed"], out=o)
+            elif j["kind"] == 2:
+                gc.color_d2(j["row_ptr"], j["col_idx"], seed=j["seed"], out=o)
+            else:
+                gc.color_d1(j["row_ptr"], j["col_idx"], seed=j["seed"], out=o)
+
+    def batched():
+        return gc.color_batch(jobs)[1]
+
+    for i in range(args.warmup):
+        t0 = time.perf_counter()
+        plain()
+        torch.cuda.synchronize()
+        log(f"[bench] warm-up {i}: plain {1e3 * (time.perf_counter() - t0):.1f} ms")
+        t0 = time.perf_counter()
+        batched()
+        torch.cuda.synchronize()
+        log(f"[bench] warm-up {i}: batched {1e3 * (time.perf_counter() - t0):.1f} ms")
+    t_plain, t_batch = [], []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain()
+        torch.cuda.synchronize()
+        t_plain.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        st = batched()
+        torch.cuda.synchronize()
+        t_batch.append(time.perf_counter() - t0)
+        log(f"[bench] step {i}: plain {t_plain[-1] * 1e3:.1f} ms, batched {t_batch[-1] * 1e3:.1f} ms")
+    same = all(torch.equal(j["out"], o) for j, o in zip(jobs, plain_out))
+    tb = sum(t_batch) / len(t_batch)
+    tp = sum(t_plain) / len(t_plain)
+    nnz = sum(_nnz_of(s) for s in specs)
+    return {
+        "metric": "graphs colored/s (batched, mixed D1/D2/PD2)",
+        "value": round(len(specs) / tb, 1),
+        "unit": "graphs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(tb * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(specs)} jobs, n log-uniform [1e3, {args.n_max:g}], ER/stencil/R-MAT thirds, "
+                               f"D1/D2/PD2 70/20/10 (D2, PD2 on ER and stencil), seed {args.stream_seed}",
+                   "sum_nnz": nnz, "rounds_max": max(x.rounds for x in st)},
+        "plain_per_graph": {"ms_per_step": round(tp * 1e3, 3), "graphs_per_s": round(len(specs) / tp, 1)},
+        "speedup_vs_plain": round(tp / tb, 3),
+        "edges_per_s_batched": round(nnz / tb, 1),
+        "identical_colorings": bool(same),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
+def bench_serve(args, torch, gc, dev):
+    import numpy as np
+    specs = _stream(args)
+    budget = int(args.serve_budget_gib * (1 << 30))
+
+    def submit(srv, s):
+        if s.kind == 3:
+            b = s.pattern
+            return srv.submit(3, b.row_ptr, b.col_idx, b.col_ptr, b.row_idx, seed=s.seed)[0]
+        return srv.submit(s.kind, s.graph.row_ptr, s.graph.col, seed=s.seed)[0]
+
+    def run(rate):
+        """Open loop at `rate` jobs/s (None: all at t=0).  Returns latencies (s) and makespan."""
+        rng = np.random.default_rng(123)
+        gaps = rng.exponential(1.0 / rate, len(specs)) if rate else np.zeros(len(specs))
+        arrive = np.cumsum(gaps)
+        srv = gc.ColorServer(budget, max_slots=args.slots)
+        lat, pending = [], {}
+        nxt = 0
+        t0 = time.perf_counter()
+        try:
+            while nxt < len(specs) or pending:
+                now = time.perf_counter() - t0
+                while nxt < len(specs) and arrive[nxt] <= now:
+                    pending[submit(srv, specs[nxt])] = arrive[nxt]
+                    nxt += 1
+                for jid in list(pending):
+                    if srv.poll(jid) is not None:
+                        lat.append(time.perf_counter() - t0 - pending.pop(jid))
+        finally:
+            srv.close()
+        return np.array(lat), time.perf_counter() - t0
+
+    _, span0 = run(None)  # warm-up (library and page-in)
+    log(f"[bench] serve warm-up: {span0:.2f} s")
+    lat_closed, span = run(None)
+    sat = len(specs) / span
+    log(f"[bench] serve closed-loop: {sat:.1f} graphs/s, p50 {np.percentile(lat_closed, 50) * 1e3:.1f} ms")
+    loads = {}
+    for f in (0.5, 0.8, 1.2):
+        lat, span_f = run(f * sat)
+        loads[str(f)] = {"rate_graphs_per_s": round(f * sat, 1),
+                         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                         "throughput_graphs_per_s": round(len(specs) / span_f, 1)}
+        log(f"[bench] serve {f}x: {loads[str(f)]}")
+    return {
+        "metric": "p99 latency (served, 0.8x saturation)",
+        "value": loads["0.8"]["p99_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(span * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(specs)} jobs as --workload batch, Poisson arrivals at 0.5/0.8/1.2x the "
+                               f"closed-loop rate; server budget {args.serve_budget_gib} GiB, {args.slots} slots",
+                   "closed_loop_graphs_per_s": round(sat, 1),
+                   "closed_loop_p50_ms": round(float(np.percentile(lat_closed, 50)) * 1e3, 3),
+                   "loads": loads},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
+# ---------------------------------------------------------------------------
+# hardware-counter summary (runs on the host, no GPU)
+# ---------------------------------------------------------------------------
+
+def _counter_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {d}")
+    rows = []
+    for fn in files:
+        with open(fn, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def _short(name):
+    base = name.split("(")[0].replace("void ", "").replace("gcol::", "").strip()
+    return base.replace("<1>", "<D1>").replace("<2>", "<D2>").replace("<3>", "<PD2>")
+
+
+def summarize_pmc(fetch_dir, write_dir, out):
+    """KiB per dispatch from FETCH_SIZE / WRITE_SIZE runs -> bytes per launch
+    per kernel, scaled so that the calibration copy reads and writes
+    COPY_BYTES each."""
+    from paper_2107_00075_amd.build import source_hash
+    per = {}
+    for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        for r in _counter_rows(d):
+            if not r.get("Counter_Name", "").startswith(counter):
+                continue
+            k = _short(r["Kernel_Name"])
+            e = per.setdefault(k, {}).setdefault(counter, [])
+            e.append(float(r["Counter_Value"]))
+    copy_keys = [k for k in per if "copyBuffer" in k]
+    if not copy_keys:
+        raise SystemExit("no copy kernel in the runs: profile bench.py --copy-calibration")
+    ck = copy_keys[0]
+    fetch_copy = max(per[ck]["FETCH_SIZE"]) * 1024.0
+    write_copy = max(per[ck]["WRITE_SIZE"]) * 1024.0
+    f_scale = COPY_BYTES / fetch_copy
+    w_scale = COPY_BYTES / write_copy
+    kernels = {}
+    for k, v in per.items():
+        if "FETCH_SIZE" not in v or "WRITE_SIZE" not in v:
+            continue
+        fb = sum(v["FETCH_SIZE"]) / len(v["FETCH_SIZE"]) * 1024.0 * f_scale
+        wb = sum(v["WRITE_SIZE"]) / len(v["WRITE_SIZE"]) * 1024.0 * w_scale
+        kernels[k] = {"dispatches": len(v["FETCH_SIZE"]), "fetch_bytes_per_launch": int(fb),
+                      "write_bytes_per_launch": int(wb), "hbm_bytes_per_launch": int(fb + wb)}
+    res = {"source_hash": source_hash(),
+           "copy_calibration": {"kernel": ck, "bytes": COPY_BYTES, "fetch_scale": round(f_scale, 4),
+                                "write_scale": round(w_scale, 4)},
+           "kernels": kernels}
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1, sort_keys=True)
+    print(json.dumps({"written": out, "kernels": len(kernels), "fetch_scale": f_scale, "write_scale": w_scale}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="d1", choices=["d1", "batch", "serve"])
+    ap.add_argument("--jobs", type=int, default=300, help="batch/serve: jobs in the stream")
+    ap.add_argument("--n-max", type=float, default=3e4, help="batch/serve: largest job size (vertices)")
+    ap.add_argument("--stream-seed", type=int, default=5)
+    ap.add_argument("--slots", type=int, default=64, help="serve: job slots")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device copy (for counter scaling)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--pmc-out", default=TRAFFIC_FILE)
+    args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_out)
+        return
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2107_00075_amd as gc
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    if args.workload == "batch":
+        out = bench_batch(args, torch, gc, dev)
+    elif args.workload == "serve":
+        out = bench_serve(args, torch, gc, dev)
+    else:
+        out = bench_d1(args, torch, gc, dev)
     print(json.dumps(out))
 
 

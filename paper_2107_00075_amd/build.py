@@ -25,6 +25,21 @@ FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """SHA-256 over the library's sources and header: tags measurements
+    (hardware counters) with the code they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    names = sorted(os.listdir(CSRC))
+    for name in names:
+        if name.endswith((".hip", ".hpp", ".cpp", ".h")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(INCLUDE, "graphcolor.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, src + ".o")
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]

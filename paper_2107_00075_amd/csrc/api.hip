@@ -71,7 +71,7 @@ void Workspace::release() {
   events.clear();
   for (DevBuf* b : {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
                     &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
-                    &inc_F, &inc_L0, &inc_L1, &inc_B0, &inc_B1, &scan_tmp})
+                    &inc_F, &inc_L0, &inc_B0, &scan_tmp})
     b->release();
   if (host) (void)hipHostFree(host);
   host = nullptr;
@@ -414,7 +414,6 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   if ((e = w->inc_words.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
   if ((e = w->inc_fwoff.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
   if ((e = w->inc_L0.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
-  if ((e = w->inc_L1.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
   int32_t* len = w->inc_len.as<int32_t>();
   int32_t* words = w->inc_words.as<int32_t>();
   if (hipMemsetAsync(len + n, 0, sizeof(int32_t), c.st) != hipSuccess) return COLOR_EHIP;
@@ -453,18 +452,20 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   const size_t list_entries = std::max<size_t>(1, total_list);
   if ((e = w->inc_F.ensure(sizeof(uint32_t) * static_cast<size_t>(std::max(fw_total, 1)), false, c.st))) return e;
   if ((e = w->inc_B0.ensure(sizeof(int32_t) * list_entries, false, c.st))) return e;
-  if ((e = w->inc_B1.ensure(sizeof(int32_t) * list_entries, false, c.st))) return e;
   if (hipMemsetAsync(w->inc_F.p, 0, sizeof(uint32_t) * static_cast<size_t>(std::max(fw_total, 1)), c.st) !=
       hipSuccess)
     return COLOR_EHIP;
-  int32_t* B[2] = {w->inc_B0.as<int32_t>(), w->inc_B1.as<int32_t>()};
-  int32_t* Lb[2] = {w->inc_L0.as<int32_t>(), w->inc_L1.as<int32_t>()};
-  const int32_t* A0 = g.ci;  // D1: round 1 reads the adjacency itself
+  // One list array, compacted in place (the lists of a round are read and
+  // rewritten only by their own vertex's workgroup); for D1 round 1 reads the
+  // adjacency itself and compacts into the list array.
+  int32_t* B = w->inc_B0.as<int32_t>();
+  int32_t* Lb = w->inc_L0.as<int32_t>();
+  const int32_t* A0 = g.ci;
   if (MODE != kD1) {
-    launch_inc_fill<MODE>(g, aoff, len, B[0], w->deferred.as<int32_t>(), &S->deferred_cnt, &S->deferred_grab[1],
+    launch_inc_fill<MODE>(g, aoff, len, B, w->deferred.as<int32_t>(), &S->deferred_cnt, &S->deferred_grab[1],
                           c.st);
     c.launches += 2;
-    A0 = B[0];
+    A0 = B;
   }
   IncBufs ib;
   ib.C = colors;
@@ -481,7 +482,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   ib.rounds_done = &S->rounds_done;
   if (init) {
     IncBufs pb = ib;
-    pb.alen_in = Lb[0];
+    pb.alen_in = Lb;
     launch_inc_init_push(pb, n, A0, c.st);
     c.launches += 1;
   }
@@ -511,10 +512,10 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
       b.wl_out = c.wl[pout];
       b.cnt_in = S->cnt[pin];
       b.cnt_out = S->cnt[pout];
-      b.A_in = local == 1 ? A0 : B[pin];
-      b.A_out = B[pout];
-      b.alen_in = Lb[pin];
-      b.alen_out = Lb[pout];
+      b.A_in = local == 1 ? A0 : B;
+      b.A_out = B;
+      b.alen_in = Lb;
+      b.alen_out = Lb;
       if (c.timing && c.record_event(0)) return COLOR_EHIP;
       launch_inc_color(b, L, local, grid_c, c.st);
       if (c.timing && c.record_event(1)) return COLOR_EHIP;

@@ -14,7 +14,9 @@
 //    tentative color equals its committed one, which T[v] avoids).  Each
 //    vertex keeps an active list A(v) of neighbours that may still be
 //    uncolored; the detect kernel scans A(v) and, when v loses, compacts it
-//    to the neighbours not yet committed.  A neighbour that commits in the
+//    in place to the neighbours not yet committed (every round at first,
+//    then periodically: stale entries of committed neighbours never
+//    conflict).  A neighbour that commits in the
 //    same round may or may not be dropped (its C is written concurrently);
 //    either way the conflict test already used its tentative color, and its
 //    commit pushes its color into F[v].
@@ -82,6 +84,20 @@ __device__ __forceinline__ void push_color(const IncBufs& b, int32_t x, int32_t 
     atomicOr(p, bit);
     ++pushes;
   }
+}
+
+// A loser compacts its list to the neighbours not yet committed in the first
+// kCompactAlways rounds (where most neighbours commit), whenever its list is
+// still the read-only adjacency (round 1 of D1), and else once every
+// kCompactPeriod rounds.  Entries of committed neighbours left in a list are
+// harmless: a committed neighbour's tentative color is its committed color,
+// which the vertex's own tentative color avoids, and pushes skip committed
+// vertices.
+constexpr int kCompactAlways = 4;
+constexpr int kCompactPeriod = 4;
+
+__device__ __forceinline__ bool compact_now(const IncBufs& b, int round, int32_t v) {
+  return b.A_in != b.A_out || round <= kCompactAlways || ((round + v) & (kCompactPeriod - 1)) == 0;
 }
 
 }  // namespace
@@ -155,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void inc_color_kernel(IncBufs b, BinLayout 
 // detect + commit/push or compact, group of G lanes per vertex
 // ---------------------------------------------------------------------------
 template <int G>
-__device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int bin, const int32_t* wl,
+__device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round, int bin, const int32_t* wl,
                                  int32_t count, int32_t off_out, int32_t* s_ent, int32_t* s_wc,
                                  int32_t& maxc_acc, uint64_t& bytes, uint64_t& pushes) {
   constexpr int per_pass = kBlock / G;
@@ -171,15 +187,29 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int bin, 
     const int32_t len = ld_dev(&b.alen_in[v]);
     const int32_t* A = b.A_in + base;
     bool lose = false;
-    for (int32_t e = sub; e < len; e += G) {
-      const int32_t u = ld_dev(&A[e]);
-      if (ld_dev(&b.T[u]) == tv && key_of(k, u) > kv) {
-        lose = true;
-        break;
+    int32_t read = 0;
+    for (int32_t e0 = sub; e0 < len && !lose; e0 += 4 * G) {
+      int32_t u[4], t[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t e = e0 + j * G;
+        u[j] = e < len ? ld_dev(&A[e]) : -1;
+        read += e < len ? 1 : 0;
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) t[j] = u[j] >= 0 ? ld_dev(&b.T[u[j]]) : -1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (t[j] == tv && key_of(k, u[j]) > kv) lose = true;
     }
     lose = group_any<G>(lose);
-    if (lose) {
+    if (lose) bytes += 8ull * static_cast<uint64_t>(read);  // the entries this lane scanned
+    if (lose && !compact_now(b, round, v)) {
+      if (sub == 0) {
+        s_ent[idx] = v;
+        bytes += 20;
+      }
+    } else if (lose) {
       // keep the neighbours that are not committed (yet)
       int32_t kept = 0;
       for (int32_t e0 = 0; e0 < len; e0 += G) {
@@ -200,12 +230,21 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int bin, 
       if (sub == 0) {
         st_dev(&b.alen_out[v], kept);
         s_ent[idx] = v;
-        bytes += 16 + 12ull * static_cast<uint64_t>(len) + 4;
+        bytes += 24 + 8ull * static_cast<uint64_t>(len) + 4ull * static_cast<uint64_t>(kept);
       }
     } else {
-      for (int32_t e = sub; e < len; e += G) {
-        const int32_t x = ld_dev(&A[e]);
-        if (ld_dev(&b.C[x]) == 0) push_color(b, x, tv, pushes);
+      for (int32_t e0 = sub; e0 < len; e0 += 4 * G) {
+        int32_t x[4], c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int32_t e = e0 + j * G;
+          x[j] = e < len ? ld_dev(&A[e]) : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = x[j] >= 0 ? ld_dev(&b.C[x[j]]) : 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (c[j] == 0) push_color(b, x[j], tv, pushes);
       }
       if (sub == 0) {
         st_dev(&b.C[v], tv);
@@ -237,9 +276,14 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int bin, 
   __syncthreads();
 }
 
-// One workgroup per heavy vertex.
-__device__ void inc_detect_block(const KeySource& k, const IncBufs& b, int32_t v, int bin, int32_t off,
-                                 int32_t* s_wc, int32_t& maxc_acc, uint64_t& bytes, uint64_t& pushes) {
+// One workgroup per heavy vertex.  Every thread keeps kIncBatch independent
+// list loads (and then their T or C loads) in flight, and the workgroup meets
+// at a barrier once per kBlock * kIncBatch entries.
+constexpr int kIncBatch = 8;
+
+__device__ void inc_detect_block(const KeySource& k, const IncBufs& b, int round, int32_t v, int bin,
+                                 int32_t off, int32_t* s_wc, int32_t& maxc_acc, uint64_t& bytes,
+                                 uint64_t& pushes) {
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int32_t tv = ld_dev(&b.T[v]);
@@ -247,52 +291,89 @@ __device__ void inc_detect_block(const KeySource& k, const IncBufs& b, int32_t v
   const int32_t base = ld_dev(&b.aoff[v]);
   const int32_t len = ld_dev(&b.alen_in[v]);
   const int32_t* A = b.A_in + base;
+  constexpr int32_t step = kBlock * kIncBatch;
   bool lose = false;
-  for (int32_t e0 = 0; e0 < len; e0 += kBlock) {
-    const int32_t e = e0 + tid;
-    if (e < len) {
-      const int32_t u = ld_dev(&A[e]);
-      if (ld_dev(&b.T[u]) == tv && key_of(k, u) > kv) lose = true;
+  for (int32_t e0 = 0; e0 < len; e0 += step) {
+    int32_t u[kIncBatch], t[kIncBatch];
+#pragma unroll
+    for (int j = 0; j < kIncBatch; ++j) {
+      const int32_t e = e0 + j * kBlock + tid;
+      u[j] = e < len ? ld_dev(&A[e]) : -1;
     }
+#pragma unroll
+    for (int j = 0; j < kIncBatch; ++j) t[j] = u[j] >= 0 ? ld_dev(&b.T[u[j]]) : -1;
+#pragma unroll
+    for (int j = 0; j < kIncBatch; ++j)
+      if (t[j] == tv && key_of(k, u[j]) > kv) lose = true;
     if (__syncthreads_or(lose)) {
       lose = true;
+      if (tid == 0) bytes += 8ull * static_cast<uint64_t>(min(len, e0 + step));
       break;
     }
   }
-  lose = __syncthreads_or(lose);
-  if (lose) {
+  if (lose && !compact_now(b, round, v)) {
+    if (tid == 0) {
+      const int32_t p = atomicAdd(&b.cnt_out[bin], 1);
+      st_dev(&b.wl_out[off + p], v);
+      bytes += 24;
+    }
+  } else if (lose) {
+    // keep the neighbours that are not committed (yet); order is free.  The
+    // list may be compacted in place: every entry of a step is read before
+    // the barrier that precedes the step's writes, and writes land below
+    // the step's first entry or inside it.
     int32_t kept = 0;
-    for (int32_t e0 = 0; e0 < len; e0 += kBlock) {
-      const int32_t e = e0 + tid;
-      int32_t u = -1;
-      bool keep = false;
-      if (e < len) {
-        u = ld_dev(&A[e]);
-        keep = ld_dev(&b.C[u]) == 0;
+    for (int32_t e0 = 0; e0 < len; e0 += step) {
+      int32_t u[kIncBatch], c[kIncBatch];
+#pragma unroll
+      for (int j = 0; j < kIncBatch; ++j) {
+        const int32_t e = e0 + j * kBlock + tid;
+        u[j] = e < len ? ld_dev(&A[e]) : -1;
       }
-      const uint64_t bal = __ballot(keep);
-      if (lane_id() == 0) s_wc[wave] = static_cast<int32_t>(__popcll(bal));
+#pragma unroll
+      for (int j = 0; j < kIncBatch; ++j) c[j] = u[j] >= 0 ? ld_dev(&b.C[u[j]]) : 1;
+      int32_t cnt = 0;
+#pragma unroll
+      for (int j = 0; j < kIncBatch; ++j) cnt += c[j] == 0 ? 1 : 0;
+      int32_t incl = cnt;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, kWave);
+        if (lane_id() >= o) incl += y;
+      }
+      if (lane_id() == kWave - 1) s_wc[wave] = incl;
       __syncthreads();
-      int32_t wbase = kept;
+      int32_t pos = kept + incl - cnt;
       int32_t tot = 0;
       for (int w = 0; w < kWavesPerBlock; ++w) {
-        if (w < wave) wbase += s_wc[w];
+        if (w < wave) pos += s_wc[w];
         tot += s_wc[w];
       }
-      if (keep) st_dev(&b.A_out[base + wbase + static_cast<int32_t>(lanes_below(bal))], u);
+#pragma unroll
+      for (int j = 0; j < kIncBatch; ++j)
+        if (c[j] == 0) st_dev(&b.A_out[base + pos++], u[j]);
       kept += tot;
       __syncthreads();
     }
     if (tid == 0) {
       st_dev(&b.alen_out[v], kept);
-      const int32_t pos = atomicAdd(&b.cnt_out[bin], 1);
-      st_dev(&b.wl_out[off + pos], v);
-      bytes += 16 + 12ull * static_cast<uint64_t>(len) + 8;
+      const int32_t p = atomicAdd(&b.cnt_out[bin], 1);
+      st_dev(&b.wl_out[off + p], v);
+      bytes += 24 + 8ull * static_cast<uint64_t>(len) + 4ull * static_cast<uint64_t>(kept);
     }
   } else {
-    for (int32_t e = tid; e < len; e += kBlock) {
-      const int32_t x = ld_dev(&A[e]);
-      if (ld_dev(&b.C[x]) == 0) push_color(b, x, tv, pushes);
+    for (int32_t e0 = 0; e0 < len; e0 += step) {
+      int32_t x[kIncBatch], c[kIncBatch];
+#pragma unroll
+      for (int j = 0; j < kIncBatch; ++j) {
+        const int32_t e = e0 + j * kBlock + tid;
+        x[j] = e < len ? ld_dev(&A[e]) : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < kIncBatch; ++j) c[j] = x[j] >= 0 ? ld_dev(&b.C[x[j]]) : 1;
+#pragma unroll
+      for (int j = 0; j < kIncBatch; ++j)
+        if (c[j] == 0) push_color(b, x[j], tv, pushes);
     }
     if (tid == 0) {
       st_dev(&b.C[v], tv);
@@ -310,7 +391,6 @@ __global__ __launch_bounds__(kBlock) void inc_detect_kernel(KeySource k, IncBufs
   __shared__ int32_t s_wc[kWavesPerBlock + 1];
   __shared__ unsigned long long s_acc[2];
   __shared__ IncMap M;
-  (void)round;
   if (threadIdx.x == 0) {
     make_inc_map(b, M);
     s_max = 0;
@@ -334,13 +414,13 @@ __global__ __launch_bounds__(kBlock) void inc_detect_kernel(KeySource k, IncBufs
     const int32_t* wl = b.wl_in + L.off[bin] + firstc;
     const int32_t oo = L.off[bin];
     switch (L.lanes[bin]) {
-      case 1: inc_detect_chunk<1>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      case 2: inc_detect_chunk<2>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      case 4: inc_detect_chunk<4>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      case 8: inc_detect_chunk<8>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      case 16: inc_detect_chunk<16>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      case 32: inc_detect_chunk<32>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      default: inc_detect_chunk<64>(k, b, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 1: inc_detect_chunk<1>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 2: inc_detect_chunk<2>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 4: inc_detect_chunk<4>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 8: inc_detect_chunk<8>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 16: inc_detect_chunk<16>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 32: inc_detect_chunk<32>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      default: inc_detect_chunk<64>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
     }
   }
   if (M.heavy_total > 0) {
@@ -353,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void inc_detect_kernel(KeySource k, IncBufs
       const int bin = u < M.cnt[kBlockBin] ? kBlockBin : kSplitBin;
       const int32_t j = bin == kBlockBin ? u : u - M.cnt[kBlockBin];
       const int32_t v = ld_dev(&b.wl_in[L.off[bin] + j]);
-      inc_detect_block(k, b, v, bin, L.off[bin], s_wc, maxc_acc, bytes, pushes);
+      inc_detect_block(k, b, round, v, bin, L.off[bin], s_wc, maxc_acc, bytes, pushes);
     }
   }
   maxc_acc = [&] {

@@ -16,9 +16,9 @@ struct IncBufs {
   int32_t* tile_ctr;           // [1]: heavy-unit counter of the detect kernel
   const int32_t* aoff;         // list offsets (D1: row_ptr; D2/PD2: prefix of list lengths)
   const int32_t* A_in;         // active lists of round r
-  int32_t* A_out;              // compacted active lists for round r+1
+  int32_t* A_out;              // compacted lists (the same array as A_in after round 1: in place)
   const int32_t* alen_in;      // list lengths of round r
-  int32_t* alen_out;           // list lengths for round r+1
+  int32_t* alen_out;           // list lengths for round r+1 (the same array as alen_in)
   const int32_t* fw_off;       // bitset word offsets, n+1 entries
   uint32_t* F;                 // forbidden-color bitsets (bit c-1 = color c)
   int32_t* maxc;               // largest committed color
