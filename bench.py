@@ -22,6 +22,9 @@ Other workloads (one JSON line each, same keys):
                        per job; value = graphs/s of the batched form
     --workload serve   the same stream through the continuous-batching
                        server with Poisson arrivals; reports p50/p99 latency
+    --workload ghost   one rank's ghost-layer step (color_d1_ghost) on part 0
+                       of a 16-way hash partition of R-MAT scale 24, with 1
+                       and 2 ghost layers, plus property checks
 
 Profiling helpers (no GPU):
     --summarize-pmc FETCH_DIR WRITE_DIR   turns two rocprofv3 --pmc runs
@@ -389,6 +392,96 @@ def bench_serve(args, torch, gc, dev):
 
 
 # ---------------------------------------------------------------------------
+# ghost-layer step on one part of a partitioned graph
+# ---------------------------------------------------------------------------
+
+def bench_ghost(args, torch, gc, dev):
+    """One rank's step (color_d1_ghost) on part 0 of a 16-way hash partition
+    of R-MAT scale `--ghost-scale`, with 1 and 2 ghost layers.  Checks
+    properties that hold at any size: owned colors proper among owned
+    vertices, every owned-ghost pair still equal after the step has its ghost
+    flagged as a remote loser, and the 2-layer result equal to the 1-layer
+    one."""
+    import numpy as np
+
+    import graphgen as gg
+    t = time.time()
+    g = gg.rmat(args.ghost_scale, 16, seed=1)
+    delta = int(g.degrees().max())
+    log(f"[bench] rmat s{args.ghost_scale}: n={g.n} nnz={g.nnz} maxdeg={delta} ({time.time() - t:.1f}s)")
+    owner = gg.hash_partition(g.n, 16, seed=7)
+    gcol = gg.ghost_colors_uniform(g.n, delta, seed=11)
+    res = {}
+    for layers in (1, 2):
+        t = time.time()
+        lg = gg.ghost_local_graph(g, owner, 0, layers, gcol)
+        log(f"[bench] part 0, {layers} layer(s): owned {lg.n_owned}, ghosts {lg.n_ghost} (G1 {lg.n_g1}), "
+            f"local nnz {lg.nnz} ({time.time() - t:.1f}s)")
+        rp, ci, gid, gco = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                            for a in (lg.row_ptr, lg.col, lg.gid, lg.ghost_colors))
+        out = torch.empty(lg.n_owned, dtype=torch.int32, device=dev)
+
+        def step():
+            return gc.color_d1_ghost(lg.n_owned, lg.n_ghost, layers, lg.n_g1, rp, ci, gid, gco, seed=1, out=out)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            colors, rl, st = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        colors = colors.cpu().numpy()
+        rl = rl.cpu().numpy()
+        owned_nnz = int(lg.row_ptr[lg.n_owned])
+        res[layers] = {"colors": colors, "rl": rl, "st": st, "ms": dt * 1e3, "lg": lg, "owned_nnz": owned_nnz}
+        log(f"[bench] {layers} layer(s): {dt * 1e3:.2f} ms, colors {st.num_colors}, rounds {st.rounds}, "
+            f"conflicts {st.boundary_conflicts}, remote losers {st.remote_losers}")
+    # properties on the 1-layer local graph
+    lg = res[1]["lg"]
+    colors, rl = res[1]["colors"], res[1]["rl"]
+    no = lg.n_owned
+    src = np.repeat(np.arange(no), np.diff(lg.row_ptr[:no + 1]))
+    dst = lg.col[:lg.row_ptr[no]]
+    inner = dst < no
+    proper = bool(np.all(colors[src[inner]] != colors[dst[inner]])) and bool(colors.min() >= 1)
+    gdst = dst[~inner] - no
+    eq = colors[src[~inner]] == lg.ghost_colors[gdst]
+    flagged = bool(np.all(rl[gdst[eq]] == 1))
+    same_layers = bool(np.array_equal(res[1]["colors"], res[2]["colors"]) and
+                       np.array_equal(res[1]["rl"], res[2]["rl"][:res[1]["rl"].size]))
+    st1 = res[1]["st"]
+    return {
+        "metric": "edges colored/s (D1 ghost-layer step, part 0 of 16)",
+        "value": round(res[1]["owned_nnz"] / (res[1]["ms"] / 1e3), 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res[1]["ms"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"R-MAT s{args.ghost_scale} ef16 seed 1, 16-way hash partition, part 0, ghost colors "
+                               f"uniform in [1, maxdeg+1]; 1 and 2 ghost layers",
+                   "layers": {str(k): {"ms": round(v["ms"], 3), "owned": v["lg"].n_owned,
+                                       "ghosts": v["lg"].n_ghost, "local_nnz": v["lg"].nnz,
+                                       "owned_row_nnz": v["owned_nnz"], "colors": v["st"].num_colors,
+                                       "rounds": v["st"].rounds,
+                                       "boundary_conflicts": v["st"].boundary_conflicts,
+                                       "remote_losers": v["st"].remote_losers} for k, v in res.items()},
+                   "checks": {"owned_proper": proper, "equal_pairs_flagged": flagged,
+                              "two_layers_equal_one": same_layers}},
+        "roofline": None,
+        "cpu_baseline": None,
+        "boundary_conflicts": st1.boundary_conflicts,
+    }
+
+
+# ---------------------------------------------------------------------------
 # hardware-counter summary (runs on the host, no GPU)
 # ---------------------------------------------------------------------------
 
@@ -452,7 +545,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="d1", choices=["d1", "batch", "serve"])
+    ap.add_argument("--workload", default="d1", choices=["d1", "batch", "serve", "ghost"])
+    ap.add_argument("--ghost-scale", type=int, default=24, help="ghost: R-MAT scale of the partitioned graph")
     ap.add_argument("--jobs", type=int, default=300, help="batch/serve: jobs in the stream")
     ap.add_argument("--n-max", type=float, default=3e4, help="batch/serve: largest job size (vertices)")
     ap.add_argument("--stream-seed", type=int, default=5)
@@ -483,6 +577,8 @@ def main():
         out = bench_batch(args, torch, gc, dev)
     elif args.workload == "serve":
         out = bench_serve(args, torch, gc, dev)
+    elif args.workload == "ghost":
+        out = bench_ghost(args, torch, gc, dev)
     else:
         out = bench_d1(args, torch, gc, dev)
     print(json.dumps(out))

@@ -197,10 +197,10 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round
         read += e < len ? 1 : 0;
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) t[j] = u[j] >= 0 ? ld_dev(&b.T[u[j]]) : -1;
+      for (int j = 0; j < 4; ++j) t[j] = (u[j] >= 0 && key_of(k, u[j]) > kv) ? ld_dev(&b.T[u[j]]) : -1;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (t[j] == tv && key_of(k, u[j]) > kv) lose = true;
+        if (t[j] == tv) lose = true;
     }
     lose = group_any<G>(lose);
     if (lose) bytes += 8ull * static_cast<uint64_t>(read);  // the entries this lane scanned
@@ -300,11 +300,13 @@ __device__ void inc_detect_block(const KeySource& k, const IncBufs& b, int round
       const int32_t e = e0 + j * kBlock + tid;
       u[j] = e < len ? ld_dev(&A[e]) : -1;
     }
+    // only a higher-key neighbour can beat v: compare keys first and read
+    // the tentative colors of those neighbours only
 #pragma unroll
-    for (int j = 0; j < kIncBatch; ++j) t[j] = u[j] >= 0 ? ld_dev(&b.T[u[j]]) : -1;
+    for (int j = 0; j < kIncBatch; ++j) t[j] = (u[j] >= 0 && key_of(k, u[j]) > kv) ? ld_dev(&b.T[u[j]]) : -1;
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j)
-      if (t[j] == tv && key_of(k, u[j]) > kv) lose = true;
+      if (t[j] == tv) lose = true;
     if (__syncthreads_or(lose)) {
       lose = true;
       if (tid == 0) bytes += 8ull * static_cast<uint64_t>(min(len, e0 + step));
@@ -478,8 +480,13 @@ __global__ __launch_bounds__(kBlock) void inc_sizes_kernel(GraphView g, const in
     l = MODE == kD1 ? d1 : static_cast<int64_t>(ld_dev(&work[v])) - (MODE == kPD2 ? 2 : 1) * d1;
     if (l < 0) l = 0;
   }
+  __shared__ unsigned long long s_t;
+  if (threadIdx.x == 0) s_t = 0ull;
+  __syncthreads();
   uint64_t t = wsum(static_cast<uint64_t>(l));
-  if (lane_id() == 0 && t) atomicAdd(total, static_cast<unsigned long long>(t));
+  if (lane_id() == 0 && t) atomicAdd(&s_t, static_cast<unsigned long long>(t));
+  __syncthreads();
+  if (threadIdx.x == 0 && s_t) atomicAdd(total, s_t);
   if (v >= g.n) return;
   const int32_t lc = static_cast<int32_t>(l > INT_MAX ? INT_MAX : l);
   st_dev(&len[v], lc);

@@ -160,7 +160,7 @@ __device__ void detect_chunk_group(const GraphView& g, const KeySource& k, const
     const uint64_t kv = key_of(k, v);
     bool lose = false;
     scan_nbhd<MODE, LD>(g, v, gld<LD>(&g.rp[v]), gld<LD>(&g.rp[v + 1]), sub, G, [&](int32_t u) {
-      if (ld_dev(&T[u]) == tv && key_of(k, u) > kv) {
+      if (key_of(k, u) > kv && ld_dev(&T[u]) == tv) {  // keys first: only higher keys can win
         lose = true;
         return true;
       }
@@ -207,7 +207,7 @@ __device__ void detect_vertex_block(const GraphView& g, const KeySource& k, cons
   const uint64_t kv = key_of(k, v);
   bool lose = false;
   scan_nbhd<MODE, LD>(g, v, gld<LD>(&g.rp[v]), gld<LD>(&g.rp[v + 1]), tid, kBlock, [&](int32_t u) {
-    if (ld_dev(&T[u]) == tv && key_of(k, u) > kv) {
+    if (key_of(k, u) > kv && ld_dev(&T[u]) == tv) {  // keys first: only higher keys can win
       lose = true;
       return true;
     }

@@ -244,7 +244,7 @@ __device__ void detect_split_chunk(const GraphView& g, const KeySource& k, const
   bool lose = false;
   if (atomic_load_u32(&b.split_flag[si]) == 0u) {  // another chunk may already have decided
     scan_nbhd<MODE>(g, v, cb, ce, tid, kBlock, [&](int32_t u) {
-      if (ld_dev(&T[u]) == tv && key_of(k, u) > kv) {
+      if (key_of(k, u) > kv && ld_dev(&T[u]) == tv) {
         lose = true;
         return true;
       }

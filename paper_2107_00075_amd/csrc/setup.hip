@@ -71,25 +71,109 @@ __device__ void account_vertex(const BinSetup& s, int32_t v, int64_t w, bool act
   }
 }
 
-// One thread per vertex.  D2/PD2 vertices whose first hop is longer than
-// kSetupHeavy entries are deferred to heavy_work_kernel (a workgroup each).
+// Per-call totals of the vertices one thread records, flushed once per
+// workgroup (a handful of device atomics per workgroup instead of per
+// wavefront).
+struct BinAcc {
+  int32_t cmax = 0, smax = 0, wmax = 0;
+  uint64_t wsum = 0;
+  int32_t all[kBins] = {0, 0, 0, 0, 0};
+  int32_t unc[kBins] = {0, 0, 0, 0, 0};
+};
+
+__device__ __forceinline__ void record_vertex(const BinSetup& s, int32_t v, int64_t w, BinAcc& a) {
+  const int32_t wc = static_cast<int32_t>(w > INT_MAX ? INT_MAX : w);
+  st_dev(&s.work[v], wc);
+  int bin = kBins - 1;
+  for (int i = 0; i < kBins - 1; ++i) {
+    if (wc <= s.bin_hi[i]) {
+      bin = i;
+      break;
+    }
+  }
+  st_dev(&s.bin[v], static_cast<int8_t>(bin));
+  const int32_t c = s.init ? ld_dev(&s.init[v]) : 0;
+  st_dev(&s.C[v], c);
+  st_dev(&s.T[v], c);
+  a.cmax = max(a.cmax, c);
+  if (c == 0) {
+    if (bin == kSplitBin) a.smax = max(a.smax, wc);
+    a.wmax = max(a.wmax, wc);
+    a.wsum += static_cast<uint64_t>(w);
+  }
+#pragma unroll
+  for (int i = 0; i < kBins; ++i) {
+    a.all[i] += bin == i ? 1 : 0;
+    a.unc[i] += (bin == i && c == 0) ? 1 : 0;
+  }
+}
+
+__device__ void flush_acc(const BinSetup& s, BinAcc& a) {
+  __shared__ int32_t s_i[3 + 2 * kBins];
+  __shared__ unsigned long long s_sum;
+  const int tid = threadIdx.x;
+  if (tid < 3 + 2 * kBins) s_i[tid] = 0;
+  if (tid == 0) s_sum = 0ull;
+  __syncthreads();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    a.cmax = max(a.cmax, __shfl_xor(a.cmax, off, kWave));
+    a.smax = max(a.smax, __shfl_xor(a.smax, off, kWave));
+    a.wmax = max(a.wmax, __shfl_xor(a.wmax, off, kWave));
+    a.wsum += __shfl_xor(a.wsum, off, kWave);
+#pragma unroll
+    for (int i = 0; i < kBins; ++i) {
+      a.all[i] += __shfl_xor(a.all[i], off, kWave);
+      a.unc[i] += __shfl_xor(a.unc[i], off, kWave);
+    }
+  }
+  if (lane_id() == 0) {
+    atomicMax(&s_i[0], a.cmax);
+    atomicMax(&s_i[1], a.smax);
+    atomicMax(&s_i[2], a.wmax);
+    for (int i = 0; i < kBins; ++i) {
+      atomicAdd(&s_i[3 + i], a.all[i]);
+      atomicAdd(&s_i[3 + kBins + i], a.unc[i]);
+    }
+    if (a.wsum) atomicAdd(&s_sum, static_cast<unsigned long long>(a.wsum));
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (s_i[0] > 0) atomicMax(s.maxc, s_i[0]);
+    if (s_i[1] > 0) atomicMax(s.max_split_work, s_i[1]);
+    if (s_i[2] > 0) atomicMax(s.max_work, s_i[2]);
+    if (s_sum) atomicAdd(s.total_work, s_sum);
+  } else if (tid <= kBins) {
+    const int i = tid - 1;
+    if (s_i[3 + i]) atomicAdd(&s.count_all[i], s_i[3 + i]);
+    if (s_i[3 + kBins + i]) atomicAdd(&s.count_unc[i], s_i[3 + kBins + i]);
+  }
+}
+
+// A grid-stride loop, one thread per vertex.  D2/PD2 vertices whose first
+// hop is longer than kSetupHeavy entries are deferred to heavy_work_kernel
+// (a workgroup each).
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
-  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-  bool active = v < g.n;
-  bool defer = false;
-  if (MODE != kD1 && active) defer = g.rp[v + 1] - g.rp[v] > kSetupHeavy;
-  const uint64_t dbal = __ballot(defer);
-  if (dbal) {
-    const int first = __builtin_ctzll(dbal);
-    int32_t base = 0;
-    if (lane_id() == first) base = atomicAdd(s.deferred_cnt, static_cast<int32_t>(__popcll(dbal)));
-    base = __shfl(base, first, kWave);
-    if (defer) st_dev(&s.deferred[base + static_cast<int32_t>(lanes_below(dbal))], v);
+  BinAcc acc;
+  const int32_t stride = gridDim.x * kBlock;
+  for (int32_t base = blockIdx.x * kBlock; base < g.n; base += stride) {
+    const int32_t v = base + threadIdx.x;
+    bool active = v < g.n;
+    bool defer = false;
+    if (MODE != kD1 && active) defer = g.rp[v + 1] - g.rp[v] > kSetupHeavy;
+    const uint64_t dbal = __ballot(defer);
+    if (dbal) {
+      const int first = __builtin_ctzll(dbal);
+      int32_t b0 = 0;
+      if (lane_id() == first) b0 = atomicAdd(s.deferred_cnt, static_cast<int32_t>(__popcll(dbal)));
+      b0 = __shfl(b0, first, kWave);
+      if (defer) st_dev(&s.deferred[b0 + static_cast<int32_t>(lanes_below(dbal))], v);
+    }
+    active = active && !defer;
+    if (active) record_vertex(s, v, vertex_work<MODE>(g, v), acc);
   }
-  active = active && !defer;
-  const int64_t w = active ? vertex_work<MODE>(g, v) : 0;
-  account_vertex(s, v, w, active);
+  flush_acc(s, acc);
 }
 
 // Deferred heavy vertices: the workgroup sums the first hop's contributions.
@@ -123,30 +207,68 @@ __global__ __launch_bounds__(kBlock) void heavy_work_kernel(GraphView g, BinSetu
 
 // Appends every uncolored vertex (C[v] == 0) to its bin's region of the
 // worklist; split vertices get a split index (their position in the split
-// region) and the region holds indices.
+// region) and the region holds indices.  Each workgroup owns a contiguous
+// range of per_block vertices: it counts its vertices per bin, reserves its
+// slots with one device atomic per bin, then writes them.
 __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_t* C, const int8_t* binv,
                                                          BinLayout L, int32_t* wl, int32_t* cnt,
-                                                         int32_t* split_vertex) {
-  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-  const bool active = v < n && ld_dev(&C[v]) == 0;
-  const int bin = active ? static_cast<int>(ld_dev(&binv[v])) : -1;
+                                                         int32_t* split_vertex, int32_t per_block) {
+  __shared__ int32_t s_cnt[kBins][kWavesPerBlock];
+  __shared__ int32_t s_next[kBins];
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int32_t lo = blockIdx.x * per_block;
+  const int32_t hi = min(n, lo + per_block);
+  int32_t my[kBins] = {0, 0, 0, 0, 0};
+  for (int32_t v = lo + tid; v < hi; v += kBlock) {
+    const bool active = ld_dev(&C[v]) == 0;
+    const int bin = active ? static_cast<int>(ld_dev(&binv[v])) : -1;
+#pragma unroll
+    for (int i = 0; i < kBins; ++i) my[i] += bin == i ? 1 : 0;
+  }
+#pragma unroll
   for (int i = 0; i < kBins; ++i) {
-    const bool mine = active && bin == i;
-    const uint64_t bal = __ballot(mine);
-    if (!bal) continue;
-    const int first = __builtin_ctzll(bal);
-    int32_t base = 0;
-    if (lane_id() == first) base = atomicAdd(&cnt[i], static_cast<int32_t>(__popcll(bal)));
-    base = __shfl(base, first, kWave);
-    if (mine) {
-      const int32_t pos = base + static_cast<int32_t>(lanes_below(bal));
-      if (i == kSplitBin) {
+    int32_t x = my[i];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) x += __shfl_xor(x, off, kWave);
+    if (lane_id() == 0) s_cnt[i][wave] = x;
+  }
+  __syncthreads();
+  if (tid < kBins) {
+    int32_t tot = 0;
+    for (int w = 0; w < kWavesPerBlock; ++w) tot += s_cnt[tid][w];
+    s_next[tid] = tot ? atomicAdd(&cnt[tid], tot) : 0;
+  }
+  __syncthreads();
+  for (int32_t base = lo; base < hi; base += kBlock) {
+    const int32_t v = base + tid;
+    const bool active = v < hi && ld_dev(&C[v]) == 0;
+    const int bin = active ? static_cast<int>(ld_dev(&binv[v])) : -1;
+    int32_t rank = 0;
+#pragma unroll
+    for (int i = 0; i < kBins; ++i) {
+      const uint64_t bal = __ballot(bin == i);
+      if (bin == i) rank = static_cast<int32_t>(lanes_below(bal));
+      if (lane_id() == 0) s_cnt[i][wave] = static_cast<int32_t>(__popcll(bal));
+    }
+    __syncthreads();
+    if (active) {
+      int32_t pos = s_next[bin] + rank;
+      for (int w = 0; w < wave; ++w) pos += s_cnt[bin][w];
+      if (bin == kSplitBin) {
         st_dev(&split_vertex[pos], v);
-        st_dev(&wl[L.off[i] + pos], pos);
+        st_dev(&wl[L.off[bin] + pos], pos);
       } else {
-        st_dev(&wl[L.off[i] + pos], v);
+        st_dev(&wl[L.off[bin] + pos], v);
       }
     }
+    __syncthreads();
+    if (tid < kBins) {
+      int32_t tot = 0;
+      for (int w = 0; w < kWavesPerBlock; ++w) tot += s_cnt[tid][w];
+      s_next[tid] += tot;
+    }
+    __syncthreads();
   }
 }
 
@@ -298,10 +420,14 @@ __global__ __launch_bounds__(kBlock) void copy_i32_kernel(int32_t n, const int32
 
 static inline int blocks_for(int64_t n) { return static_cast<int>((n + kBlock - 1) / kBlock); }
 
+// Grid cap of the grid-stride setup kernels (their per-workgroup totals
+// become device atomics).
+constexpr int kSetupGrid = 2048;
+
 template <int MODE>
 void launch_bin(const GraphView& g, const BinSetup& s, hipStream_t st) {
   if (g.n <= 0) return;
-  hipLaunchKernelGGL(bin_kernel<MODE>, dim3(blocks_for(g.n)), dim3(kBlock), 0, st, g, s);
+  hipLaunchKernelGGL(bin_kernel<MODE>, dim3(std::min(blocks_for(g.n), kSetupGrid)), dim3(kBlock), 0, st, g, s);
   if (MODE != kD1)
     hipLaunchKernelGGL(heavy_work_kernel<MODE>, dim3(std::min(blocks_for(g.n), 512)), dim3(kBlock), 0, st, g, s);
 }
@@ -311,9 +437,12 @@ template void launch_bin<kPD2>(const GraphView&, const BinSetup&, hipStream_t);
 
 void launch_scatter(int32_t n, const int32_t* C, const int8_t* bin, const BinLayout& L, int32_t* wl,
                     int32_t* cnt, int32_t* split_vertex, hipStream_t st) {
-  if (n > 0)
-    hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, C, bin, L, wl, cnt,
-                       split_vertex);
+  if (n <= 0) return;
+  const int blocks = std::min(blocks_for(n), kSetupGrid);
+  const int64_t per = (static_cast<int64_t>(n) + blocks - 1) / blocks;
+  const int32_t per_block = static_cast<int32_t>((per + kBlock - 1) / kBlock * kBlock);
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(kBlock), 0, st, n, C, bin, L, wl, cnt, split_vertex,
+                     per_block);
 }
 
 void launch_validate(int32_t n_rows, int32_t n_cols, const int32_t* rp, const int32_t* ci,
