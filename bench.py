@@ -22,6 +22,8 @@ Other workloads (one JSON line each, same keys):
                        per job; value = graphs/s of the batched form
     --workload serve   the same stream through the continuous-batching
                        server with Poisson arrivals; reports p50/p99 latency
+    --workload d2pd2   D2 on the 7-point stencil 96^3 and PD2 on the
+                       4,000,000 x 1,000,000 power-law pattern
     --workload ghost   one rank's ghost-layer step (color_d1_ghost) on part 0
                        of a 16-way hash partition of R-MAT scale 24, with 1
                        and 2 ghost layers, plus property checks
@@ -64,6 +66,17 @@ def d1_kernel_bytes(st):
     color = 20 * st.vertex_visits + 8 * st.edge_visits
     detect = 20 * st.vertex_visits + 8 * st.edge_visits
     return color, detect
+
+
+def pull_two_hop_bytes(st, avg_deg):
+    """Pull engine, D2/PD2: per worklist vertex 20 bytes; per first-hop entry
+    its id and the two row offsets of its hop-2 row (12 bytes); per hop-2
+    entry its id and color (8 bytes).  edge_visits counts first-hop plus
+    hop-2 entries; the first-hop share is estimated as avg_deg per visit."""
+    e1 = min(st.edge_visits, int(st.vertex_visits * avg_deg))
+    e2 = st.edge_visits - e1
+    b = 20 * st.vertex_visits + 12 * e1 + 8 * e2
+    return b, b
 
 
 def make_d1_workload():
@@ -219,6 +232,88 @@ def bench_d1(args, torch, gc, dev):
                    "graphs": per_graph},
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+
+
+# ---------------------------------------------------------------------------
+# distance-2 and partial distance-2
+# ---------------------------------------------------------------------------
+
+def bench_d2pd2(args, torch, gc, dev):
+    """D2 on the 7-point stencil 96^3 and PD2 on the 4,000,000 x 1,000,000
+    power-law pattern (8 columns per row, tail exponent 2.1), one step = both."""
+    import graphgen as gg
+    t = time.time()
+    g = gg.stencil((96, 96, 96), 7)
+    b = gg.bipartite_powerlaw(4_000_000, 1_000_000, 8, 2.1, seed=1)
+    log(f"[bench] 7pt 96^3: n={g.n} nnz={g.nnz}; PD2 {b.n_rows}x{b.n_cols} nnz={b.nnz} ({time.time() - t:.1f}s)")
+    d = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    grp, gci = d(g.row_ptr), d(g.col)
+    brp, bci, bcp, bri = d(b.row_ptr), d(b.col_idx), d(b.col_ptr), d(b.row_idx)
+    out_d2 = torch.empty(g.n, dtype=torch.int32, device=dev)
+    out_pd2 = torch.empty(b.n_cols, dtype=torch.int32, device=dev)
+    params = gc.Params(flags=gc.COLOR_FLAG_KERNEL_TIMING)
+
+    def step():
+        _, s1 = gc.color_d2(grp, gci, seed=1, out=out_d2, params=params)
+        _, s2 = gc.color_pd2(brp, bci, bcp, bri, seed=1, out=out_pd2, params=params)
+        return s1, s2
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    times, stats = [], []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats.append(step())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"[bench] step {i}: {times[-1] * 1e3:.1f} ms")
+    tm = sum(times) / len(times)
+    kern, graphs = {}, {}
+    for s1, s2 in stats:
+        for name, st, nnz, deg, mode in (("stencil7_96_d2", s1, g.nnz, g.nnz / g.n, "D2"),
+                                         ("pd2_4m_1m", s2, b.nnz, b.nnz / b.n_cols, "PD2")):
+            if st.engine == gc.ENGINE_INCREMENTAL:
+                names, (cb, db) = ("inc_color_kernel", "inc_detect_kernel"), (st.color_bytes, st.detect_bytes)
+            else:
+                names = (f"color_round_kernel<{mode}>", f"detect_round_kernel<{mode}>")
+                cb, db = pull_two_hop_bytes(st, deg)
+            for kname, byts, ns, nl in ((names[0], cb, st.color_kernel_ns, st.color_launches),
+                                        (names[1], db, st.detect_kernel_ns, st.detect_launches)):
+                acc = kern.setdefault(kname, [0, 0, 0])
+                acc[0] += byts
+                acc[1] += ns
+                acc[2] += nl
+            pg = graphs.setdefault(name, {"nnz": nnz, "colors": st.num_colors, "rounds": st.rounds,
+                                          "edge_visits": st.edge_visits, "vertex_visits": st.vertex_visits,
+                                          "engine": {1: "pull", 2: "incremental"}.get(st.engine, "?"),
+                                          "kernel_ms": 0.0})
+            pg["kernel_ms"] += (st.color_kernel_ns + st.detect_kernel_ns) / 1e6 / args.steps
+    dom = max(kern, key=lambda k: kern[k][1])
+    byts, ns, launches = kern[dom]
+    achieved = byts / ns if ns else 0.0
+    return {
+        "metric": "edges colored/s (D2 + PD2)",
+        "value": round((g.nnz + b.nnz) / tm, 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(tm * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "D2 on 7-pt stencil 96^3 + PD2 (columns) on 4,000,000 x 1,000,000 power-law pattern, "
+                               "8 columns per row, gamma 2.1; seed 1", "graphs": graphs},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom),
+                     "avg_launch_us": round(ns / max(launches, 1) / 1e3, 3),
+                     "alg_bytes_per_launch": int(byts / max(launches, 1))},
+        "cpu_baseline": None,
     }
 
 
@@ -406,7 +501,7 @@ def bench_ghost(args, torch, gc, dev):
 
     import graphgen as gg
     t = time.time()
-    g = gg.rmat(args.ghost_scale, 16, seed=1)
+    g = gg.rmat(args.ghost_scale, 16, seed=1, progress=lambda m: log(f"[bench] {m} ({time.time() - t:.0f}s)"))
     delta = int(g.degrees().max())
     log(f"[bench] rmat s{args.ghost_scale}: n={g.n} nnz={g.nnz} maxdeg={delta} ({time.time() - t:.1f}s)")
     owner = gg.hash_partition(g.n, 16, seed=7)
@@ -414,7 +509,8 @@ def bench_ghost(args, torch, gc, dev):
     res = {}
     for layers in (1, 2):
         t = time.time()
-        lg = gg.ghost_local_graph(g, owner, 0, layers, gcol)
+        log(f"[bench] building part 0 with {layers} ghost layer(s)")
+        lg = gg.ghost_local_graph(g, owner, 0, layers, gcol, sort_rows=False)
         log(f"[bench] part 0, {layers} layer(s): owned {lg.n_owned}, ghosts {lg.n_ghost} (G1 {lg.n_g1}), "
             f"local nnz {lg.nnz} ({time.time() - t:.1f}s)")
         rp, ci, gid, gco = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -545,7 +641,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="d1", choices=["d1", "batch", "serve", "ghost"])
+    ap.add_argument("--workload", default="d1", choices=["d1", "d2pd2", "batch", "serve", "ghost"])
     ap.add_argument("--ghost-scale", type=int, default=24, help="ghost: R-MAT scale of the partitioned graph")
     ap.add_argument("--jobs", type=int, default=300, help="batch/serve: jobs in the stream")
     ap.add_argument("--n-max", type=float, default=3e4, help="batch/serve: largest job size (vertices)")
@@ -579,6 +675,8 @@ def main():
         out = bench_serve(args, torch, gc, dev)
     elif args.workload == "ghost":
         out = bench_ghost(args, torch, gc, dev)
+    elif args.workload == "d2pd2":
+        out = bench_d2pd2(args, torch, gc, dev)
     else:
         out = bench_d1(args, torch, gc, dev)
     print(json.dumps(out))

@@ -263,7 +263,7 @@ def stencil(dims, points: int) -> Graph:
 
 
 def rmat(scale: int, edge_factor: int, seed: int, a: float = 0.57, b: float = 0.19,
-         c: float = 0.19, permute: bool = True, chunk: int = 1 << 24) -> Graph:
+         c: float = 0.19, permute: bool = True, chunk: int = 1 << 24, progress=None) -> Graph:
     """R-MAT (Chakrabarti et al.) with m = edge_factor * 2^scale samples, no
     noise, a seeded vertex-id permutation (Graph500 practice), then the
     Section 4 preprocessing: self-loops dropped, symmetrized, deduplicated.
@@ -288,6 +288,8 @@ def rmat(scale: int, edge_factor: int, seed: int, a: float = 0.57, b: float = 0.
         us.append(u)
         vs.append(v)
         done += k
+        if progress:
+            progress(f"rmat s{scale}: {done}/{m} samples")
     u = np.concatenate(us)
     v = np.concatenate(vs)
     del us, vs
@@ -295,6 +297,8 @@ def rmat(scale: int, edge_factor: int, seed: int, a: float = 0.57, b: float = 0.
         perm = rng.permutation(n).astype(np.int64)
         u = perm[u]
         v = perm[v]
+    if progress:
+        progress(f"rmat s{scale}: building the CSR")
     return csr_from_pairs(n, u, v, True, f"RMAT(s={scale},ef={edge_factor})")
 
 
@@ -401,7 +405,7 @@ class LocalGraph:
 
 
 def ghost_local_graph(g: Graph, owner: np.ndarray, part: int, layers: int,
-                      global_colors: np.ndarray) -> LocalGraph:
+                      global_colors: np.ndarray, sort_rows: bool = True) -> LocalGraph:
     assert layers in (1, 2)
     rp = g.row_ptr.astype(np.int64)
     owned = np.nonzero(owner == part)[0].astype(np.int64)
@@ -426,10 +430,11 @@ def ghost_local_graph(g: Graph, owner: np.ndarray, part: int, layers: int,
     ridx = np.repeat(rp[row_vertices], d) + (np.arange(d.sum()) - np.repeat(np.cumsum(d) - d, d))
     lcol = local[g.col[ridx].astype(np.int64)]
     assert np.all(lcol >= 0)
-    # rows sorted by local id
-    src = np.repeat(np.arange(row_vertices.size, dtype=np.int64), d)
-    order = np.lexsort((lcol, src))
-    lcol = lcol[order].astype(np.int32)
+    if sort_rows:  # columns of every row in increasing local id
+        src = np.repeat(np.arange(row_vertices.size, dtype=np.int64), d)
+        order = np.lexsort((lcol, src))
+        lcol = lcol[order]
+    lcol = lcol.astype(np.int32)
     row_ptr = np.zeros(row_vertices.size + 1, dtype=np.int64)
     np.cumsum(d, out=row_ptr[1:])
     n_g = gid.size - n_o

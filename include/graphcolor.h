@@ -106,7 +106,8 @@ typedef struct color_params {
     int32_t bin_hi[4];      /* work bounds of degree bins 0..3 (bin 4 = above bin_hi[3]) */
     int32_t lanes[3];       /* lanes per vertex of bins 0..2: 1,2,4,8,16,32 or 64 */
     int32_t split_chunks;   /* workgroups per vertex in bin 4 */
-    int32_t max_rounds;     /* stop after this many rounds: COLOR_ENOCONVERGE */
+    int32_t max_rounds;     /* stop after this many rounds: COLOR_ENOCONVERGE (0: n + 1, which
+                               no run reaches: each round commits at least one vertex) */
     int32_t rounds_per_poll;/* rounds enqueued between host checks of the worklist size */
     int32_t tail_threshold; /* worklist size below which the tail kernel finishes the call */
     int32_t max_workgroups; /* cap on the grid of the round kernels */

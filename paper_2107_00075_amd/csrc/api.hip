@@ -71,7 +71,7 @@ void Workspace::release() {
   events.clear();
   for (DevBuf* b : {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
                     &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
-                    &inc_F, &inc_L0, &inc_B0, &scan_tmp})
+                    &inc_F, &inc_L0, &inc_B0, &inc_bm, &scan_tmp})
     b->release();
   if (host) (void)hipHostFree(host);
   host = nullptr;
@@ -305,6 +305,10 @@ int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, 
                int32_t n_total) {
   int e = merge_params(mode, user, &c.P);
   if (e) return e;
+  // Every round commits at least the worklist vertex of highest key, so no
+  // run needs more than n rounds; the default cap turns a defect into
+  // COLOR_ENOCONVERGE instead of an endless loop.
+  if (c.P.max_rounds == 0) c.P.max_rounds = n_total < INT_MAX ? n_total + 1 : INT_MAX;
   c.st = static_cast<hipStream_t>(stream);
   c.ws = workspace_for_current_device(&e);
   if (!c.ws) return e;
@@ -466,6 +470,13 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
                           c.st);
     c.launches += 2;
     A0 = B;
+    const int32_t words = n / 32 + 1;
+    const int grid = dedup_grid(words);
+    const size_t bm_bytes = sizeof(uint32_t) * static_cast<size_t>(words) * static_cast<size_t>(grid);
+    if ((e = w->inc_bm.ensure(bm_bytes, false, c.st))) return e;
+    if (hipMemsetAsync(w->inc_bm.p, 0, bm_bytes, c.st) != hipSuccess) return COLOR_EHIP;
+    launch_inc_dedup(n, aoff, Lb, B, w->inc_bm.as<uint32_t>(), words, grid, c.st);
+    c.launches += 1;
   }
   IncBufs ib;
   ib.C = colors;
@@ -480,6 +491,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   ib.trace = w->trace.as<int32_t>();
   ib.trace_cap = c.trace_cap;
   ib.rounds_done = &S->rounds_done;
+
   if (init) {
     IncBufs pb = ib;
     pb.alen_in = Lb;

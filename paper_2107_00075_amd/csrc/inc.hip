@@ -187,7 +187,7 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round
     const int32_t len = ld_dev(&b.alen_in[v]);
     const int32_t* A = b.A_in + base;
     bool lose = false;
-    int32_t read = 0;
+    int32_t read = 0, gath = 0;
     for (int32_t e0 = sub; e0 < len && !lose; e0 += 4 * G) {
       int32_t u[4], t[4];
 #pragma unroll
@@ -197,13 +197,17 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round
         read += e < len ? 1 : 0;
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) t[j] = (u[j] >= 0 && key_of(k, u[j]) > kv) ? ld_dev(&b.T[u[j]]) : -1;
+      for (int j = 0; j < 4; ++j) {
+        const bool higher = u[j] >= 0 && key_of(k, u[j]) > kv;
+        t[j] = higher ? ld_dev(&b.T[u[j]]) : -1;
+        gath += higher ? 1 : 0;
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         if (t[j] == tv) lose = true;
     }
     lose = group_any<G>(lose);
-    if (lose) bytes += 8ull * static_cast<uint64_t>(read);  // the entries this lane scanned
+    bytes += 4ull * static_cast<uint64_t>(read + gath);  // list entries and tentative colors this lane read
     if (lose && !compact_now(b, round, v)) {
       if (sub == 0) {
         s_ent[idx] = v;
@@ -250,7 +254,7 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round
         st_dev(&b.C[v], tv);
         maxc_acc = max(maxc_acc, tv);
         s_ent[idx] = -1;
-        bytes += 16 + 16ull * static_cast<uint64_t>(len) + 4;
+        bytes += 20 + 8ull * static_cast<uint64_t>(len);  // own fields, C write, the push pass
       }
     }
   }
@@ -293,26 +297,32 @@ __device__ void inc_detect_block(const KeySource& k, const IncBufs& b, int round
   const int32_t* A = b.A_in + base;
   constexpr int32_t step = kBlock * kIncBatch;
   bool lose = false;
+  uint32_t read = 0;
   for (int32_t e0 = 0; e0 < len; e0 += step) {
     int32_t u[kIncBatch], t[kIncBatch];
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j) {
       const int32_t e = e0 + j * kBlock + tid;
       u[j] = e < len ? ld_dev(&A[e]) : -1;
+      read += e < len ? 1u : 0u;
     }
     // only a higher-key neighbour can beat v: compare keys first and read
     // the tentative colors of those neighbours only
 #pragma unroll
-    for (int j = 0; j < kIncBatch; ++j) t[j] = (u[j] >= 0 && key_of(k, u[j]) > kv) ? ld_dev(&b.T[u[j]]) : -1;
+    for (int j = 0; j < kIncBatch; ++j) {
+      const bool higher = u[j] >= 0 && key_of(k, u[j]) > kv;
+      t[j] = higher ? ld_dev(&b.T[u[j]]) : -1;
+      read += higher ? 1u : 0u;
+    }
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j)
       if (t[j] == tv) lose = true;
     if (__syncthreads_or(lose)) {
       lose = true;
-      if (tid == 0) bytes += 8ull * static_cast<uint64_t>(min(len, e0 + step));
       break;
     }
   }
+  bytes += 4ull * read;  // list entries and tentative colors this thread read
   if (lose && !compact_now(b, round, v)) {
     if (tid == 0) {
       const int32_t p = atomicAdd(&b.cnt_out[bin], 1);
@@ -380,7 +390,7 @@ __device__ void inc_detect_block(const KeySource& k, const IncBufs& b, int round
     if (tid == 0) {
       st_dev(&b.C[v], tv);
       maxc_acc = max(maxc_acc, tv);
-      bytes += 16 + 16ull * static_cast<uint64_t>(len) + 4;
+      bytes += 20 + 8ull * static_cast<uint64_t>(len);  // own fields, C write, the push pass
     }
   }
   __syncthreads();
@@ -603,6 +613,72 @@ void launch_inc_sizes(const GraphView& g, const int32_t* work, int32_t* len, int
     hipLaunchKernelGGL(inc_sizes_kernel<MODE>, dim3(blocks_for(g.n)), dim3(kBlock), 0, st, g, work, len, words,
                        alen0, total);
 }
+// Duplicates of the materialized two-hop lists (a column pair sharing
+// several rows, a vertex reachable through several middle vertices) are
+// removed once per call from every list longer than kDedupMin entries: the
+// lists are sets, so the colorings do not change.  A workgroup walks one long
+// list at a time with its own bitmap of the id range; an entry is kept when
+// its atomic OR finds the bit clear.  The list is compacted in place (each
+// step's entries are read before the barrier that precedes its writes), then
+// the bits of the kept entries are cleared again.
+constexpr int32_t kDedupMin = 4096;
+
+__global__ __launch_bounds__(kBlock) void inc_dedup_kernel(int32_t n, const int32_t* aoff, int32_t* alen,
+                                                           int32_t* A, uint32_t* bitmaps, int32_t words) {
+  __shared__ int32_t s_wc[kWavesPerBlock];
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  uint32_t* bm = bitmaps + static_cast<size_t>(blockIdx.x) * static_cast<size_t>(words);
+  constexpr int32_t step = kBlock * kIncBatch;
+  for (int32_t v = blockIdx.x; v < n; v += gridDim.x) {
+    const int32_t len = ld_dev(&alen[v]);
+    if (len <= kDedupMin) continue;
+    int32_t* L = A + ld_dev(&aoff[v]);
+    int32_t kept = 0;
+    for (int32_t e0 = 0; e0 < len; e0 += step) {
+      int32_t x[kIncBatch];
+      bool keep[kIncBatch];
+      int32_t cnt = 0;
+#pragma unroll
+      for (int j = 0; j < kIncBatch; ++j) {
+        const int32_t e = e0 + j * kBlock + tid;
+        x[j] = e < len ? ld_dev(&L[e]) : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < kIncBatch; ++j) {
+        keep[j] = false;
+        if (x[j] >= 0) {
+          const uint32_t bit = 1u << (x[j] & 31);
+          keep[j] = (atomicOr(&bm[x[j] >> 5], bit) & bit) == 0u;
+        }
+        cnt += keep[j] ? 1 : 0;
+      }
+      int32_t incl = cnt;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, kWave);
+        if (lane_id() >= o) incl += y;
+      }
+      if (lane_id() == kWave - 1) s_wc[wave] = incl;
+      __syncthreads();
+      int32_t pos = kept + incl - cnt;
+      int32_t tot = 0;
+      for (int w = 0; w < kWavesPerBlock; ++w) {
+        if (w < wave) pos += s_wc[w];
+        tot += s_wc[w];
+      }
+#pragma unroll
+      for (int j = 0; j < kIncBatch; ++j)
+        if (keep[j]) st_dev(&L[pos++], x[j]);
+      kept += tot;
+      __syncthreads();
+    }
+    for (int32_t e = tid; e < kept; e += kBlock) st_dev(&bm[ld_dev(&L[e]) >> 5], 0u);
+    if (tid == 0) st_dev(&alen[v], kept);
+    __syncthreads();
+  }
+}
+
 template <int MODE>
 void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A,
                      const int32_t* deferred, const int32_t* nd, int32_t* grab, hipStream_t st) {
@@ -611,6 +687,18 @@ void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len
   hipLaunchKernelGGL(inc_fill_heavy_kernel<MODE>, dim3(std::min(blocks_for(g.n), 512)), dim3(kBlock), 0, st, g,
                      aoff, len, A, deferred, nd, grab);
 }
+int dedup_grid(int32_t words) {
+  const size_t per = sizeof(uint32_t) * static_cast<size_t>(words);
+  const size_t cap = static_cast<size_t>(256) << 20;  // bitmaps of all workgroups together
+  return static_cast<int>(std::max<size_t>(8, std::min<size_t>(256, cap / std::max<size_t>(per, 1))));
+}
+
+void launch_inc_dedup(int32_t n, const int32_t* aoff, int32_t* alen, int32_t* A, uint32_t* bitmaps, int32_t words,
+                      int grid, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(inc_dedup_kernel, dim3(grid), dim3(kBlock), 0, st, n, aoff, alen, A, bitmaps, words);
+}
+
 void launch_inc_init_push(const IncBufs& b, int32_t n, const int32_t* A0, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(inc_init_push_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, n, A0);
 }

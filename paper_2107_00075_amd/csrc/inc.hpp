@@ -39,6 +39,11 @@ template <int MODE>
 void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A,
                      const int32_t* deferred, const int32_t* nd, int32_t* grab, hipStream_t st);
 void launch_inc_init_push(const IncBufs& b, int32_t n, const int32_t* A0, hipStream_t st);
+// Removes duplicates from the long two-hop lists (alen in: capacity, out:
+// distinct entries); bitmaps: grid x words zeroed uint32 (left zeroed).
+int dedup_grid(int32_t words);
+void launch_inc_dedup(int32_t n, const int32_t* aoff, int32_t* alen, int32_t* A, uint32_t* bitmaps, int32_t words,
+                      int grid, hipStream_t st);
 int resident_inc_blocks();
 
 // Exclusive prefix sum of n+1 int32 values (the last input is 0, so out[n] is
