@@ -235,6 +235,11 @@ typedef struct color_job {
  *            validated first).  Bins and lanes come from the autotuner's
  *            per-device record for the job's kind and average degree class
  *            (library defaults until color_autotune has run).
+ * D2/PD2 jobs whose two-hop walk per visit is long (>= 128 entries,
+ * estimated from nnz/n) are colored after the persistent launch by the
+ * single-graph call of their kind, whose incremental engine serves them
+ * better than the launch's pull-style steps (their stats say so in
+ * `engine`); every other job shares the one persistent launch.
  * The library allocates 16 bytes per vertex of workspace (grow-only, per
  * device).  Returns COLOR_OK, COLOR_EINVAL, COLOR_EOVERFLOW, COLOR_EGRAPH,
  * COLOR_ENOMEM, COLOR_EHIP or the first job's COLOR_ENOCONVERGE. */

@@ -623,10 +623,13 @@ static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32
     c.P = saved;
     if (e) return e;
     // library choice: the incremental engine pays off when the work is
-    // concentrated in a few vertices that would be rescanned every round
+    // concentrated in a few vertices that would be rescanned every round, or
+    // when two-hop walks are long (dense D2/PD2: every revisit of a vertex
+    // would re-walk thousands of entries; measured 2-12x faster)
     const double avg = static_cast<double>(c.H->total_work) / std::max<int64_t>(1, n);
     const bool skewed = c.H->max_work > 64 && c.H->max_work > 16.0 * std::max(1.0, avg);
-    if (c.P.engine == COLOR_ENGINE_INCREMENTAL || skewed) {
+    const bool long_walks = MODE != kD1 && avg >= 128.0;
+    if (c.P.engine == COLOR_ENGINE_INCREMENTAL || skewed || long_walks) {
       int fell_back = 0;
       const int rc = run_incremental<MODE>(c, g, k, init, colors, L, known, &fell_back);
       if (!fell_back) {

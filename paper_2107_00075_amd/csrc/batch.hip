@@ -458,6 +458,15 @@ __global__ void unpark_kernel(BatchJob* jobs, uint64_t* words, int32_t num_jobs,
   store_word(&words[j], phase_word(static_cast<uint32_t>(e), static_cast<uint32_t>(ld_dev(&J->parked_units)), 0));
 }
 
+// First-hop nnz of every job (row_ptr[n] of its hop-1 array).
+__global__ void job_nnz_kernel(const BatchJob* jobs, int32_t num_jobs, int32_t* out) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= num_jobs) return;
+  const BatchJob* J = &jobs[j];
+  const int32_t n = ld_dev(&J->n);
+  out[j] = n > 0 ? ld_dev(&ld_ptr(&J->rp)[n]) : 0;
+}
+
 int launch_batch(BatchJob* jobs, uint64_t* words, int32_t num_jobs, int32_t active, int32_t* retired,
                  const BatchTune* tune, int grid, bool coherent_graph, hipStream_t st) {
   if (coherent_graph)
@@ -530,11 +539,11 @@ void tune_table_for_device(BatchTune* t) {
 
 struct BatchWorkspace {
   std::mutex mu;
-  DevBuf table, words, ctr, tune, arrays;
+  DevBuf table, words, ctr, tune, arrays, nnz;
   BatchJob* host = nullptr;  // pinned staging of the job table
   size_t host_cap = 0;
   ~BatchWorkspace() {
-    for (DevBuf* b : {&table, &words, &ctr, &tune, &arrays}) b->release();
+    for (DevBuf* b : {&table, &words, &ctr, &tune, &arrays, &nnz}) b->release();
     if (host) (void)hipHostFree(host);
   }
 };
@@ -624,12 +633,23 @@ void job_stats(const BatchJob& J, color_stats* st) {
   st->detect_bytes = 0;
 }
 
-}  // namespace gcol
+// Two-hop walk per visit that makes a job better served by the single-graph
+// incremental engine than by the persistent kernel's pull steps (the same
+// bound as the single-graph engine choice).
+constexpr double kLongWalk = 128.0;
 
-using namespace gcol;
+// A job's average two-hop walk, from its sizes: D2 deg (deg + 1), PD2
+// (column degree)(1 + row degree), with average degrees (a lower bound of
+// the true average, by convexity).  D1: 0.
+double estimated_walk(const color_job& j, int32_t nnz) {
+  if (j.kind == COLOR_KIND_D1 || j.n <= 0) return 0.0;
+  const double d = static_cast<double>(nnz) / j.n;
+  if (j.kind == COLOR_KIND_D2) return d * (d + 1.0);
+  return d * (1.0 + static_cast<double>(nnz) / std::max(j.n_rows, 1));
+}
 
-extern "C" int color_batch(int32_t num_jobs, const color_job* jobs, color_stats* per_job,
-                           const color_params* params, void* stream) {
+int run_batch(int32_t num_jobs, const color_job* jobs, color_stats* per_job, const color_params* params,
+                     void* stream, bool route_long_walks) {
   if (num_jobs < 0 || (num_jobs > 0 && !jobs)) return COLOR_EINVAL;
   int e = COLOR_OK;
   for (int i = 0; i < num_jobs; ++i)
@@ -645,65 +665,114 @@ extern "C" int color_batch(int32_t num_jobs, const color_job* jobs, color_stats*
   hipStream_t st = static_cast<hipStream_t>(stream);
   BatchWorkspace* w = batch_workspace(&e);
   if (!w) return e;
-  std::lock_guard<std::mutex> lk(w->mu);
-
-  int64_t total = 0;
-  for (int i = 0; i < num_jobs; ++i) total += 4 * batch_stride(jobs[i].n);
-  const size_t nj = static_cast<size_t>(num_jobs);
-  if ((e = w->arrays.ensure(sizeof(int32_t) * static_cast<size_t>(total), false, st))) return e;
-  if ((e = w->table.ensure(sizeof(BatchJob) * nj, false, st))) return e;
-  if ((e = w->words.ensure(sizeof(uint64_t) * nj, false, st))) return e;
-  if ((e = w->ctr.ensure(256, false, st))) return e;
-  if ((e = w->tune.ensure(sizeof(BatchTune) * 3 * kTuneClasses, false, st))) return e;
-  const size_t host_bytes = sizeof(BatchJob) * nj + sizeof(uint64_t) * nj + sizeof(BatchTune) * 3 * kTuneClasses;
-  if (w->host_cap < host_bytes) {
-    if (w->host) (void)hipHostFree(w->host);
-    w->host = nullptr;
-    w->host_cap = 0;
-    if (hipHostMalloc(reinterpret_cast<void**>(&w->host), host_bytes, hipHostMallocDefault) != hipSuccess)
-      return COLOR_ENOMEM;
-    w->host_cap = host_bytes;
-  }
-  BatchJob* hj = w->host;
-  uint64_t* hw = reinterpret_cast<uint64_t*>(hj + nj);
-  BatchTune* ht = reinterpret_cast<BatchTune*>(hw + nj);
-  int32_t* base = w->arrays.as<int32_t>();
-  int32_t active = 0;
-  int64_t units0 = 0;
-  for (int i = 0; i < num_jobs; ++i) {
-    fill_job(jobs[i], max_rounds, base, &hj[i]);
-    base += 4 * batch_stride(jobs[i].n);
-    hw[i] = initial_word(jobs[i].n);
-    if (jobs[i].n > 0) {
-      ++active;
-      units0 += (jobs[i].n + kBlock - 1) / kBlock;
+  std::vector<int> routed;  // jobs for the single-graph engine
+  {
+    std::lock_guard<std::mutex> lk(w->mu);
+    int64_t total = 0;
+    bool two_hop = false;
+    for (int i = 0; i < num_jobs; ++i) {
+      total += 4 * batch_stride(jobs[i].n);
+      two_hop = two_hop || (jobs[i].kind != COLOR_KIND_D1 && jobs[i].n > 0);
     }
+    const size_t nj = static_cast<size_t>(num_jobs);
+    if ((e = w->arrays.ensure(sizeof(int32_t) * static_cast<size_t>(total), false, st))) return e;
+    if ((e = w->table.ensure(sizeof(BatchJob) * nj, false, st))) return e;
+    if ((e = w->words.ensure(sizeof(uint64_t) * nj, false, st))) return e;
+    if ((e = w->nnz.ensure(sizeof(int32_t) * nj, false, st))) return e;
+    if ((e = w->ctr.ensure(256, false, st))) return e;
+    if ((e = w->tune.ensure(sizeof(BatchTune) * 3 * kTuneClasses, false, st))) return e;
+    const size_t host_bytes = sizeof(BatchJob) * nj + sizeof(uint64_t) * nj + sizeof(int32_t) * nj +
+                              sizeof(BatchTune) * 3 * kTuneClasses;
+    if (w->host_cap < host_bytes) {
+      if (w->host) (void)hipHostFree(w->host);
+      w->host = nullptr;
+      w->host_cap = 0;
+      if (hipHostMalloc(reinterpret_cast<void**>(&w->host), host_bytes, hipHostMallocDefault) != hipSuccess)
+        return COLOR_ENOMEM;
+      w->host_cap = host_bytes;
+    }
+    BatchJob* hj = w->host;
+    uint64_t* hw = reinterpret_cast<uint64_t*>(hj + nj);
+    int32_t* hn = reinterpret_cast<int32_t*>(hw + nj);
+    BatchTune* ht = reinterpret_cast<BatchTune*>(hn + nj);
+    int32_t* base = w->arrays.as<int32_t>();
+    for (int i = 0; i < num_jobs; ++i) {
+      fill_job(jobs[i], max_rounds, base, &hj[i]);
+      base += 4 * batch_stride(jobs[i].n);
+      hw[i] = initial_word(jobs[i].n);
+    }
+    tune_table_for_device(ht);
+    if (hipMemcpyAsync(w->table.p, hj, sizeof(BatchJob) * nj, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(w->tune.p, ht, sizeof(BatchTune) * 3 * kTuneClasses, hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemsetAsync(w->ctr.p, 0, 256, st) != hipSuccess)
+      return COLOR_EHIP;
+    if (route_long_walks && two_hop) {
+      hipLaunchKernelGGL(job_nnz_kernel, dim3((num_jobs + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                         w->table.as<BatchJob>(), num_jobs, w->nnz.as<int32_t>());
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(hn, w->nnz.p, sizeof(int32_t) * nj, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return COLOR_EHIP;
+      for (int i = 0; i < num_jobs; ++i) {
+        if (estimated_walk(jobs[i], hn[i]) >= kLongWalk) {
+          routed.push_back(i);
+          hw[i] = 0;  // no open phase: the persistent kernel never takes it
+        }
+      }
+    }
+    int32_t active = 0;
+    int64_t units0 = 0;
+    for (int i = 0; i < num_jobs; ++i) {
+      if (hw[i] != 0) {
+        ++active;
+        units0 += (jobs[i].n + kBlock - 1) / kBlock;
+      }
+    }
+    if (hipMemcpyAsync(w->words.p, hw, sizeof(uint64_t) * nj, hipMemcpyHostToDevice, st) != hipSuccess)
+      return COLOR_EHIP;
+    if (active > 0) {
+      int grid = batch_resident_blocks();
+      if (params && params->max_workgroups > 0) grid = std::min(grid, params->max_workgroups);
+      grid = static_cast<int>(std::min<int64_t>(grid, std::max<int64_t>(8, (units0 + 7) / 8 * 8)));
+      if ((e = launch_batch(w->table.as<BatchJob>(), w->words.as<uint64_t>(), num_jobs, active,
+                            w->ctr.as<int32_t>(), w->tune.as<BatchTune>(), grid, false, st)))
+        return e;
+    }
+    if (hipMemcpyAsync(hj, w->table.p, sizeof(BatchJob) * nj, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return COLOR_EHIP;
+    int rc = COLOR_OK;
+    for (int i = 0; i < num_jobs; ++i) {
+      if (hw[i] == 0 && jobs[i].n > 0) continue;  // routed
+      if (per_job) job_stats(hj[i], &per_job[i]);
+      if (rc == COLOR_OK && hj[i].status == kJobFinished && hj[i].rc != COLOR_OK) rc = hj[i].rc;
+    }
+    if (rc != COLOR_OK) return rc;
   }
-  tune_table_for_device(ht);
-  if (hipMemcpyAsync(w->table.p, hj, sizeof(BatchJob) * nj, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(w->words.p, hw, sizeof(uint64_t) * nj, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(w->tune.p, ht, sizeof(BatchTune) * 3 * kTuneClasses, hipMemcpyHostToDevice, st) !=
-          hipSuccess ||
-      hipMemsetAsync(w->ctr.p, 0, 256, st) != hipSuccess)
-    return COLOR_EHIP;
-  if (active > 0) {
-    int grid = batch_resident_blocks();
-    if (params && params->max_workgroups > 0) grid = std::min(grid, params->max_workgroups);
-    grid = static_cast<int>(std::min<int64_t>(grid, std::max<int64_t>(8, (units0 + 7) / 8 * 8)));
-    if ((e = launch_batch(w->table.as<BatchJob>(), w->words.as<uint64_t>(), num_jobs, active,
-                          w->ctr.as<int32_t>(), w->tune.as<BatchTune>(), grid, false, st)))
-      return e;
+  // jobs with long two-hop walks: the single-graph calls (their engine choice
+  // takes the incremental engine for them)
+  for (int i : routed) {
+    const color_job& j = jobs[i];
+    color_stats* sp = per_job ? &per_job[i] : nullptr;
+    if (j.kind == COLOR_KIND_D2)
+      e = color_d2(j.n, j.row_ptr, j.col_idx, j.seed, nullptr, nullptr, j.colors, sp, params, stream);
+    else
+      e = color_pd2(j.n_rows, j.n, j.row_ptr, j.col_idx, j.col_ptr, j.row_idx, j.seed, nullptr, nullptr, j.colors,
+                    sp, params, stream);
+    if (e) return e;
   }
-  if (hipMemcpyAsync(hj, w->table.p, sizeof(BatchJob) * nj, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return COLOR_EHIP;
-  int rc = COLOR_OK;
-  for (int i = 0; i < num_jobs; ++i) {
-    if (per_job) job_stats(hj[i], &per_job[i]);
-    if (rc == COLOR_OK && hj[i].status == kJobFinished && hj[i].rc != COLOR_OK) rc = hj[i].rc;
-  }
-  return rc;
+  return COLOR_OK;
 }
+
+}  // namespace gcol
+
+extern "C" int color_batch(int32_t num_jobs, const color_job* jobs, color_stats* per_job,
+                           const color_params* params, void* stream) {
+  return gcol::run_batch(num_jobs, jobs, per_job, params, stream, true);
+}
+
+using namespace gcol;
 
 namespace {
 
@@ -761,7 +830,7 @@ extern "C" int color_autotune(const color_job* job, int32_t reps, color_params* 
     double t_min = 1e300;
     for (int r = 0; r < reps && e == COLOR_OK; ++r) {
       const auto t0 = std::chrono::steady_clock::now();
-      e = color_batch(1, job, nullptr, nullptr, stream);
+      e = run_batch(1, job, nullptr, nullptr, stream, false);
       const auto t1 = std::chrono::steady_clock::now();
       t_min = std::min(t_min, std::chrono::duration<double>(t1 - t0).count());
     }

@@ -99,7 +99,8 @@ def test_batch_mixed_stream_vs_oracle_and_single(gc):
     for i, (s, o, st) in enumerate(zip(specs, outs, stats)):
         got = o.cpu().numpy()
         what = f"job {i} kind {s.kind} {s.family} n={s.graph.n}"
-        assert st.engine == gc.ENGINE_BATCH
+        # jobs with long two-hop walks go to the single-graph incremental engine
+        assert st.engine == gc.ENGINE_BATCH or (s.kind != 1 and st.engine == gc.ENGINE_INCREMENTAL)
         if oracle_ok(s):
             r = ref_of(s)
             check_same(got, st, r.colors, r, what + " vs oracle")

@@ -358,8 +358,13 @@ def test_device_buffers_rewritten_between_calls(gc):
 
 def test_library_engine_choice(gc):
     """The library's own choice: pull on regular meshes, incremental on skewed
-    graphs; both give the oracle's coloring."""
+    graphs and on long two-hop walks; both give the oracle's coloring."""
     for g, want in ((gg.stencil((24, 20, 16), 27), 1), (gg.rmat(14, 16, 2), 2)):
         colors, st = gc.color_d1(dev(g.row_ptr), dev(g.col), seed=5)
         assert st.engine == want
         assert np.array_equal(colors.cpu().numpy(), oracle.color_d1(g, seed=5).colors)
+    # D2: short two-hop walks (7-point stencil) pull, long ones (ER, mean degree 20) incremental
+    for g, want in ((gg.stencil((20, 18, 16), 7), 1), (gg.erdos_renyi(1500, 20.0, 4), 2)):
+        colors, st = gc.color_d2(dev(g.row_ptr), dev(g.col), seed=5)
+        assert st.engine == want
+        assert np.array_equal(colors.cpu().numpy(), oracle.color_d2(g, seed=5).colors)
