@@ -15,10 +15,12 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "api_internal.hpp"
@@ -96,6 +98,7 @@ struct ServedJob {
   size_t arena_off = 0;
   int32_t slot = -1;
   hipEvent_t ev = nullptr;  // copy in / copy out
+  bool heavy = false;       // long two-hop walks: the single-graph engine's lane
 };
 
 }  // namespace
@@ -123,6 +126,14 @@ struct color_server {
   bool in_flight = false;
   hipEvent_t epoch_done = nullptr;
   int error = COLOR_OK;
+  // heavy lane: jobs with long two-hop walks, colored one at a time by the
+  // single-graph calls (incremental engine) on their own stream and thread
+  std::deque<uint64_t> heavy_queue;
+  std::thread heavy_thread;
+  std::condition_variable heavy_cv;  // wakes the heavy lane
+  std::condition_variable done_cv;   // a heavy job finished
+  hipStream_t heavy_stream = nullptr;
+  bool stopping = false;
 };
 
 namespace {
@@ -339,7 +350,103 @@ bool busy(const color_server* s) {
   return false;
 }
 
+// Two-hop walk per visit above which a job goes to the heavy lane (the same
+// bound as the single-graph engine choice and color_batch).
+constexpr double kLongWalk = 128.0;
+
+double job_walk(const color_job& j, int32_t nnz) {
+  if (j.kind == COLOR_KIND_D1 || j.n <= 0) return 0.0;
+  const double d = static_cast<double>(nnz) / j.n;
+  if (j.kind == COLOR_KIND_D2) return d * (d + 1.0);
+  return d * (1.0 + static_cast<double>(nnz) / std::max(j.n_rows, 1));
+}
+
+// Copies a heavy job in, colors it with the single-graph call of its kind
+// and copies the colors out, all on the heavy lane's stream.
+int run_heavy(color_server* s, ServedJob& J) {
+  char* p = s->arena_base + J.arena_off;
+  const int32_t* h = J.h_in;
+  auto put = [&](size_t entries) {
+    int32_t* d = reinterpret_cast<int32_t*>(p);
+    p += align_up(sizeof(int32_t) * entries);
+    if (entries && hipMemcpyAsync(d, h, sizeof(int32_t) * entries, hipMemcpyHostToDevice, s->heavy_stream) !=
+                       hipSuccess)
+      return static_cast<int32_t*>(nullptr);
+    h += entries;
+    return d;
+  };
+  color_job& d = J.desc;
+  const int32_t* rp = put(static_cast<size_t>(J.n_csr_rows) + 1);
+  const int32_t* ci = put(static_cast<size_t>(J.nnz));
+  if (!rp || (J.nnz > 0 && !ci)) return COLOR_EHIP;
+  const int32_t* cp = nullptr;
+  const int32_t* ri = nullptr;
+  if (d.kind == COLOR_KIND_PD2) {
+    cp = put(static_cast<size_t>(d.n) + 1);
+    ri = put(static_cast<size_t>(J.nnz));
+    if (!cp || (J.nnz > 0 && !ri)) return COLOR_EHIP;
+  }
+  int32_t* colors = reinterpret_cast<int32_t*>(p);
+  int rc = d.kind == COLOR_KIND_D2
+               ? color_d2(d.n, rp, ci, d.seed, nullptr, nullptr, colors, &J.stats, nullptr, s->heavy_stream)
+               : color_pd2(J.n_csr_rows, d.n, rp, ci, cp, ri, d.seed, nullptr, nullptr, colors, &J.stats, nullptr,
+                           s->heavy_stream);
+  if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
+  J.rc = rc;
+  J.colors.resize(static_cast<size_t>(d.n));
+  if (hipMemcpyAsync(J.colors.data(), colors, sizeof(int32_t) * J.colors.size(), hipMemcpyDeviceToHost,
+                     s->heavy_stream) != hipSuccess ||
+      hipStreamSynchronize(s->heavy_stream) != hipSuccess)
+    return COLOR_EHIP;
+  return COLOR_OK;
+}
+
+void heavy_lane(color_server* s) {
+  if (hipSetDevice(s->device) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->error = COLOR_EHIP;
+    s->done_cv.notify_all();
+    return;
+  }
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (true) {
+    s->heavy_cv.wait(lk, [&] { return s->stopping || !s->heavy_queue.empty(); });
+    if (s->stopping) break;
+    const uint64_t id = s->heavy_queue.front();
+    ServedJob& J = s->jobs[id];
+    size_t off = 0;
+    if (!s->arena.alloc(J.footprint, &off)) {  // wait for arena space freed by the other lane
+      s->heavy_cv.wait_for(lk, std::chrono::milliseconds(1));
+      continue;
+    }
+    s->heavy_queue.pop_front();
+    J.arena_off = off;
+    J.state = JobState::Running;
+    lk.unlock();
+    const int e = run_heavy(s, J);  // J stays put: only Done jobs are erased
+    lk.lock();
+    s->arena.release(J.arena_off, J.footprint);
+    J.footprint = 0;
+    if (J.h_in) {
+      (void)hipHostFree(J.h_in);
+      J.h_in = nullptr;
+    }
+    if (e) s->error = e;
+    J.state = JobState::Done;
+    s->done_cv.notify_all();
+  }
+}
+
 void destroy_server(color_server* s) {
+  if (s->heavy_thread.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stopping = true;
+    }
+    s->heavy_cv.notify_all();
+    s->heavy_thread.join();
+  }
+  if (s->heavy_stream) (void)hipStreamSynchronize(s->heavy_stream);
   if (s->compute) (void)hipStreamSynchronize(s->compute);
   if (s->copy) (void)hipStreamSynchronize(s->copy);
   for (auto& kv : s->jobs) free_job_resources(s, kv.second);
@@ -353,6 +460,7 @@ void destroy_server(color_server* s) {
   if (s->h_words) (void)hipHostFree(s->h_words);
   if (s->compute) (void)hipStreamDestroy(s->compute);
   if (s->copy) (void)hipStreamDestroy(s->copy);
+  if (s->heavy_stream) (void)hipStreamDestroy(s->heavy_stream);
   delete s;
 }
 
@@ -378,6 +486,7 @@ color_server* color_server_create(size_t hbm_budget_bytes, int32_t max_slots, in
   if (hipGetDevice(&s->device) != hipSuccess) return fail(COLOR_EHIP);
   if (hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->heavy_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&s->epoch_done, hipEventDisableTiming) != hipSuccess)
     return fail(COLOR_EHIP);
   if (hipMalloc(reinterpret_cast<void**>(&s->arena_base), hbm_budget_bytes) != hipSuccess ||
@@ -403,6 +512,11 @@ color_server* color_server_create(size_t hbm_budget_bytes, int32_t max_slots, in
       hipStreamSynchronize(s->compute) != hipSuccess)
     return fail(COLOR_EHIP);
   s->slot_job.assign(ns, 0);
+  try {
+    s->heavy_thread = std::thread(heavy_lane, s);
+  } catch (...) {
+    return fail(COLOR_ENOMEM);
+  }
   *err = COLOR_OK;
   return s;
 }
@@ -459,10 +573,16 @@ int color_server_submit(color_server* s, const color_host_job* job, uint64_t* jo
     return COLOR_EHIP;
   }
   J.desc = d;
+  J.heavy = job_walk(d, nnz) >= kLongWalk;
   const uint64_t id = s->next_id++;
   s->jobs.emplace(id, J);
-  s->queue.push_back(id);
   if (job_id) *job_id = id;
+  if (J.heavy) {
+    s->heavy_queue.push_back(id);
+    s->heavy_cv.notify_one();
+    return COLOR_EQUEUED;
+  }
+  s->queue.push_back(id);
   if ((e = advance(s, false))) return e;
   return s->jobs[id].state == JobState::Queued ? COLOR_EQUEUED : COLOR_OK;
 }
@@ -485,12 +605,15 @@ int color_server_poll(color_server* s, uint64_t job_id, int32_t* host_colors, co
 
 int color_server_drain(color_server* s) {
   if (!s) return COLOR_EINVAL;
-  std::lock_guard<std::mutex> lk(s->mu);
+  std::unique_lock<std::mutex> lk(s->mu);
   while (busy(s)) {
     int e = advance(s, true);
     if (e) return e;
+    // nothing launched: the heavy lane holds the remaining work or the arena
+    // space queued jobs wait for; let it run
+    if (!s->in_flight && busy(s)) s->done_cv.wait_for(lk, std::chrono::milliseconds(1));
   }
-  return COLOR_OK;
+  return s->error;
 }
 
 int color_server_destroy(color_server* s) {

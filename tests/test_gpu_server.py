@@ -63,6 +63,13 @@ def oracle_ok(s, limit=1_000_000):
     return (g.n * d if s.kind == 1 else g.n * d * (d + 1)) <= limit
 
 
+def walk(s):
+    """The server's estimate of a job's two-hop walk per visit."""
+    g = s.graph
+    d = g.nnz / max(g.n, 1)
+    return d * (d + 1)  # square patterns: column and row degrees are the vertex degrees
+
+
 def footprint(s):
     g = s.graph
     nnz = g.nnz
@@ -94,6 +101,10 @@ def test_server_queueing_and_reuse_match_oracle(gc):
                     del pending[jid]
         assert not pending, "jobs never finished: " + ", ".join(
             f"{j} ({s.family} kind {s.kind} n={s.graph.n})" for j, s in pending.items())
+        engines = {done[j][1].engine for j in ids}
+        assert gc.ENGINE_BATCH in engines
+        if any(s.kind != 1 and walk(s) >= 128 for s in specs):  # long two-hop walks: the heavy lane
+            assert gc.ENGINE_INCREMENTAL in engines
         for jid, s in zip(ids, specs):
             colors, st = done[jid]
             ref = ref_of(s) if oracle_ok(s) else None
