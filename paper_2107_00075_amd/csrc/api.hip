@@ -71,7 +71,7 @@ void Workspace::release() {
   events.clear();
   for (DevBuf* b : {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
                     &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
-                    &inc_F, &inc_L0, &inc_B0, &inc_bm, &scan_tmp})
+                    &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &scan_tmp})
     b->release();
   if (host) (void)hipHostFree(host);
   host = nullptr;
@@ -459,13 +459,16 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   if (hipMemsetAsync(w->inc_F.p, 0, sizeof(uint32_t) * static_cast<size_t>(std::max(fw_total, 1)), c.st) !=
       hipSuccess)
     return COLOR_EHIP;
-  // One list array, compacted in place (the lists of a round are read and
-  // rewritten only by their own vertex's workgroup); for D1 round 1 reads the
-  // adjacency itself and compacts into the list array.
+  // Round 1 reads the unsplit lists (D1: the adjacency itself; D2/PD2: the
+  // materialized two-hop lists) and its losers write their lists, split by
+  // key, into the list array B; later rounds compact B in place (the lists
+  // of a round are read and rewritten only by their own vertex's workgroup).
   int32_t* B = w->inc_B0.as<int32_t>();
   int32_t* Lb = w->inc_L0.as<int32_t>();
+  if ((e = w->inc_Ll.ensure(sizeof(int32_t) * n1, false, c.st))) return e;
   const int32_t* A0 = g.ci;
   if (MODE != kD1) {
+    if ((e = w->inc_B1.ensure(sizeof(int32_t) * list_entries, false, c.st))) return e;
     launch_inc_fill<MODE>(g, aoff, len, B, w->deferred.as<int32_t>(), &S->deferred_cnt, &S->deferred_grab[1],
                           c.st);
     c.launches += 2;
@@ -477,6 +480,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
     if (hipMemsetAsync(w->inc_bm.p, 0, bm_bytes, c.st) != hipSuccess) return COLOR_EHIP;
     launch_inc_dedup(n, aoff, Lb, B, w->inc_bm.as<uint32_t>(), words, grid, c.st);
     c.launches += 1;
+    B = w->inc_B1.as<int32_t>();  // the split lists
   }
   IncBufs ib;
   ib.C = colors;
@@ -491,6 +495,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   ib.trace = w->trace.as<int32_t>();
   ib.trace_cap = c.trace_cap;
   ib.rounds_done = &S->rounds_done;
+  ib.llen = w->inc_Ll.as<int32_t>();
 
   if (init) {
     IncBufs pb = ib;

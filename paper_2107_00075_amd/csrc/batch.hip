@@ -187,7 +187,7 @@ struct StepShared {
 // Units [first, first + count) of the color (detect = false) or detect step
 // of round r.
 template <int MODE, int LD>
-__device__ void round_units(BatchJob* J, const JobView& V, const KeySource& k, const BatchTune& t, int r,
+__device__ __forceinline__ void round_units(BatchJob* J, const JobView& V, const KeySource& k, const BatchTune& t, int r,
                             bool detect, uint32_t first, uint32_t count, StepShared& sh, uint64_t& work_acc,
                             int32_t& maxc_acc) {
   const int p = (r - 1) & 1;
@@ -205,21 +205,28 @@ __device__ void round_units(BatchJob* J, const JobView& V, const KeySource& k, c
   b.wl_out = p ? V.wl0 : V.wl1;
   b.cnt_in = J->cnt[p];
   b.cnt_out = J->cnt[p ^ 1];
-  int32_t chunks[3];
-  for (int i = 0; i < 3; ++i) chunks[i] = (sh.cnt_in[i] + kBlock - 1) / kBlock;
-  const int32_t light = chunks[0] + chunks[1] + chunks[2];
+  // scalars, not arrays: a dynamically indexed local array would live in
+  // scratch memory
+  const int32_t ch0 = (sh.cnt_in[0] + kBlock - 1) / kBlock;
+  const int32_t ch1 = (sh.cnt_in[1] + kBlock - 1) / kBlock;
+  const int32_t ch2 = (sh.cnt_in[2] + kBlock - 1) / kBlock;
+  const int32_t light = ch0 + ch1 + ch2;
   for (uint32_t q = 0; q < count; ++q) {
     int32_t uu = static_cast<int32_t>(first + q);
     if (uu < light) {
       int bin = 0;
-      while (bin < 2 && uu >= chunks[bin]) {
-        uu -= chunks[bin];
-        ++bin;
+      if (uu >= ch0) {
+        uu -= ch0;
+        bin = 1;
+        if (uu >= ch1) {
+          uu -= ch1;
+          bin = 2;
+        }
       }
       const int32_t f = uu * kBlock;
       const int32_t cnt = min(kBlock, sh.cnt_in[bin] - f);
       const int32_t* wl = b.wl_in + sh.off[bin] + f;
-      const int G = t.lanes[bin];
+      const int G = bin == 0 ? t.lanes[0] : (bin == 1 ? t.lanes[1] : t.lanes[2]);
       if (!detect) {
         switch (G) {
           case 1: color_chunk_group<MODE, 1, LD>(g, b, wl, cnt, work_acc); break;
@@ -283,9 +290,8 @@ __device__ void finish_job(BatchJob* J, uint64_t* word, uint32_t e, int32_t roun
 }
 
 // The last unit of epoch e has completed: open the next phase.
-__device__ void close_phase(BatchJob* J, const JobView& V, uint64_t* word, uint32_t e, uint32_t U,
+__device__ void close_phase(BatchJob* J, int32_t n, int32_t max_rounds, uint64_t* word, uint32_t e, uint32_t U,
                             int32_t* retired) {
-  const int32_t n = V.n;
   if (e == 1) {
     int32_t o = 0;
     for (int b = 0; b < kBatchBins; ++b) {
@@ -317,7 +323,7 @@ __device__ void close_phase(BatchJob* J, const JobView& V, uint64_t* word, uint3
     }
     if (total == 0) {
       finish_job(J, word, e, r, COLOR_OK, retired);
-    } else if (r >= V.max_rounds) {
+    } else if (r >= max_rounds) {
       finish_job(J, word, e, r, COLOR_ENOCONVERGE, retired);
     } else {
       for (int b = 0; b < kBatchBins; ++b) atomic_reset_i32(&J->cnt[p][b]);
@@ -329,7 +335,7 @@ __device__ void close_phase(BatchJob* J, const JobView& V, uint64_t* word, uint3
 
 // Runs the owned units of one grab.
 template <int MODE, int LD>
-__device__ void run_grab(BatchJob* J, const JobView& V, const BatchTune* tune, uint32_t e, uint32_t first,
+__device__ __forceinline__ void run_grab(BatchJob* J, const JobView& V, const BatchTune* tune, uint32_t e, uint32_t first,
                          uint32_t count, StepShared& sh, int32_t* s_bc, int32_t* s_base, uint64_t& work_acc,
                          int32_t& maxc_acc) {
   const BatchTune t = tune_of<LD>(V, tune);
@@ -438,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchJob* jobs, uint64_t*
       const uint32_t before = atomicAdd(&J->done, s_cnt);
       if (before + s_cnt == s_u) {
         __threadfence();
-        close_phase(J, V, &words[job], e, s_u, retired);
+        close_phase(J, V.n, V.max_rounds, &words[job], e, s_u, retired);
       }
     }
     __syncthreads();

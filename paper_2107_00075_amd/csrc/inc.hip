@@ -170,8 +170,14 @@ __global__ __launch_bounds__(kBlock) void inc_color_kernel(IncBufs b, BinLayout 
 // ---------------------------------------------------------------------------
 // detect + commit/push or compact, group of G lanes per vertex
 // ---------------------------------------------------------------------------
+// Lists are partitioned by key in the round that first copies them out of
+// the adjacency (D1) or the materialized two-hop lists (D2/PD2): the
+// not-yet-committed neighbours of higher key at the front (length alen), the
+// lower ones at the back of the vertex's list region (length llen).  Only a
+// higher-key neighbour can beat v, so later detect scans read the front part
+// only; the one push a winner makes reads both parts.
 template <int G>
-__device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round, int bin, const int32_t* wl,
+__device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round, int bin, const int32_t* wl,
                                  int32_t count, int32_t off_out, int32_t* s_ent, int32_t* s_wc,
                                  int32_t& maxc_acc, uint64_t& bytes, uint64_t& pushes) {
   constexpr int per_pass = kBlock / G;
@@ -179,6 +185,7 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round
   const int sub = threadIdx.x % G;
   const int first = lane_id() & ~(G - 1);
   const uint64_t gm = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  const bool first_pass = b.A_in != b.A_out;
   for (int32_t idx = gi; idx < count; idx += per_pass) {
     const int32_t v = ld_dev(&wl[idx]);
     const int32_t tv = ld_dev(&b.T[v]);
@@ -198,7 +205,7 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool higher = u[j] >= 0 && key_of(k, u[j]) > kv;
+        const bool higher = u[j] >= 0 && (!first_pass || key_of(k, u[j]) > kv);
         t[j] = higher ? ld_dev(&b.T[u[j]]) : -1;
         gath += higher ? 1 : 0;
       }
@@ -214,47 +221,60 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round
         bytes += 20;
       }
     } else if (lose) {
-      // keep the neighbours that are not committed (yet)
-      int32_t kept = 0;
+      // keep the neighbours that are not committed (yet); the first pass
+      // also splits them by key
+      const int32_t cap = ld_dev(&b.aoff[v + 1]) - base;
+      int32_t kept = 0, kept_lo = 0;
       for (int32_t e0 = 0; e0 < len; e0 += G) {
         const int32_t e = e0 + sub;
         int32_t u = -1;
-        bool keep = false;
+        bool keep = false, hi = true;
         if (e < len) {
           u = ld_dev(&A[e]);
           keep = ld_dev(&b.C[u]) == 0;
+          if (first_pass) hi = key_of(k, u) > kv;
         }
-        const uint64_t bal = (__ballot(keep) >> first) & gm;
-        if (keep) {
-          const int32_t pos = kept + __popcll(bal & ((1ull << sub) - 1ull));
-          st_dev(&b.A_out[base + pos], u);
-        }
-        kept += __popcll(bal);
+        const uint64_t bal_h = (__ballot(keep && hi) >> first) & gm;
+        const uint64_t bal_l = (__ballot(keep && !hi) >> first) & gm;
+        const uint64_t below = (1ull << sub) - 1ull;
+        if (keep && hi) st_dev(&b.A_out[base + kept + __popcll(bal_h & below)], u);
+        if (keep && !hi) st_dev(&b.A_out[base + cap - 1 - (kept_lo + __popcll(bal_l & below))], u);
+        kept += __popcll(bal_h);
+        kept_lo += __popcll(bal_l);
       }
       if (sub == 0) {
         st_dev(&b.alen_out[v], kept);
+        if (first_pass) st_dev(&b.llen[v], kept_lo);
         s_ent[idx] = v;
-        bytes += 24 + 8ull * static_cast<uint64_t>(len) + 4ull * static_cast<uint64_t>(kept);
+        bytes += 24 + 8ull * static_cast<uint64_t>(len) + 4ull * static_cast<uint64_t>(kept + kept_lo);
       }
     } else {
-      for (int32_t e0 = sub; e0 < len; e0 += 4 * G) {
-        int32_t x[4], c[4];
+      // push the color to the uncommitted neighbours: the whole list on the
+      // first pass, else both parts
+      const int32_t cap = first_pass ? len : ld_dev(&b.aoff[v + 1]) - base;
+      const int32_t lo_len = first_pass ? 0 : ld_dev(&b.llen[v]);
+      for (int part = 0; part < 2; ++part) {
+        const int32_t pb = part == 0 ? 0 : cap - lo_len;
+        const int32_t pe = part == 0 ? len : cap;
+        for (int32_t e0 = pb + sub; e0 < pe; e0 += 4 * G) {
+          int32_t x[4], c[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int32_t e = e0 + j * G;
-          x[j] = e < len ? ld_dev(&A[e]) : -1;
+          for (int j = 0; j < 4; ++j) {
+            const int32_t e = e0 + j * G;
+            x[j] = e < pe ? ld_dev(&A[e]) : -1;
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) c[j] = x[j] >= 0 ? ld_dev(&b.C[x[j]]) : 1;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (c[j] == 0) push_color(b, x[j], tv, pushes);
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) c[j] = x[j] >= 0 ? ld_dev(&b.C[x[j]]) : 1;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (c[j] == 0) push_color(b, x[j], tv, pushes);
       }
       if (sub == 0) {
         st_dev(&b.C[v], tv);
         maxc_acc = max(maxc_acc, tv);
         s_ent[idx] = -1;
-        bytes += 20 + 8ull * static_cast<uint64_t>(len);  // own fields, C write, the push pass
+        bytes += 20 + 8ull * static_cast<uint64_t>(len + lo_len);  // own fields, C write, the push pass
       }
     }
   }
@@ -285,11 +305,12 @@ __device__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round
 // at a barrier once per kBlock * kIncBatch entries.
 constexpr int kIncBatch = 8;
 
-__device__ void inc_detect_block(const KeySource& k, const IncBufs& b, int round, int32_t v, int bin,
+__device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBufs& b, int round, int32_t v, int bin,
                                  int32_t off, int32_t* s_wc, int32_t& maxc_acc, uint64_t& bytes,
                                  uint64_t& pushes) {
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
+  const bool first_pass = b.A_in != b.A_out;
   const int32_t tv = ld_dev(&b.T[v]);
   const uint64_t kv = key_of(k, v);
   const int32_t base = ld_dev(&b.aoff[v]);
@@ -306,11 +327,11 @@ __device__ void inc_detect_block(const KeySource& k, const IncBufs& b, int round
       u[j] = e < len ? ld_dev(&A[e]) : -1;
       read += e < len ? 1u : 0u;
     }
-    // only a higher-key neighbour can beat v: compare keys first and read
-    // the tentative colors of those neighbours only
+    // only a higher-key neighbour can beat v: before the lists are split by
+    // key, compare keys first and read the tentative colors of those only
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j) {
-      const bool higher = u[j] >= 0 && key_of(k, u[j]) > kv;
+      const bool higher = u[j] >= 0 && (!first_pass || key_of(k, u[j]) > kv);
       t[j] = higher ? ld_dev(&b.T[u[j]]) : -1;
       read += higher ? 1u : 0u;
     }
@@ -330,67 +351,97 @@ __device__ void inc_detect_block(const KeySource& k, const IncBufs& b, int round
       bytes += 24;
     }
   } else if (lose) {
-    // keep the neighbours that are not committed (yet); order is free.  The
-    // list may be compacted in place: every entry of a step is read before
-    // the barrier that precedes the step's writes, and writes land below
-    // the step's first entry or inside it.
-    int32_t kept = 0;
+    // keep the neighbours that are not committed (yet), order free; the
+    // first pass also splits them by key (higher to the front, lower to the
+    // back).  Later passes compact the front part in place: every entry of a
+    // step is read before the barrier that precedes the step's writes, and
+    // writes land below the step's first entry or inside it.
+    const int32_t cap = ld_dev(&b.aoff[v + 1]) - base;
+    int32_t kept = 0, kept_lo = 0;
+    int32_t* s_lo = s_wc + kWavesPerBlock;
     for (int32_t e0 = 0; e0 < len; e0 += step) {
-      int32_t u[kIncBatch], c[kIncBatch];
+      int32_t u[kIncBatch];
+      uint32_t keep_hi = 0, keep_lo = 0;  // bit j: entry j kept in the front / back part
 #pragma unroll
       for (int j = 0; j < kIncBatch; ++j) {
         const int32_t e = e0 + j * kBlock + tid;
         u[j] = e < len ? ld_dev(&A[e]) : -1;
       }
 #pragma unroll
-      for (int j = 0; j < kIncBatch; ++j) c[j] = u[j] >= 0 ? ld_dev(&b.C[u[j]]) : 1;
-      int32_t cnt = 0;
-#pragma unroll
-      for (int j = 0; j < kIncBatch; ++j) cnt += c[j] == 0 ? 1 : 0;
-      int32_t incl = cnt;
+      for (int j = 0; j < kIncBatch; ++j) {
+        const bool keep = u[j] >= 0 && ld_dev(&b.C[u[j]]) == 0;
+        const bool hi = !first_pass || (u[j] >= 0 && key_of(k, u[j]) > kv);
+        keep_hi |= (keep && hi) ? (1u << j) : 0u;
+        keep_lo |= (keep && !hi) ? (1u << j) : 0u;
+      }
+      const int32_t cnt = __builtin_popcount(keep_hi), cnt_lo = __builtin_popcount(keep_lo);
+      int32_t incl = cnt, incl_lo = cnt_lo;
 #pragma unroll
       for (int o = 1; o < kWave; o <<= 1) {
         const int32_t y = __shfl_up(incl, o, kWave);
-        if (lane_id() >= o) incl += y;
+        const int32_t z = __shfl_up(incl_lo, o, kWave);
+        if (lane_id() >= o) {
+          incl += y;
+          incl_lo += z;
+        }
       }
-      if (lane_id() == kWave - 1) s_wc[wave] = incl;
+      if (lane_id() == kWave - 1) {
+        s_wc[wave] = incl;
+        s_lo[wave] = incl_lo;
+      }
       __syncthreads();
-      int32_t pos = kept + incl - cnt;
-      int32_t tot = 0;
+      int32_t pos = kept + incl - cnt, pos_lo = kept_lo + incl_lo - cnt_lo;
+      int32_t tot = 0, tot_lo = 0;
       for (int w = 0; w < kWavesPerBlock; ++w) {
-        if (w < wave) pos += s_wc[w];
+        if (w < wave) {
+          pos += s_wc[w];
+          pos_lo += s_lo[w];
+        }
         tot += s_wc[w];
+        tot_lo += s_lo[w];
       }
 #pragma unroll
-      for (int j = 0; j < kIncBatch; ++j)
-        if (c[j] == 0) st_dev(&b.A_out[base + pos++], u[j]);
+      for (int j = 0; j < kIncBatch; ++j) {
+        if (keep_hi & (1u << j)) st_dev(&b.A_out[base + pos++], u[j]);
+        if (keep_lo & (1u << j)) st_dev(&b.A_out[base + cap - 1 - pos_lo++], u[j]);
+      }
       kept += tot;
+      kept_lo += tot_lo;
       __syncthreads();
     }
     if (tid == 0) {
       st_dev(&b.alen_out[v], kept);
+      if (first_pass) st_dev(&b.llen[v], kept_lo);
       const int32_t p = atomicAdd(&b.cnt_out[bin], 1);
       st_dev(&b.wl_out[off + p], v);
-      bytes += 24 + 8ull * static_cast<uint64_t>(len) + 4ull * static_cast<uint64_t>(kept);
+      bytes += 24 + 8ull * static_cast<uint64_t>(len) + 4ull * static_cast<uint64_t>(kept + kept_lo);
     }
   } else {
-    for (int32_t e0 = 0; e0 < len; e0 += step) {
-      int32_t x[kIncBatch], c[kIncBatch];
+    // push the color to the uncommitted neighbours: the whole list on the
+    // first pass, else both parts
+    const int32_t cap = first_pass ? len : ld_dev(&b.aoff[v + 1]) - base;
+    const int32_t lo_len = first_pass ? 0 : ld_dev(&b.llen[v]);
+    for (int part = 0; part < 2; ++part) {
+      const int32_t pb = part == 0 ? 0 : cap - lo_len;
+      const int32_t pe = part == 0 ? len : cap;
+      for (int32_t e0 = pb; e0 < pe; e0 += step) {
+        int32_t x[kIncBatch], c[kIncBatch];
 #pragma unroll
-      for (int j = 0; j < kIncBatch; ++j) {
-        const int32_t e = e0 + j * kBlock + tid;
-        x[j] = e < len ? ld_dev(&A[e]) : -1;
+        for (int j = 0; j < kIncBatch; ++j) {
+          const int32_t e = e0 + j * kBlock + tid;
+          x[j] = e < pe ? ld_dev(&A[e]) : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < kIncBatch; ++j) c[j] = x[j] >= 0 ? ld_dev(&b.C[x[j]]) : 1;
+#pragma unroll
+        for (int j = 0; j < kIncBatch; ++j)
+          if (c[j] == 0) push_color(b, x[j], tv, pushes);
       }
-#pragma unroll
-      for (int j = 0; j < kIncBatch; ++j) c[j] = x[j] >= 0 ? ld_dev(&b.C[x[j]]) : 1;
-#pragma unroll
-      for (int j = 0; j < kIncBatch; ++j)
-        if (c[j] == 0) push_color(b, x[j], tv, pushes);
     }
     if (tid == 0) {
       st_dev(&b.C[v], tv);
       maxc_acc = max(maxc_acc, tv);
-      bytes += 20 + 8ull * static_cast<uint64_t>(len);  // own fields, C write, the push pass
+      bytes += 20 + 8ull * static_cast<uint64_t>(len + lo_len);  // own fields, C write, the push pass
     }
   }
   __syncthreads();
@@ -400,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void inc_detect_kernel(KeySource k, IncBufs
   __shared__ int32_t s_unit;
   __shared__ int32_t s_max;
   __shared__ int32_t s_ent[kBlock];
-  __shared__ int32_t s_wc[kWavesPerBlock + 1];
+  __shared__ int32_t s_wc[2 * kWavesPerBlock + 1];
   __shared__ unsigned long long s_acc[2];
   __shared__ IncMap M;
   if (threadIdx.x == 0) {

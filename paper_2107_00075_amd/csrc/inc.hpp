@@ -18,7 +18,9 @@ struct IncBufs {
   const int32_t* A_in;         // active lists of round r
   int32_t* A_out;              // compacted lists (the same array as A_in after round 1: in place)
   const int32_t* alen_in;      // list lengths of round r
-  int32_t* alen_out;           // list lengths for round r+1 (the same array as alen_in)
+  int32_t* alen_out;           // list lengths for round r+1 (the same array as alen_in); after the
+                               // first pass: the higher-key part at the front of a list
+  int32_t* llen;               // after the first pass: the lower-key part at the back of a list
   const int32_t* fw_off;       // bitset word offsets, n+1 entries
   uint32_t* F;                 // forbidden-color bitsets (bit c-1 = color c)
   int32_t* maxc;               // largest committed color

@@ -60,7 +60,7 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
 // color: group of G lanes per vertex, one chunk of kBlock worklist entries
 // ---------------------------------------------------------------------------
 template <int MODE, int G, int LD = 0>
-__device__ void color_chunk_group(const GraphView& g, const RoundBufs& b, const int32_t* wl, int32_t count,
+__device__ __forceinline__ void color_chunk_group(const GraphView& g, const RoundBufs& b, const int32_t* wl, int32_t count,
                                   uint64_t& work_acc) {
   constexpr int per_pass = kBlock / G;
   const int gi = threadIdx.x / G;
@@ -92,7 +92,7 @@ __device__ void color_chunk_group(const GraphView& g, const RoundBufs& b, const 
 // color: one workgroup per vertex
 // ---------------------------------------------------------------------------
 template <int MODE, int LD = 0>
-__device__ void color_vertex_block(const GraphView& g, const RoundBufs& b, int32_t v,
+__device__ __forceinline__ void color_vertex_block(const GraphView& g, const RoundBufs& b, int32_t v,
                                    uint32_t* ovf, uint64_t* red, int32_t* s_min) {
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
@@ -147,7 +147,7 @@ __device__ void color_vertex_block(const GraphView& g, const RoundBufs& b, int32
 // Losers of the chunk are collected in LDS and appended to W_{r+1} with one
 // device atomic per chunk (workgroup prefix over the wavefront ballots).
 template <int MODE, int G, int LD = 0>
-__device__ void detect_chunk_group(const GraphView& g, const KeySource& k, const RoundBufs& b, int bin,
+__device__ __forceinline__ void detect_chunk_group(const GraphView& g, const KeySource& k, const RoundBufs& b, int bin,
                                    const int32_t* wl, int32_t count, int32_t off_out, int32_t* s_ent,
                                    int32_t* s_wc, int32_t& maxc_acc) {
   constexpr int per_pass = kBlock / G;
@@ -199,7 +199,7 @@ __device__ void detect_chunk_group(const GraphView& g, const KeySource& k, const
 }
 
 template <int MODE, int LD = 0>
-__device__ void detect_vertex_block(const GraphView& g, const KeySource& k, const RoundBufs& b,
+__device__ __forceinline__ void detect_vertex_block(const GraphView& g, const KeySource& k, const RoundBufs& b,
                                     int32_t v, int32_t off, int32_t& maxc_acc) {
   const int tid = threadIdx.x;
   const int32_t* __restrict__ T = b.T;
