@@ -496,6 +496,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   ib.trace_cap = c.trace_cap;
   ib.rounds_done = &S->rounds_done;
   ib.llen = w->inc_Ll.as<int32_t>();
+  ib.uniform = 0;
 
   if (init) {
     IncBufs pb = ib;
@@ -531,6 +532,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
       b.cnt_out = S->cnt[pout];
       b.A_in = local == 1 ? A0 : B;
       b.A_out = B;
+      b.uniform = (local == 1 && !init) ? 1 : 0;
       b.alen_in = Lb;
       b.alen_out = Lb;
       if (c.timing && c.record_event(0)) return COLOR_EHIP;

@@ -206,8 +206,8 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const bool higher = u[j] >= 0 && (!first_pass || key_of(k, u[j]) > kv);
-        t[j] = higher ? ld_dev(&b.T[u[j]]) : -1;
-        gath += higher ? 1 : 0;
+        t[j] = higher ? (b.uniform ? tv : ld_dev(&b.T[u[j]])) : -1;
+        gath += (higher && !b.uniform) ? 1 : 0;
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -231,7 +231,7 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
         bool keep = false, hi = true;
         if (e < len) {
           u = ld_dev(&A[e]);
-          keep = ld_dev(&b.C[u]) == 0;
+          keep = b.uniform || ld_dev(&b.C[u]) == 0;  // round 1: nobody was committed before it
           if (first_pass) hi = key_of(k, u) > kv;
         }
         const uint64_t bal_h = (__ballot(keep && hi) >> first) & gm;
@@ -263,8 +263,10 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
             const int32_t e = e0 + j * G;
             x[j] = e < pe ? ld_dev(&A[e]) : -1;
           }
+          // round 1: a winner's neighbours all lose (two neighbours cannot
+          // both be the highest key of their neighbourhoods)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) c[j] = x[j] >= 0 ? ld_dev(&b.C[x[j]]) : 1;
+          for (int j = 0; j < 4; ++j) c[j] = x[j] >= 0 ? (b.uniform ? 0 : ld_dev(&b.C[x[j]])) : 1;
 #pragma unroll
           for (int j = 0; j < 4; ++j)
             if (c[j] == 0) push_color(b, x[j], tv, pushes);
@@ -332,8 +334,8 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j) {
       const bool higher = u[j] >= 0 && (!first_pass || key_of(k, u[j]) > kv);
-      t[j] = higher ? ld_dev(&b.T[u[j]]) : -1;
-      read += higher ? 1u : 0u;
+      t[j] = higher ? (b.uniform ? tv : ld_dev(&b.T[u[j]])) : -1;
+      read += (higher && !b.uniform) ? 1u : 0u;
     }
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j)
@@ -369,7 +371,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
       }
 #pragma unroll
       for (int j = 0; j < kIncBatch; ++j) {
-        const bool keep = u[j] >= 0 && ld_dev(&b.C[u[j]]) == 0;
+        const bool keep = u[j] >= 0 && (b.uniform || ld_dev(&b.C[u[j]]) == 0);
         const bool hi = !first_pass || (u[j] >= 0 && key_of(k, u[j]) > kv);
         keep_hi |= (keep && hi) ? (1u << j) : 0u;
         keep_lo |= (keep && !hi) ? (1u << j) : 0u;
@@ -432,7 +434,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
           x[j] = e < pe ? ld_dev(&A[e]) : -1;
         }
 #pragma unroll
-        for (int j = 0; j < kIncBatch; ++j) c[j] = x[j] >= 0 ? ld_dev(&b.C[x[j]]) : 1;
+        for (int j = 0; j < kIncBatch; ++j) c[j] = x[j] >= 0 ? (b.uniform ? 0 : ld_dev(&b.C[x[j]])) : 1;
 #pragma unroll
         for (int j = 0; j < kIncBatch; ++j)
           if (c[j] == 0) push_color(b, x[j], tv, pushes);

@@ -21,6 +21,8 @@ struct IncBufs {
   int32_t* alen_out;           // list lengths for round r+1 (the same array as alen_in); after the
                                // first pass: the higher-key part at the front of a list
   int32_t* llen;               // after the first pass: the lower-key part at the back of a list
+  int32_t uniform;             // 1 in round 1 without initial colors: every vertex is uncolored and
+                               // every tentative color is 1
   const int32_t* fw_off;       // bitset word offsets, n+1 entries
   uint32_t* F;                 // forbidden-color bitsets (bit c-1 = color c)
   int32_t* maxc;               // largest committed color
