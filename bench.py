@@ -132,6 +132,17 @@ def copy_calibration(torch, dev):
     del a, b
 
 
+def kernel_rows(gc, st, names, color_bytes, detect_bytes):
+    """(kernel, algorithmic bytes, HIP-event ns, launches) of one call's round
+    kernels; the incremental engine's cooperative tail kernel (all rounds once
+    the worklist is small, in one launch) is a kernel of its own."""
+    rows = [(names[0], color_bytes, st.color_kernel_ns, st.color_launches),
+            (names[1], detect_bytes, st.detect_kernel_ns, st.detect_launches)]
+    if st.tail_rounds:
+        rows.append(("inc_tail_kernel", st.tail_bytes, st.tail_kernel_ns, 1))
+    return rows
+
+
 def bench_d1(args, torch, gc, dev):
     work = make_d1_workload()
     graphs = []
@@ -181,8 +192,7 @@ def bench_d1(args, torch, gc, dev):
             else:
                 names = ("color_round_kernel<D1>", "detect_round_kernel<D1>")
                 cb, db = d1_kernel_bytes(st)
-            for kname, byts, ns, nl in ((names[0], cb, st.color_kernel_ns, st.color_launches),
-                                        (names[1], db, st.detect_kernel_ns, st.detect_launches)):
+            for kname, byts, ns, nl in kernel_rows(gc, st, names, cb, db):
                 acc = kern.setdefault(kname, [0, 0, 0])
                 acc[0] += byts
                 acc[1] += ns
@@ -192,7 +202,8 @@ def bench_d1(args, torch, gc, dev):
                                              "vertex_visits": st.vertex_visits, "kernel_ms": 0.0,
                                              "engine": {1: "pull", 2: "incremental"}.get(st.engine, "?"),
                                              "list_visits": st.list_visits})
-            pg["kernel_ms"] += (st.color_kernel_ns + st.detect_kernel_ns) / 1e6 / args.steps
+            pg["kernel_ms"] += (st.color_kernel_ns + st.detect_kernel_ns + st.tail_kernel_ns) / 1e6 / args.steps
+            pg["tail_rounds"] = st.tail_rounds
     dom = max(kern, key=lambda k: kern[k][1])
     b, ns, launches = kern[dom]
     achieved = b / ns if ns else 0.0   # bytes per ns == GB/s
@@ -280,8 +291,7 @@ def bench_d2pd2(args, torch, gc, dev):
             else:
                 names = (f"color_round_kernel<{mode}>", f"detect_round_kernel<{mode}>")
                 cb, db = pull_two_hop_bytes(st, deg)
-            for kname, byts, ns, nl in ((names[0], cb, st.color_kernel_ns, st.color_launches),
-                                        (names[1], db, st.detect_kernel_ns, st.detect_launches)):
+            for kname, byts, ns, nl in kernel_rows(gc, st, names, cb, db):
                 acc = kern.setdefault(kname, [0, 0, 0])
                 acc[0] += byts
                 acc[1] += ns
@@ -290,7 +300,8 @@ def bench_d2pd2(args, torch, gc, dev):
                                           "edge_visits": st.edge_visits, "vertex_visits": st.vertex_visits,
                                           "engine": {1: "pull", 2: "incremental"}.get(st.engine, "?"),
                                           "kernel_ms": 0.0})
-            pg["kernel_ms"] += (st.color_kernel_ns + st.detect_kernel_ns) / 1e6 / args.steps
+            pg["kernel_ms"] += (st.color_kernel_ns + st.detect_kernel_ns + st.tail_kernel_ns) / 1e6 / args.steps
+            pg["tail_rounds"] = st.tail_rounds
     dom = max(kern, key=lambda k: kern[k][1])
     byts, ns, launches = kern[dom]
     achieved = byts / ns if ns else 0.0

@@ -69,7 +69,8 @@ extern "C" {
 #define COLOR_EPENDING      2   /* server: job not finished yet */
 
 #define COLOR_FLAG_VALIDATE 0x1u  /* check the input contract on the device first */
-#define COLOR_FLAG_NO_TAIL  0x2u  /* never switch to the single-workgroup tail kernel */
+#define COLOR_FLAG_NO_TAIL  0x2u  /* incremental engine: run every round as its own pair of
+                                     launches, never finish with the cooperative tail kernel */
 #define COLOR_FLAG_KERNEL_TIMING 0x4u  /* time every round kernel with HIP events on `stream` */
 
 /* Per-call statistics (HOST struct, every pointer argument of this type is
@@ -92,11 +93,13 @@ typedef struct color_stats {
     int32_t color_launches;
     int32_t detect_launches;
     int32_t engine;              /* COLOR_ENGINE_* that ran */
-    int32_t reserved_;
+    int32_t tail_rounds;         /* INCREMENTAL: rounds run by the cooperative tail kernel */
     int64_t list_visits;         /* INCREMENTAL: active-list entries scanned by the detect kernels */
     int64_t pushes;              /* INCREMENTAL: forbidden-color bits pushed */
-    int64_t color_bytes;         /* algorithmic bytes of the color kernels (INCREMENTAL; PULL: 0) */
-    int64_t detect_bytes;        /* algorithmic bytes of the detect kernels (INCREMENTAL; PULL: 0) */
+    int64_t color_bytes;         /* algorithmic bytes of the per-round color kernels (INCREMENTAL; PULL: 0) */
+    int64_t detect_bytes;        /* algorithmic bytes of the per-round detect kernels (INCREMENTAL; PULL: 0) */
+    int64_t tail_kernel_ns;      /* COLOR_FLAG_KERNEL_TIMING: HIP-event duration of the tail kernel */
+    int64_t tail_bytes;          /* algorithmic bytes of the tail kernel's rounds (color + detect) */
 } color_stats;
 
 /* Tuning knobs (HOST struct, nullable = library defaults / autotuned).  None
@@ -109,7 +112,8 @@ typedef struct color_params {
     int32_t max_rounds;     /* stop after this many rounds: COLOR_ENOCONVERGE (0: n + 1, which
                                no run reaches: each round commits at least one vertex) */
     int32_t rounds_per_poll;/* rounds enqueued between host checks of the worklist size */
-    int32_t tail_threshold; /* worklist size below which the tail kernel finishes the call */
+    int32_t tail_threshold; /* INCREMENTAL: worklist size at or below which one cooperative launch
+                               runs all remaining rounds (grid barriers between the steps) */
     int32_t max_workgroups; /* cap on the grid of the round kernels */
     uint32_t flags;         /* COLOR_FLAG_* */
     int32_t engine;         /* COLOR_ENGINE_*: 0 = library choice */

@@ -55,9 +55,10 @@ class CStats(ctypes.Structure):
                 ("kernel_launches", ctypes.c_int32), ("color_kernel_ns", ctypes.c_int64),
                 ("detect_kernel_ns", ctypes.c_int64), ("color_launches", ctypes.c_int32),
                 ("detect_launches", ctypes.c_int32), ("engine", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32), ("list_visits", ctypes.c_int64),
+                ("tail_rounds", ctypes.c_int32), ("list_visits", ctypes.c_int64),
                 ("pushes", ctypes.c_int64), ("color_bytes", ctypes.c_int64),
-                ("detect_bytes", ctypes.c_int64)]
+                ("detect_bytes", ctypes.c_int64), ("tail_kernel_ns", ctypes.c_int64),
+                ("tail_bytes", ctypes.c_int64)]
 
 
 class CParams(ctypes.Structure):
@@ -98,6 +99,9 @@ class Stats:
     pushes: int = 0
     color_bytes: int = 0
     detect_bytes: int = 0
+    tail_rounds: int = 0
+    tail_kernel_ns: int = 0
+    tail_bytes: int = 0
     converged: bool = True
     worklist: list = field(default_factory=list)
 

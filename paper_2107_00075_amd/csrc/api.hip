@@ -9,6 +9,8 @@
 // cap, so a call with r rounds costs O(log r) synchronizations.
 #include <algorithm>
 #include <climits>
+#include <cstddef>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -103,6 +105,21 @@ Workspace* workspace_for_current_device(int* err) {
 // ---------------------------------------------------------------------------
 // parameters
 // ---------------------------------------------------------------------------
+
+// Degree-bin work bounds (bins 0..2) for the incremental engine, measured on
+// MI355X: R-MAT scale 22 (D1) 69 -> 60 ms against the pull engine's bounds,
+// the 4M x 1M power-law PD2 pattern 285 -> 126 ms.
+void incremental_bins(int mode, int32_t bin_hi[4]) {
+  if (mode == kD1) {
+    bin_hi[0] = 16;
+    bin_hi[1] = 64;
+    bin_hi[2] = 512;
+  } else {
+    bin_hi[0] = 64;
+    bin_hi[1] = 256;
+    bin_hi[2] = 1024;
+  }
+}
 
 static bool valid_lanes(int x) {
   return x == 1 || x == 2 || x == 4 || x == 8 || x == 16 || x == 32 || x == 64;
@@ -305,6 +322,9 @@ int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, 
                int32_t n_total) {
   int e = merge_params(mode, user, &c.P);
   if (e) return e;
+  c.user_bins = false;
+  if (user)
+    for (int i = 0; i < 3; ++i) c.user_bins = c.user_bins || user->bin_hi[i] > 0;
   // Every round commits at least the worklist vertex of highest key, so no
   // run needs more than n rounds; the default cap turns a defect into
   // COLOR_ENOCONVERGE instead of an endless loop.
@@ -347,7 +367,9 @@ int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc) {
     stats->color_launches = c.color_launches;
     stats->detect_launches = c.detect_launches;
     stats->engine = c.engine;
-    stats->reserved_ = 0;
+    stats->tail_rounds = c.tail_rounds;
+    stats->tail_kernel_ns = 0;
+    stats->tail_bytes = static_cast<int64_t>(c.H->visits[6] + c.H->visits[7]);
     stats->list_visits = static_cast<int64_t>(c.H->visits[2]);
     stats->color_bytes = static_cast<int64_t>(c.H->visits[3]);
     stats->detect_bytes = static_cast<int64_t>(c.H->visits[4]);
@@ -361,7 +383,8 @@ int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc) {
         if (hipEventElapsedTime(&ms, c.ws->events[i], c.ws->events[i + 1]) != hipSuccess) return COLOR_EHIP;
         const int64_t ns = static_cast<int64_t>(static_cast<double>(ms) * 1e6);
         if (kind == 0) stats->color_kernel_ns += ns;
-        else stats->detect_kernel_ns += ns;
+        else if (kind == 1) stats->detect_kernel_ns += ns;
+        else stats->tail_kernel_ns += ns;
       }
     }
     if (c.trace_cap > 0) {
@@ -507,13 +530,68 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
   const int resident = std::min(resident_inc_blocks(), std::max(8, c.P.max_workgroups));
   const int max_rounds = c.P.max_rounds;
+  // the buffers of round r: worklists and counts ping-pong; round 1 reads the
+  // unsplit lists (and, without initial colors, takes the uniform shortcut)
+  auto round_bufs = [&](int r) {
+    IncBufs b = ib;
+    const int pin = (r - 1) & 1, pout = r & 1;
+    b.wl_in = c.wl[pin];
+    b.wl_out = c.wl[pout];
+    b.cnt_in = S->cnt[pin];
+    b.cnt_out = S->cnt[pout];
+    b.A_in = r == 1 ? A0 : B;
+    b.A_out = B;
+    b.uniform = (r == 1 && !init) ? 1 : 0;
+    b.alen_in = Lb;
+    b.alen_out = Lb;
+    return b;
+  };
+  bool tail_on = !(c.P.flags & COLOR_FLAG_NO_TAIL) && tail_blocks_resident() > 0;
+  const int64_t tail_at = c.P.tail_threshold > 0 ? c.P.tail_threshold : kTailDefault;
   int local = 0;
   int R = std::max(1, c.P.rounds_per_poll);
+  int64_t prev_total = 0;
+  int prev_local = 0;
   while (true) {
     int64_t total = 0;
     for (int i = 0; i < kBins; ++i) total += known[i];
     if (total == 0) break;
     if (max_rounds > 0 && local >= max_rounds) return COLOR_ENOCONVERGE;
+    if (tail_on && total <= tail_at) {
+      // the remaining rounds in one cooperative launch: no launch gaps and no
+      // host polls between the (small) rounds of the tail
+      int64_t g = std::max<int64_t>((total + kBlock - 1) / kBlock, round_units(known, L));
+      g = std::min<int64_t>(g, std::min(tail_blocks_resident(), std::max(8, c.P.max_workgroups)));
+      if (g >= 8) g = g / 8 * 8;
+      IncRoundSet set;
+      set.b[0] = round_bufs(1);
+      set.b[1] = round_bufs(3);
+      set.b[2] = round_bufs(2);
+      for (IncBufs& b : set.b) b.bytes_slot = 6;
+      static_assert(offsetof(Scalars, tail_left) == offsetof(Scalars, bar) + sizeof(Scalars::bar) + sizeof(int32_t),
+                    "barrier words and tail flags are cleared together");
+      if (hipMemsetAsync(S->bar, 0, sizeof(S->bar) + 2 * sizeof(int32_t), c.st) != hipSuccess) return COLOR_EHIP;
+      const int cap = max_rounds > 0 ? max_rounds : INT_MAX;
+      if (c.timing && c.record_event(2)) return COLOR_EHIP;
+      if (launch_inc_tail(k, set, L, local + 1, cap, S->bar, &S->tail_err, &S->tail_left,
+                          static_cast<int>(std::max<int64_t>(1, g)), c.st)) {
+        if (c.timing && c.record_event(-1)) return COLOR_EHIP;
+        c.launches += 1;
+        if (hipMemcpyAsync(&H->tail_err, &S->tail_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c.st) !=
+                hipSuccess ||
+            hipMemcpyAsync(&H->rounds_done, &S->rounds_done, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) !=
+                hipSuccess)
+          return COLOR_EHIP;
+        if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+        if (H->tail_err) return COLOR_EHIP;  // a grid barrier gave up: the outputs are not valid
+        c.tail_rounds = std::max(0, H->rounds_done - local);
+        return H->tail_left ? COLOR_ENOCONVERGE : COLOR_OK;
+      }
+      // cooperative launch refused: per-round launches from here on
+      (void)hipGetLastError();
+      if (c.timing) c.event_kind.back() = -1;
+      tail_on = false;
+    }
     int64_t gc = std::min<int64_t>((total + kBlock - 1) / kBlock, resident);
     if (gc >= 8) gc = gc / 8 * 8;
     int64_t gd = std::min<int64_t>(round_units(known, L), resident);
@@ -521,20 +599,20 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
     const int grid_c = static_cast<int>(std::max<int64_t>(1, gc));
     const int grid_d = static_cast<int>(std::max<int64_t>(1, gd));
     int n_launch = R;
+    if (tail_on && local > prev_local && total < prev_total) {
+      // poll again about when the worklist should reach the tail threshold,
+      // from its geometric shrink rate over the last batch of rounds
+      const double f = std::pow(static_cast<double>(total) / static_cast<double>(prev_total),
+                                1.0 / static_cast<double>(local - prev_local));
+      const double k = std::ceil(std::log(static_cast<double>(tail_at) / static_cast<double>(total)) / std::log(f));
+      if (k >= 1.0 && k < static_cast<double>(n_launch)) n_launch = static_cast<int>(k);
+    }
+    prev_total = total;
+    prev_local = local;
     if (max_rounds > 0) n_launch = std::min(n_launch, max_rounds - local);
     for (int i = 0; i < n_launch; ++i) {
       ++local;
-      IncBufs b = ib;
-      const int pin = (local - 1) & 1, pout = local & 1;
-      b.wl_in = c.wl[pin];
-      b.wl_out = c.wl[pout];
-      b.cnt_in = S->cnt[pin];
-      b.cnt_out = S->cnt[pout];
-      b.A_in = local == 1 ? A0 : B;
-      b.A_out = B;
-      b.uniform = (local == 1 && !init) ? 1 : 0;
-      b.alen_in = Lb;
-      b.alen_out = Lb;
+      const IncBufs b = round_bufs(local);
       if (c.timing && c.record_event(0)) return COLOR_EHIP;
       launch_inc_color(b, L, local, grid_c, c.st);
       if (c.timing && c.record_event(1)) return COLOR_EHIP;
@@ -550,6 +628,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
       return COLOR_EHIP;
     if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
     for (int i = 0; i < kBins; ++i) known[i] = H->cnt[local & 1][i];
+    // a round cap inside the tail threshold is reached by the tail kernel
     R = std::min(R * 2, 64);
   }
   return COLOR_OK;
@@ -623,9 +702,13 @@ static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32
   int32_t known[kBins];
   if (c.P.engine != COLOR_ENGINE_PULL) {
     // bins without split units (the incremental engine has none; the pull
-    // engine only runs on them here for graphs without heavy vertices)
+    // engine only runs on them here for graphs without heavy vertices), and
+    // unless the caller set them, the incremental engine's own bounds: its
+    // active lists shrink round by round, and a vertex whose list is longer
+    // than one pass of a wavefront is faster on a whole workgroup
     color_params saved = c.P;
     c.P.bin_hi[3] = INT_MAX;
+    if (!c.user_bins) incremental_bins(MODE, c.P.bin_hi);
     e = setup_bins<MODE>(c, g, init, colors, n, L, rb, known);
     c.P = saved;
     if (e) return e;

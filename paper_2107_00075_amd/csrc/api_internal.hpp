@@ -35,12 +35,14 @@ struct Scalars {
   int32_t count_all[8];
   int32_t count_unc[8];
   unsigned long long visits[8]; // [0] sum |W_r|, [1] sum work(W_r), [2] list entries, [3] color bytes,
-                                // [4] detect bytes, [5] pushes
+                                // [4] detect bytes, [5] pushes, [6] + [7] tail-kernel bytes
   unsigned long long list_total; // incremental engine: entries of all lists
   int32_t max_work;              // largest work of an uncolored vertex
   int32_t deferred_cnt;          // heavy D2/PD2 vertices set up by workgroups
   int32_t deferred_grab[2];      // their work counters (work, list fill)
-  int32_t pad3_[2];
+  uint32_t bar[kBarWords];       // tail kernel: grid-barrier words
+  int32_t tail_err;              // tail kernel: error bits (a barrier gave up)
+  int32_t tail_left;             // tail kernel: 1 if it stopped at the round cap with vertices left
   unsigned long long total_work;
   unsigned long long conflicts; // ghost phase-2 conflicts
   unsigned long long remote;    // ghost remote losers
@@ -74,13 +76,16 @@ struct Call {
   // round kernel, resolved after the call's last synchronization
   bool timing = false;
   size_t n_events = 0;
-  std::vector<int> event_kind;  // per event pair start index: 0 color, 1 detect
+  std::vector<int> event_kind;  // per event pair start index: 0 color, 1 detect, 2 tail, -1 none
   int color_launches = 0, detect_launches = 0;
+  int tail_rounds = 0;  // rounds run by the incremental engine's tail kernel
+  bool user_bins = false;  // the caller set degree-bin bounds
   int engine = 1;
   int record_event(int kind_of_next);  // records the next pool event on st
 };
 
 void default_params(int mode, color_params* p);
+void incremental_bins(int mode, int32_t bin_hi[4]);
 int validate_job(const color_job& j, void* stream);
 int merge_params(int mode, const color_params* user, color_params* out);
 int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, void* stream, int32_t n,

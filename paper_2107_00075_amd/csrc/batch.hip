@@ -632,7 +632,9 @@ void job_stats(const BatchJob& J, color_stats* st) {
   st->color_launches = 0;
   st->detect_launches = 0;
   st->engine = COLOR_ENGINE_BATCH;
-  st->reserved_ = 0;
+  st->tail_rounds = 0;
+  st->tail_kernel_ns = 0;
+  st->tail_bytes = 0;
   st->list_visits = 0;
   st->pushes = 0;
   st->color_bytes = 0;

@@ -27,13 +27,35 @@ struct IncBufs {
   uint32_t* F;                 // forbidden-color bitsets (bit c-1 = color c)
   int32_t* maxc;               // largest committed color
   unsigned long long* acc;     // [0] sum |W|, [1] sum work, [2] list entries, [3] color bytes,
-                               // [4] detect bytes, [5] pushes
+                               // [4] detect bytes, [5] pushes, [6] and [7] color and detect bytes
+                               // of the tail kernel
+  int32_t bytes_slot = 3;      // where this launch adds its color bytes (detect: the next slot)
   int32_t* trace;
   int32_t trace_cap;
   int32_t* rounds_done;
 };
 
+// Buffers of round 1 ([0]) and of later odd ([1]) and even ([2]) rounds.
+struct IncRoundSet {
+  IncBufs b[3];
+};
+
+constexpr int32_t kErrTailBarrier = 0x100;  // error bit: a tail-kernel grid barrier gave up
+constexpr int kTailBarrierSeconds = 30;
+// tail-kernel barrier words (32 apart: one cache line each): top arrivals at
+// 0, the generation at kBarGen, group g's arrivals at kBarGroup + 32 g
+constexpr int kBarGen = 32;
+constexpr int kBarGroup = 64;
+constexpr int kBarWords = kBarGroup + 32 * 8;     // a grid barrier of the tail kernel gives up after this long
+constexpr int32_t kTailDefault = 32768;     // default worklist size at which the tail kernel takes over
+
 void launch_inc_color(const IncBufs& b, const BinLayout& L, int round, int grid, hipStream_t st);
+// All remaining rounds in one cooperative launch (grid <= tail_blocks_resident());
+// false if the runtime refused the launch.
+bool launch_inc_tail(const KeySource& k, const IncRoundSet& set, const BinLayout& L, int round0, int round_cap,
+                    uint32_t* bar, int32_t* err, int32_t* left, int grid, hipStream_t st);
+// Workgroups of the tail kernel that fit on the device at once (-1: unknown).
+int tail_blocks_resident();
 void launch_inc_detect(const KeySource& k, const IncBufs& b, const BinLayout& L, int round, int grid,
                        hipStream_t st);
 template <int MODE>

@@ -21,15 +21,19 @@ def gc():
     return m
 
 
-ENGINE = {"id": 0}
+ENGINE = {"id": 0, "flags": 0}
 
 
-@pytest.fixture(autouse=True, scope="module", params=[2, 1], ids=["incremental", "pull"])
+@pytest.fixture(autouse=True, scope="module", params=[(2, 0), (2, 2), (1, 0)],
+                ids=["incremental", "incremental-no-tail", "pull"])
 def engine(request):
-    """Every parity case runs on both engines (2 = incremental, 1 = pull)."""
-    ENGINE["id"] = request.param
+    """Every parity case runs on both engines (2 = incremental, 1 = pull); the
+    incremental engine both with its cooperative tail kernel (the default: it
+    takes over once the worklist is small, which is every round of most of
+    these graphs) and with per-round launches only (COLOR_FLAG_NO_TAIL = 2)."""
+    ENGINE["id"], ENGINE["flags"] = request.param
     yield request.param
-    ENGINE["id"] = 0
+    ENGINE["id"], ENGINE["flags"] = 0, 0
 
 
 def with_engine(gc, kw):
@@ -37,6 +41,7 @@ def with_engine(gc, kw):
     if p is None:
         p = gc.Params()
     p.engine = ENGINE["id"]
+    p.flags |= ENGINE["flags"]
     kw["params"] = p
     return kw
 
