@@ -73,7 +73,7 @@ void Workspace::release() {
   events.clear();
   for (DevBuf* b : {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
                     &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
-                    &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &scan_tmp})
+                    &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &inc_wl0, &inc_wl1, &scan_tmp})
     b->release();
   if (host) (void)hipHostFree(host);
   host = nullptr;
@@ -276,7 +276,10 @@ int setup_bins(Call& c, const GraphView& g, const int32_t* init, int32_t* C, int
     L.off[i] = off;
     off += H->count_all[i];
   }
-  for (int i = 0; i < 3; ++i) L.lanes[i] = c.P.lanes[i];
+  for (int i = 0; i < 3; ++i) {
+    L.lanes[i] = c.P.lanes[i];
+    L.hi[i] = c.P.bin_hi[i];
+  }
   L.split_chunks = c.P.split_chunks;
   L.grab = 4;
   const int32_t nsplit = H->count_all[kSplitBin];
@@ -528,6 +531,35 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
     c.launches += 1;
   }
   if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
+  // Worklists binned by active-list length: a loser goes to the bin of its
+  // current list, never above the bin of its static work, so bin b's region
+  // holds every vertex whose static bin is b or above.  The round-1
+  // worklist moves over from the static layout.
+  BinLayout IL = L;
+  int64_t wl_total = 0;
+  {
+    int64_t above = 0, cap[kBins];
+    cap[kSplitBin] = known[kSplitBin];  // none: this engine bins without split units
+    for (int i = kBlockBin; i >= 0; --i) {
+      above += known[i];
+      cap[i] = above;
+    }
+    for (int i = 0; i < kBins; ++i) {
+      IL.off[i] = static_cast<int32_t>(std::min<int64_t>(wl_total, INT_MAX));
+      wl_total += cap[i];
+    }
+  }
+  if (wl_total >= INT_MAX) return COLOR_EOVERFLOW;
+  if ((e = w->inc_wl0.ensure(sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(wl_total, 1)), false, c.st)))
+    return e;
+  if ((e = w->inc_wl1.ensure(sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(wl_total, 1)), false, c.st)))
+    return e;
+  int32_t* wl[2] = {w->inc_wl0.as<int32_t>(), w->inc_wl1.as<int32_t>()};
+  for (int i = 0; i < kBins; ++i) {
+    if (known[i] > 0 && hipMemcpyAsync(wl[0] + IL.off[i], c.wl[0] + L.off[i], sizeof(int32_t) * known[i],
+                                       hipMemcpyDeviceToDevice, c.st) != hipSuccess)
+      return COLOR_EHIP;
+  }
   const int resident = std::min(resident_inc_blocks(), std::max(8, c.P.max_workgroups));
   const int max_rounds = c.P.max_rounds;
   // the buffers of round r: worklists and counts ping-pong; round 1 reads the
@@ -535,8 +567,8 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   auto round_bufs = [&](int r) {
     IncBufs b = ib;
     const int pin = (r - 1) & 1, pout = r & 1;
-    b.wl_in = c.wl[pin];
-    b.wl_out = c.wl[pout];
+    b.wl_in = wl[pin];
+    b.wl_out = wl[pout];
     b.cnt_in = S->cnt[pin];
     b.cnt_out = S->cnt[pout];
     b.A_in = r == 1 ? A0 : B;
@@ -560,7 +592,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
     if (tail_on && total <= tail_at) {
       // the remaining rounds in one cooperative launch: no launch gaps and no
       // host polls between the (small) rounds of the tail
-      int64_t g = std::max<int64_t>((total + kBlock - 1) / kBlock, round_units(known, L));
+      int64_t g = std::max<int64_t>((total + kBlock - 1) / kBlock, inc_round_units(known, IL));
       g = std::min<int64_t>(g, std::min(tail_blocks_resident(), std::max(8, c.P.max_workgroups)));
       if (g >= 8) g = g / 8 * 8;
       IncRoundSet set;
@@ -573,7 +605,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
       if (hipMemsetAsync(S->bar, 0, sizeof(S->bar) + 2 * sizeof(int32_t), c.st) != hipSuccess) return COLOR_EHIP;
       const int cap = max_rounds > 0 ? max_rounds : INT_MAX;
       if (c.timing && c.record_event(2)) return COLOR_EHIP;
-      if (launch_inc_tail(k, set, L, local + 1, cap, S->bar, &S->tail_err, &S->tail_left,
+      if (launch_inc_tail(k, set, IL, local + 1, cap, S->bar, &S->tail_err, &S->tail_left,
                           static_cast<int>(std::max<int64_t>(1, g)), c.st)) {
         if (c.timing && c.record_event(-1)) return COLOR_EHIP;
         c.launches += 1;
@@ -594,7 +626,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
     }
     int64_t gc = std::min<int64_t>((total + kBlock - 1) / kBlock, resident);
     if (gc >= 8) gc = gc / 8 * 8;
-    int64_t gd = std::min<int64_t>(round_units(known, L), resident);
+    int64_t gd = std::min<int64_t>(inc_round_units(known, IL), resident);
     if (gd >= 8) gd = gd / 8 * 8;
     const int grid_c = static_cast<int>(std::max<int64_t>(1, gc));
     const int grid_d = static_cast<int>(std::max<int64_t>(1, gd));
@@ -614,9 +646,9 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
       ++local;
       const IncBufs b = round_bufs(local);
       if (c.timing && c.record_event(0)) return COLOR_EHIP;
-      launch_inc_color(b, L, local, grid_c, c.st);
+      launch_inc_color(b, IL, local, grid_c, c.st);
       if (c.timing && c.record_event(1)) return COLOR_EHIP;
-      launch_inc_detect(k, b, L, local, grid_d, c.st);
+      launch_inc_detect(k, b, IL, local, grid_d, c.st);
       if (c.timing && c.record_event(-1)) return COLOR_EHIP;
       c.launches += 2;
       c.color_launches += 1;

@@ -36,20 +36,29 @@ namespace {
 
 struct IncMap {
   int32_t cnt[kBins];
+  int32_t csize[3];     // vertices per chunk of bins 0..2: kIncPasses passes of the lane groups
   int32_t chunks[3];
   int32_t light_total;
   int32_t heavy_total;  // one unit per bin-3/bin-4 vertex (the incremental engine has no split units)
   int32_t total;        // all worklist entries
 };
 
-__device__ __forceinline__ void make_inc_map(const IncBufs& b, IncMap& m) {
+// Bin of a vertex by the current length of its active list (both parts):
+// lists only shrink, so a vertex moves to narrower lane groups as its
+// neighbours commit (never above the bin of its static work).
+__device__ __forceinline__ int inc_bin_of(const BinLayout& L, int32_t len) {
+  return len <= L.hi[0] ? 0 : len <= L.hi[1] ? 1 : len <= L.hi[2] ? 2 : kBlockBin;
+}
+
+__device__ __forceinline__ void make_inc_map(const IncBufs& b, const BinLayout& L, IncMap& m) {
   int32_t lt = 0, tot = 0;
   for (int i = 0; i < kBins; ++i) {
     m.cnt[i] = ld_dev(&b.cnt_in[i]);
     tot += m.cnt[i];
   }
   for (int i = 0; i < 3; ++i) {
-    m.chunks[i] = (m.cnt[i] + kBlock - 1) / kBlock;
+    m.csize[i] = inc_chunk_size(L.lanes[i]);
+    m.chunks[i] = (m.cnt[i] + m.csize[i] - 1) / m.csize[i];
     lt += m.chunks[i];
   }
   m.light_total = lt;
@@ -115,7 +124,7 @@ __device__ __forceinline__ void inc_color_phase(const IncBufs& b, const BinLayou
   IncMap& M = sh.M;
   unsigned long long* s_acc = sh.acc;
   if (threadIdx.x == 0) {
-    make_inc_map(b, M);
+    make_inc_map(b, L, M);
     s_acc[0] = s_acc[1] = s_acc[2] = 0ull;
     if (blockIdx.x == 0) {
       for (int i = 0; i < kBins; ++i) atomic_reset_i32(&b.cnt_out[i]);
@@ -188,9 +197,10 @@ __global__ __launch_bounds__(kBlock) void inc_color_kernel(IncBufs b, BinLayout 
 // higher-key neighbour can beat v, so later detect scans read the front part
 // only; the one push a winner makes reads both parts.
 template <int G>
-__device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, int round, int bin, const int32_t* wl,
-                                 int32_t count, int32_t off_out, int32_t* s_ent, int32_t* s_wc,
-                                 int32_t& maxc_acc, uint64_t& bytes, uint64_t& pushes) {
+__device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, const BinLayout& L, int round,
+                                                 const int32_t* wl, int32_t count, int32_t* s_ent, int8_t* s_tb,
+                                                 int32_t* s_wc, int32_t& maxc_acc, uint64_t& bytes,
+                                                 uint64_t& pushes) {
   constexpr int per_pass = kBlock / G;
   const int gi = threadIdx.x / G;
   const int sub = threadIdx.x % G;
@@ -229,7 +239,8 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
     if (lose && !compact_now(b, round, v)) {
       if (sub == 0) {
         s_ent[idx] = v;
-        bytes += 20;
+        s_tb[idx] = static_cast<int8_t>(inc_bin_of(L, len + ld_dev(&b.llen[v])));  // not the first pass
+        bytes += 24;
       }
     } else if (lose) {
       // keep the neighbours that are not committed (yet); the first pass
@@ -256,8 +267,10 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
       if (sub == 0) {
         st_dev(&b.alen_out[v], kept);
         if (first_pass) st_dev(&b.llen[v], kept_lo);
+        else kept_lo = ld_dev(&b.llen[v]);
         s_ent[idx] = v;
-        bytes += 24 + 8ull * static_cast<uint64_t>(len) + 4ull * static_cast<uint64_t>(kept + kept_lo);
+        s_tb[idx] = static_cast<int8_t>(inc_bin_of(L, kept + kept_lo));
+        bytes += 28 + 8ull * static_cast<uint64_t>(len) + 4ull * static_cast<uint64_t>(kept + kept_lo);
       }
     } else {
       // push the color to the uncommitted neighbours: the whole list on the
@@ -291,25 +304,39 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
       }
     }
   }
+  // append the losers to the next worklist, each to the bin of its list
+  // length: per target bin a wave count, a scan over the waves and one
+  // counter atomic per workgroup
   __syncthreads();
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const int32_t x = tid < count ? s_ent[tid] : -1;
-  const uint64_t bal = __ballot(x >= 0);
-  if (lane_id() == 0) s_wc[wave] = static_cast<int32_t>(__popcll(bal));
-  __syncthreads();
-  if (tid == 0) {
-    int32_t tot = 0;
-    for (int w = 0; w < kWavesPerBlock; ++w) {
-      const int32_t c = s_wc[w];
-      s_wc[w] = tot;
-      tot += c;
-    }
-    s_wc[kWavesPerBlock] = tot ? atomicAdd(&b.cnt_out[bin], tot) : 0;
+  const int t = x >= 0 ? s_tb[tid] : -1;
+  const uint64_t b0 = __ballot(t == 0), b1 = __ballot(t == 1), b2 = __ballot(t == 2), b3 = __ballot(t == kBlockBin);
+  if (lane_id() == 0) {
+    s_wc[0 * kWavesPerBlock + wave] = static_cast<int32_t>(__popcll(b0));
+    s_wc[1 * kWavesPerBlock + wave] = static_cast<int32_t>(__popcll(b1));
+    s_wc[2 * kWavesPerBlock + wave] = static_cast<int32_t>(__popcll(b2));
+    s_wc[3 * kWavesPerBlock + wave] = static_cast<int32_t>(__popcll(b3));
   }
   __syncthreads();
-  if (x >= 0)
-    st_dev(&b.wl_out[off_out + s_wc[kWavesPerBlock] + s_wc[wave] + static_cast<int32_t>(lanes_below(bal))], x);
+  if (tid < 4) {
+    int32_t tot = 0;
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+      const int32_t c = s_wc[tid * kWavesPerBlock + w];
+      s_wc[tid * kWavesPerBlock + w] = tot;
+      tot += c;
+    }
+    s_wc[4 * kWavesPerBlock + tid] = tot ? atomicAdd(&b.cnt_out[tid == 3 ? kBlockBin : tid], tot) : 0;
+  }
+  __syncthreads();
+  if (x >= 0) {
+    const uint64_t mine = t == 0 ? b0 : t == 1 ? b1 : t == 2 ? b2 : b3;
+    const int q = t == kBlockBin ? 3 : t;
+    st_dev(&b.wl_out[L.off[t] + s_wc[4 * kWavesPerBlock + q] + s_wc[q * kWavesPerBlock + wave] +
+                     static_cast<int32_t>(lanes_below(mine))],
+           x);
+  }
   __syncthreads();
 }
 
@@ -318,9 +345,9 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
 // at a barrier once per kBlock * kIncBatch entries.
 constexpr int kIncBatch = 8;
 
-__device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBufs& b, int round, int32_t v, int bin,
-                                 int32_t off, int32_t* s_wc, int32_t& maxc_acc, uint64_t& bytes,
-                                 uint64_t& pushes) {
+__device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBufs& b, const BinLayout& L, int round,
+                                                 int32_t v, int32_t* s_wc, int32_t& maxc_acc, uint64_t& bytes,
+                                                 uint64_t& pushes) {
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const bool first_pass = b.A_in != b.A_out;
@@ -359,9 +386,10 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
   bytes += 4ull * read;  // list entries and tentative colors this thread read
   if (lose && !compact_now(b, round, v)) {
     if (tid == 0) {
-      const int32_t p = atomicAdd(&b.cnt_out[bin], 1);
-      st_dev(&b.wl_out[off + p], v);
-      bytes += 24;
+      const int nb = inc_bin_of(L, len + ld_dev(&b.llen[v]));  // not the first pass
+      const int32_t p = atomicAdd(&b.cnt_out[nb], 1);
+      st_dev(&b.wl_out[L.off[nb] + p], v);
+      bytes += 28;
     }
   } else if (lose) {
     // keep the neighbours that are not committed (yet), order free; the
@@ -461,8 +489,9 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
     if (tid == 0) {
       st_dev(&b.alen_out[v], kept);
       st_dev(&b.llen[v], kept_lo);
-      const int32_t p = atomicAdd(&b.cnt_out[bin], 1);
-      st_dev(&b.wl_out[off + p], v);
+      const int nb = inc_bin_of(L, kept + kept_lo);
+      const int32_t p = atomicAdd(&b.cnt_out[nb], 1);
+      st_dev(&b.wl_out[L.off[nb] + p], v);
       bytes += 24 + 8ull * static_cast<uint64_t>(len + lo_len) + 4ull * static_cast<uint64_t>(kept + kept_lo);
     }
   } else {
@@ -500,7 +529,8 @@ struct IncDetectShared {
   int32_t unit;
   int32_t max;
   int32_t ent[kBlock];
-  int32_t wc[2 * kWavesPerBlock + 1];
+  int8_t tb[kBlock];                    // target bin of each loser in ent
+  int32_t wc[4 * kWavesPerBlock + 4];   // per-target-bin wave offsets, then per-bin bases
   unsigned long long acc[2];
   IncMap M;
 };
@@ -511,10 +541,11 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
   int32_t& s_max = sh.max;
   int32_t* s_ent = sh.ent;
   int32_t* s_wc = sh.wc;
+  int8_t* s_tb = sh.tb;
   unsigned long long* s_acc = sh.acc;
   IncMap& M = sh.M;
   if (threadIdx.x == 0) {
-    make_inc_map(b, M);
+    make_inc_map(b, L, M);
     s_max = 0;
     s_acc[0] = s_acc[1] = 0ull;
   }
@@ -531,18 +562,17 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
       cc -= M.chunks[bin];
       ++bin;
     }
-    const int32_t firstc = cc * kBlock;
-    const int32_t count = min(kBlock, M.cnt[bin] - firstc);
+    const int32_t firstc = cc * M.csize[bin];
+    const int32_t count = min(M.csize[bin], M.cnt[bin] - firstc);
     const int32_t* wl = b.wl_in + L.off[bin] + firstc;
-    const int32_t oo = L.off[bin];
     switch (L.lanes[bin]) {
-      case 1: inc_detect_chunk<1>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      case 2: inc_detect_chunk<2>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      case 4: inc_detect_chunk<4>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      case 8: inc_detect_chunk<8>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      case 16: inc_detect_chunk<16>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      case 32: inc_detect_chunk<32>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
-      default: inc_detect_chunk<64>(k, b, round, bin, wl, count, oo, s_ent, s_wc, maxc_acc, bytes, pushes); break;
+      case 1: inc_detect_chunk<1>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 2: inc_detect_chunk<2>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 4: inc_detect_chunk<4>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 8: inc_detect_chunk<8>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 16: inc_detect_chunk<16>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 32: inc_detect_chunk<32>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      default: inc_detect_chunk<64>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
     }
   }
   // heavy units: the first one of every workgroup is its own (no atomic),
@@ -551,7 +581,7 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
     const int bin = u < M.cnt[kBlockBin] ? kBlockBin : kSplitBin;
     const int32_t j = bin == kBlockBin ? u : u - M.cnt[kBlockBin];
     const int32_t v = ld_dev(&b.wl_in[L.off[bin] + j]);
-    inc_detect_block(k, b, round, v, bin, L.off[bin], s_wc, maxc_acc, bytes, pushes);
+    inc_detect_block(k, b, L, round, v, s_wc, maxc_acc, bytes, pushes);
     if (threadIdx.x == 0) s_unit = static_cast<int32_t>(gridDim.x) + atomicAdd(&b.tile_ctr[1], 1);
     __syncthreads();
     u = s_unit;

@@ -35,6 +35,25 @@ struct IncBufs {
   int32_t* rounds_done;
 };
 
+// Vertices per light chunk of a bin with `lanes` lanes per vertex: a chunk
+// takes kIncPasses passes of the workgroup's lane groups, so that a bin of
+// wide groups (whose vertices are processed few at a time) is spread over
+// many workgroups.
+constexpr int kIncPasses = 2;
+__host__ __device__ inline int32_t inc_chunk_size(int32_t lanes) {
+  const int32_t c = (kBlock / lanes) * kIncPasses;
+  return c < kBlock ? c : kBlock;
+}
+// Work units of a round: light chunks plus one unit per heavy vertex.
+inline int64_t inc_round_units(const int32_t cnt[kBins], const BinLayout& L) {
+  int64_t u = 0;
+  for (int b = 0; b < 3; ++b) {
+    const int32_t cs = inc_chunk_size(L.lanes[b]);
+    u += (cnt[b] + cs - 1) / cs;
+  }
+  return u + cnt[kBlockBin] + cnt[kSplitBin];
+}
+
 // Buffers of round 1 ([0]) and of later odd ([1]) and even ([2]) rounds.
 struct IncRoundSet {
   IncBufs b[3];

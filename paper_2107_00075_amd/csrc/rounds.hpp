@@ -31,6 +31,8 @@ struct BinLayout {
   int32_t lanes[3];       // lanes per vertex of bins 0..2 (power of two <= 64)
   int32_t split_chunks;   // workgroups per split vertex
   int32_t grab;           // tiles of bins 0..2 taken per dynamic grab
+  int32_t hi[3];          // work bounds of bins 0..2 (the incremental engine also bins its
+                          // active lists by length with them)
 };
 
 // Per-round buffers (device pointers, resolved for the round's parity).
