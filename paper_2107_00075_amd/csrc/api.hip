@@ -106,14 +106,15 @@ Workspace* workspace_for_current_device(int* err) {
 // parameters
 // ---------------------------------------------------------------------------
 
-// Degree-bin work bounds (bins 0..2) for the incremental engine, measured on
-// MI355X: R-MAT scale 22 (D1) 69 -> 60 ms against the pull engine's bounds,
-// the 4M x 1M power-law PD2 pattern 285 -> 126 ms.
+// Degree-bin bounds (bins 0..2) for the incremental engine, on work and on
+// active-list length, measured on MI355X against the pull engine's bounds:
+// R-MAT scale 22 (D1) 69 -> 46 ms, the 4M x 1M power-law PD2 pattern
+// 285 -> 125 ms.
 void incremental_bins(int mode, int32_t bin_hi[4]) {
   if (mode == kD1) {
     bin_hi[0] = 16;
-    bin_hi[1] = 64;
-    bin_hi[2] = 512;
+    bin_hi[1] = 96;
+    bin_hi[2] = 1024;
   } else {
     bin_hi[0] = 64;
     bin_hi[1] = 256;
@@ -495,16 +496,33 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   const int32_t* A0 = g.ci;
   if (MODE != kD1) {
     if ((e = w->inc_B1.ensure(sizeof(int32_t) * list_entries, false, c.st))) return e;
-    launch_inc_fill<MODE>(g, aoff, len, B, w->deferred.as<int32_t>(), &S->deferred_cnt, &S->deferred_grab[1],
-                          c.st);
-    c.launches += 2;
-    A0 = B;
+    // heavy (deferred) vertices: their sets through one bitmap each when the
+    // bitmaps of all of them together stay small, else a workgroup per list
+    // and the duplicate removal below
     const int32_t words = n / 32 + 1;
+    const int32_t nd = H->deferred_cnt;  // from the setup's read-back
+    const bool sets = nd > 0 && static_cast<int64_t>(nd) * words <= kSetsMaxWords;
+    const int32_t nb_max = sets ? static_cast<int32_t>(std::max<int64_t>(
+                                      1, std::min<int64_t>(nd, kSetsBatchWords / words)))
+                                : 0;
+    launch_inc_fill<MODE>(g, aoff, len, B, w->deferred.as<int32_t>(), &S->deferred_cnt, &S->deferred_grab[1], !sets,
+                          c.st);
+    c.launches += sets ? 1 : 2;
+    A0 = B;
     const int grid = dedup_grid(words);
     const size_t bm_bytes = sizeof(uint32_t) * static_cast<size_t>(words) * static_cast<size_t>(grid);
-    if ((e = w->inc_bm.ensure(bm_bytes, false, c.st))) return e;
+    const size_t sets_bytes = sizeof(uint32_t) * static_cast<size_t>(words) * static_cast<size_t>(nb_max);
+    if ((e = w->inc_bm.ensure(std::max(bm_bytes, sets_bytes), false, c.st))) return e;
+    for (int32_t i0 = 0; sets && i0 < nd; i0 += nb_max) {
+      const int32_t nb = std::min(nb_max, nd - i0);
+      if (hipMemsetAsync(w->inc_bm.p, 0, sizeof(uint32_t) * static_cast<size_t>(words) * nb, c.st) != hipSuccess)
+        return COLOR_EHIP;
+      launch_inc_bitmap_sets<MODE>(g, w->deferred.as<int32_t>(), i0, nb, w->inc_bm.as<uint32_t>(), words, aoff, Lb,
+                                   B, c.st);
+      c.launches += 2;
+    }
     if (hipMemsetAsync(w->inc_bm.p, 0, bm_bytes, c.st) != hipSuccess) return COLOR_EHIP;
-    launch_inc_dedup(n, aoff, Lb, B, w->inc_bm.as<uint32_t>(), words, grid, c.st);
+    launch_inc_dedup(n, aoff, Lb, B, w->inc_bm.as<uint32_t>(), words, grid, sets ? g.rp : nullptr, c.st);
     c.launches += 1;
     B = w->inc_B1.as<int32_t>();  // the split lists
   }

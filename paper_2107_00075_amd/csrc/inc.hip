@@ -888,7 +888,8 @@ void launch_inc_sizes(const GraphView& g, const int32_t* work, int32_t* len, int
 constexpr int32_t kDedupMin = 4096;
 
 __global__ __launch_bounds__(kBlock) void inc_dedup_kernel(int32_t n, const int32_t* aoff, int32_t* alen,
-                                                           int32_t* A, uint32_t* bitmaps, int32_t words) {
+                                                           int32_t* A, uint32_t* bitmaps, int32_t words,
+                                                           const int32_t* skip_rp) {
   __shared__ int32_t s_wc[kWavesPerBlock];
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
@@ -897,6 +898,7 @@ __global__ __launch_bounds__(kBlock) void inc_dedup_kernel(int32_t n, const int3
   for (int32_t v = blockIdx.x; v < n; v += gridDim.x) {
     const int32_t len = ld_dev(&alen[v]);
     if (len <= kDedupMin) continue;
+    if (skip_rp && skip_rp[v + 1] - skip_rp[v] > kSetupHeavy) continue;  // built as sets already
     int32_t* L = A + ld_dev(&aoff[v]);
     int32_t kept = 0;
     for (int32_t e0 = 0; e0 < len; e0 += step) {
@@ -943,13 +945,79 @@ __global__ __launch_bounds__(kBlock) void inc_dedup_kernel(int32_t n, const int3
   }
 }
 
+// Two-hop sets of heavy (deferred) vertices built as bitmaps, for graphs
+// where one bitmap of the id range per heavy vertex is affordable: every
+// first-hop entry of every heavy vertex is its own thread (blockIdx.y picks
+// the vertex, the x blocks stride over its entries), so the longest walk is
+// spread over many workgroups instead of one; the bits then become the list,
+// duplicate-free and in id order.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void inc_mark_kernel(GraphView g, const int32_t* deferred, int32_t i0,
+                                                         uint32_t* bm, int32_t words, int32_t* alen) {
+  const int32_t v = ld_dev(&deferred[i0 + static_cast<int32_t>(blockIdx.y)]);
+  uint32_t* m = bm + static_cast<size_t>(blockIdx.y) * static_cast<size_t>(words);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st_dev(&alen[v], 0);
+  const int32_t q1 = g.rp[v + 1];
+  for (int32_t q = g.rp[v] + static_cast<int32_t>(blockIdx.x * kBlock + threadIdx.x); q < q1;
+       q += static_cast<int32_t>(gridDim.x * kBlock)) {
+    const int32_t u = g.ci[q];
+    if (MODE == kD2 && u != v) atomicOr(&m[u >> 5], 1u << (u & 31));
+    for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
+      const int32_t x = g.ci2[p];
+      if (x != v) atomicOr(&m[x >> 5], 1u << (x & 31));
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void inc_bitmap_list_kernel(const int32_t* deferred, int32_t i0,
+                                                                 const uint32_t* bm, int32_t words,
+                                                                 const int32_t* aoff, int32_t* alen, int32_t* A) {
+  const int32_t v = ld_dev(&deferred[i0 + static_cast<int32_t>(blockIdx.y)]);
+  const uint32_t* m = bm + static_cast<size_t>(blockIdx.y) * static_cast<size_t>(words);
+  int32_t* out = A + ld_dev(&aoff[v]);
+  for (int32_t w0 = static_cast<int32_t>(blockIdx.x * kBlock); w0 < words;
+       w0 += static_cast<int32_t>(gridDim.x * kBlock)) {
+    const int32_t w = w0 + static_cast<int32_t>(threadIdx.x);
+    uint32_t x = w < words ? ld_dev(&m[w]) : 0u;
+    const int32_t c = __popc(x);
+    int32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int32_t y = __shfl_up(incl, o, kWave);
+      if (lane_id() >= o) incl += y;
+    }
+    const int32_t tot = __shfl(incl, kWave - 1, kWave);
+    int32_t base = 0;
+    if (lane_id() == kWave - 1 && tot > 0) base = atomicAdd(&alen[v], tot);
+    base = __shfl(base, kWave - 1, kWave);
+    int32_t pos = base + incl - c;
+    while (x) {
+      const int bit = __builtin_ctz(x);
+      x &= x - 1u;
+      st_dev(&out[pos++], 32 * w + bit);
+    }
+  }
+}
+
 template <int MODE>
 void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A,
-                     const int32_t* deferred, const int32_t* nd, int32_t* grab, hipStream_t st) {
+                     const int32_t* deferred, const int32_t* nd, int32_t* grab, bool heavy, hipStream_t st) {
   if (g.n <= 0) return;
   hipLaunchKernelGGL(inc_fill_kernel<MODE>, dim3(blocks_for(g.n)), dim3(kBlock), 0, st, g, aoff, len, A);
-  hipLaunchKernelGGL(inc_fill_heavy_kernel<MODE>, dim3(std::min(blocks_for(g.n), 512)), dim3(kBlock), 0, st, g,
-                     aoff, len, A, deferred, nd, grab);
+  if (heavy)
+    hipLaunchKernelGGL(inc_fill_heavy_kernel<MODE>, dim3(std::min(blocks_for(g.n), 512)), dim3(kBlock), 0, st, g,
+                       aoff, len, A, deferred, nd, grab);
+}
+
+template <int MODE>
+void launch_inc_bitmap_sets(const GraphView& g, const int32_t* deferred, int32_t i0, int32_t nb, uint32_t* bm,
+                            int32_t words, const int32_t* aoff, int32_t* alen, int32_t* A, hipStream_t st) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(inc_mark_kernel<MODE>, dim3(kSetsBlocksPerVertex, nb), dim3(kBlock), 0, st, g, deferred, i0, bm,
+                     words, alen);
+  const int wx = std::max(1, std::min(kSetsBlocksPerVertex, (words + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(inc_bitmap_list_kernel, dim3(wx, nb), dim3(kBlock), 0, st, deferred, i0, bm, words, aoff, alen,
+                     A);
 }
 int dedup_grid(int32_t words) {
   const size_t per = sizeof(uint32_t) * static_cast<size_t>(words);
@@ -958,9 +1026,9 @@ int dedup_grid(int32_t words) {
 }
 
 void launch_inc_dedup(int32_t n, const int32_t* aoff, int32_t* alen, int32_t* A, uint32_t* bitmaps, int32_t words,
-                      int grid, hipStream_t st) {
+                      int grid, const int32_t* skip_rp, hipStream_t st) {
   if (n > 0)
-    hipLaunchKernelGGL(inc_dedup_kernel, dim3(grid), dim3(kBlock), 0, st, n, aoff, alen, A, bitmaps, words);
+    hipLaunchKernelGGL(inc_dedup_kernel, dim3(grid), dim3(kBlock), 0, st, n, aoff, alen, A, bitmaps, words, skip_rp);
 }
 
 void launch_inc_init_push(const IncBufs& b, int32_t n, const int32_t* A0, hipStream_t st) {
@@ -972,10 +1040,14 @@ template void launch_inc_sizes<kD2>(const GraphView&, const int32_t*, int32_t*, 
                                     unsigned long long*, hipStream_t);
 template void launch_inc_sizes<kPD2>(const GraphView&, const int32_t*, int32_t*, int32_t*, int32_t*,
                                      unsigned long long*, hipStream_t);
+template void launch_inc_bitmap_sets<kD2>(const GraphView&, const int32_t*, int32_t, int32_t, uint32_t*, int32_t,
+                                          const int32_t*, int32_t*, int32_t*, hipStream_t);
+template void launch_inc_bitmap_sets<kPD2>(const GraphView&, const int32_t*, int32_t, int32_t, uint32_t*, int32_t,
+                                           const int32_t*, int32_t*, int32_t*, hipStream_t);
 template void launch_inc_fill<kD2>(const GraphView&, const int32_t*, const int32_t*, int32_t*, const int32_t*,
-                                   const int32_t*, int32_t*, hipStream_t);
+                                   const int32_t*, int32_t*, bool, hipStream_t);
 template void launch_inc_fill<kPD2>(const GraphView&, const int32_t*, const int32_t*, int32_t*, const int32_t*,
-                                    const int32_t*, int32_t*, hipStream_t);
+                                    const int32_t*, int32_t*, bool, hipStream_t);
 
 int exclusive_scan_i32(const int32_t* in, int32_t* out, int32_t n_plus_1, void* tmp, size_t* tmp_bytes,
                        hipStream_t st) {

@@ -80,15 +80,28 @@ void launch_inc_detect(const KeySource& k, const IncBufs& b, const BinLayout& L,
 template <int MODE>
 void launch_inc_sizes(const GraphView& g, const int32_t* work, int32_t* len, int32_t* words, int32_t* alen0,
                       unsigned long long* total, hipStream_t st);
+// Materializes the two-hop lists: one thread per light vertex, and (heavy)
+// one workgroup per deferred vertex.
 template <int MODE>
 void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A,
-                     const int32_t* deferred, const int32_t* nd, int32_t* grab, hipStream_t st);
+                     const int32_t* deferred, const int32_t* nd, int32_t* grab, bool heavy, hipStream_t st);
+// The lists of deferred vertices i0 .. i0+nb-1 as duplicate-free sets, through
+// bitmaps of `words` words each (bm: nb x words, zeroed by the caller); alen
+// receives the set sizes.
+constexpr int kSetsBlocksPerVertex = 64;
+constexpr int64_t kSetsMaxWords = int64_t{1} << 28;    // all heavy bitmaps together (1 GiB), else per-list
+constexpr int64_t kSetsBatchWords = int64_t{1} << 27;  // bitmaps of one batch (512 MiB)
+template <int MODE>
+void launch_inc_bitmap_sets(const GraphView& g, const int32_t* deferred, int32_t i0, int32_t nb, uint32_t* bm,
+                            int32_t words, const int32_t* aoff, int32_t* alen, int32_t* A, hipStream_t st);
 void launch_inc_init_push(const IncBufs& b, int32_t n, const int32_t* A0, hipStream_t st);
 // Removes duplicates from the long two-hop lists (alen in: capacity, out:
 // distinct entries); bitmaps: grid x words zeroed uint32 (left zeroed).
 int dedup_grid(int32_t words);
+// skip_rp (nullable): the first-hop row offsets; vertices deferred by their
+// first-hop length are skipped (their lists were built as sets).
 void launch_inc_dedup(int32_t n, const int32_t* aoff, int32_t* alen, int32_t* A, uint32_t* bitmaps, int32_t words,
-                      int grid, hipStream_t st);
+                      int grid, const int32_t* skip_rp, hipStream_t st);
 int resident_inc_blocks();
 
 // Exclusive prefix sum of n+1 int32 values (the last input is 0, so out[n] is

@@ -240,6 +240,33 @@ def test_pd2_square_pattern_and_single_row(gc):
     same(got1, st1, ref1, "PD2 single row")
 
 
+def test_pd2_heavy_columns(gc):
+    """Columns in more than 1024 rows: the incremental engine builds their
+    two-hop lists as duplicate-free sets through bitmaps."""
+    rng = np.random.default_rng(5)
+    n_rows, n_cols = 3000, 4000
+    a = np.zeros((n_rows, n_cols), dtype=bool)
+    a[:, 0] = True        # column 0 in every row
+    a[:1500, 1] = True    # column 1 in half of them
+    for r in range(n_rows):
+        a[r, 2 + rng.choice(n_cols - 2, 3, replace=False)] = True
+    b = gg.bipartite_from_dense(a)
+    ref = oracle.color_pd2(b, seed=4)
+    got, st = run_pd2(gc, b, seed=4)
+    same(got, st, ref, "PD2 heavy columns")
+
+
+def test_d2_heavy_vertex(gc):
+    """A vertex of degree 1025 (its two-hop list built as a bitmap set by the
+    incremental engine) whose leaves also form a path: a D2 clique of 1026."""
+    leaves = 1025
+    edges = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 1) for i in range(1, leaves)]
+    g = gg.from_edge_list(leaves + 1, edges)
+    ref = oracle.color_d2(g, seed=6)
+    got, st = run_d2(gc, g, seed=6)
+    same(got, st, ref, "D2 heavy vertex")
+
+
 # ------------------------------------------------------------------------ ghost
 
 def _ghost_case(seed, layers, n=20000, parts=4):
