@@ -507,7 +507,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
                                 : 0;
     launch_inc_fill<MODE>(g, aoff, len, B, w->deferred.as<int32_t>(), &S->deferred_cnt, &S->deferred_grab[1], !sets,
                           c.st);
-    c.launches += sets ? 1 : 2;
+    c.launches += sets ? 2 : 3;
     A0 = B;
     const int grid = dedup_grid(words);
     const size_t bm_bytes = sizeof(uint32_t) * static_cast<size_t>(words) * static_cast<size_t>(grid);

@@ -80,8 +80,10 @@ void launch_inc_detect(const KeySource& k, const IncBufs& b, const BinLayout& L,
 template <int MODE>
 void launch_inc_sizes(const GraphView& g, const int32_t* work, int32_t* len, int32_t* words, int32_t* alen0,
                       unsigned long long* total, hipStream_t st);
-// Materializes the two-hop lists: one thread per light vertex, and (heavy)
+// Materializes the two-hop lists: one thread per vertex of first-hop length
+// up to kFillThread, a wavefront per vertex up to kSetupHeavy, and (heavy)
 // one workgroup per deferred vertex.
+constexpr int32_t kFillThread = 16;
 template <int MODE>
 void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A,
                      const int32_t* deferred, const int32_t* nd, int32_t* grab, bool heavy, hipStream_t st);
