@@ -49,7 +49,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+def traffic_file(workload):
+    """Committed counter summary of a workload's kernels (d1: pmc_traffic.json)."""
+    name = "pmc_traffic.json" if workload == "d1" else f"pmc_traffic_{workload}.json"
+    return os.path.join(ROOT, "profiles", name)
 COPY_BYTES = 1 << 30    # the calibration copy: 1 GiB read + 1 GiB written
 
 
@@ -105,14 +108,14 @@ def cpu_baseline(sample):
     return tot_e / tot_t, tot_t
 
 
-def load_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    if it was taken on the current library sources."""
+def load_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    the same workload, if it was taken on the current library sources."""
     try:
         from paper_2107_00075_amd.build import source_hash
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(workload)) as f:
             t = json.load(f)
-        if t.get("source_hash") != source_hash():
+        if t.get("source_hash") != source_hash() or t.get("workload") != workload:
             return None
         k = t["kernels"].get(kernel)
         return None if k is None else int(k["hbm_bytes_per_launch"])
@@ -207,7 +210,7 @@ def bench_d1(args, torch, gc, dev):
     dom = max(kern, key=lambda k: kern[k][1])
     b, ns, launches = kern[dom]
     achieved = b / ns if ns else 0.0   # bytes per ns == GB/s
-    traffic = load_traffic(dom)
+    traffic = load_traffic(dom, "d1")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "avg_launch_us": round(ns / max(launches, 1) / 1e3, 3),
@@ -263,6 +266,9 @@ def bench_d2pd2(args, torch, gc, dev):
     brp, bci, bcp, bri = d(b.row_ptr), d(b.col_idx), d(b.col_ptr), d(b.row_idx)
     out_d2 = torch.empty(g.n, dtype=torch.int32, device=dev)
     out_pd2 = torch.empty(b.n_cols, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
     params = gc.Params(flags=gc.COLOR_FLAG_KERNEL_TIMING)
 
     def step():
@@ -337,7 +343,7 @@ def bench_d2pd2(args, torch, gc, dev):
         "config": {"workload": "D2 on 7-pt stencil 96^3 + PD2 (columns) on 4,000,000 x 1,000,000 power-law pattern, "
                                "8 columns per row, gamma 2.1; seed 1", "graphs": graphs},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom),
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, "d2pd2"),
                      "avg_launch_us": round(ns / max(launches, 1) / 1e3, 3),
                      "alg_bytes_per_launch": int(byts / max(launches, 1))},
         "cpu_baseline": cpu,
@@ -609,13 +615,23 @@ def bench_ghost(args, torch, gc, dev):
 # ---------------------------------------------------------------------------
 
 def _counter_rows(d):
-    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-    if not files:
-        raise SystemExit(f"no *counter_collection.csv under {d}")
+    """Per-dispatch counter values from a rocprofv3 output folder: the CSV
+    output (*counter_collection.csv) or the rocpd database (*.db), whose
+    `counters_collection` view holds the same rows."""
     rows = []
-    for fn in files:
+    for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         with open(fn, newline="") as f:
             rows.extend(csv.DictReader(f))
+    if not rows:
+        import sqlite3
+        for fn in glob.glob(os.path.join(d, "**", "*.db"), recursive=True):
+            con = sqlite3.connect(fn)
+            for name, counter, value in con.execute(
+                    "select kernel_name, counter_name, value from counters_collection"):
+                rows.append({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
+            con.close()
+    if not rows:
+        raise SystemExit(f"no counter rows (*counter_collection.csv or rocpd *.db) under {d}")
     return rows
 
 
@@ -624,7 +640,7 @@ def _short(name):
     return base.replace("<1>", "<D1>").replace("<2>", "<D2>").replace("<3>", "<PD2>")
 
 
-def summarize_pmc(fetch_dir, write_dir, out):
+def summarize_pmc(fetch_dir, write_dir, workload, out):
     """KiB per dispatch from FETCH_SIZE / WRITE_SIZE runs -> bytes per launch
     per kernel, scaled so that the calibration copy reads and writes
     COPY_BYTES each."""
@@ -653,7 +669,7 @@ def summarize_pmc(fetch_dir, write_dir, out):
         wb = sum(v["WRITE_SIZE"]) / len(v["WRITE_SIZE"]) * 1024.0 * w_scale
         kernels[k] = {"dispatches": len(v["FETCH_SIZE"]), "fetch_bytes_per_launch": int(fb),
                       "write_bytes_per_launch": int(wb), "hbm_bytes_per_launch": int(fb + wb)}
-    res = {"source_hash": source_hash(),
+    res = {"source_hash": source_hash(), "workload": workload,
            "copy_calibration": {"kernel": ck, "bytes": COPY_BYTES, "fetch_scale": round(f_scale, 4),
                                 "write_scale": round(w_scale, 4)},
            "kernels": kernels}
@@ -678,10 +694,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for counter scaling)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
-    ap.add_argument("--pmc-out", default=TRAFFIC_FILE)
+    ap.add_argument("--pmc-out", default=None, help="default: the workload's profiles/pmc_traffic*.json")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_out)
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload,
+                      args.pmc_out or traffic_file(args.workload))
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "

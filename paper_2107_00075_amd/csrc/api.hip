@@ -505,8 +505,8 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
     const int32_t nb_max = sets ? static_cast<int32_t>(std::max<int64_t>(
                                       1, std::min<int64_t>(nd, kSetsBatchWords / words)))
                                 : 0;
-    launch_inc_fill<MODE>(g, aoff, len, B, w->deferred.as<int32_t>(), &S->deferred_cnt, &S->deferred_grab[1], !sets,
-                          c.st);
+    launch_inc_fill<MODE>(g, aoff, len, B, Lb, w->deferred.as<int32_t>(), &S->deferred_cnt, &S->deferred_grab[1],
+                          !sets, c.st);
     c.launches += sets ? 2 : 3;
     A0 = B;
     const int grid = dedup_grid(words);

@@ -772,12 +772,16 @@ __global__ __launch_bounds__(kBlock) void inc_sizes_kernel(GraphView g, const in
 // Materializes the two-hop list of a vertex with a short first hop (one
 // thread).  At most len(v) entries are written.
 template <int MODE>
+// Every fill stores the number of entries it wrote as the list length
+// (alen), so that a list never exposes an unwritten slot, even where the
+// graph breaks the input contract and the walk is shorter than its bound.
 __global__ __launch_bounds__(kBlock) void inc_fill_kernel(GraphView g, const int32_t* aoff, const int32_t* len,
-                                                          int32_t* A) {
+                                                          int32_t* A, int32_t* alen) {
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
   if (v >= g.n || g.rp[v + 1] - g.rp[v] > kFillThread) return;
-  int32_t o = ld_dev(&aoff[v]);
-  const int32_t end = o + ld_dev(&len[v]);
+  const int32_t base = ld_dev(&aoff[v]);
+  const int32_t end = base + ld_dev(&len[v]);
+  int32_t o = base;
   for (int32_t q = g.rp[v]; q < g.rp[v + 1]; ++q) {
     const int32_t u = g.ci[q];
     if (MODE == kD2 && o < end) st_dev(&A[o++], u);
@@ -786,6 +790,7 @@ __global__ __launch_bounds__(kBlock) void inc_fill_kernel(GraphView g, const int
       if (x != v && o < end) st_dev(&A[o++], x);
     }
   }
+  st_dev(&alen[v], o - base);
 }
 
 // Two-hop lists of vertices with kFillThread < first-hop length <= kSetupHeavy:
@@ -793,7 +798,7 @@ __global__ __launch_bounds__(kBlock) void inc_fill_kernel(GraphView g, const int
 // entry counts across the wavefront and writes them in first-hop order.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void inc_fill_wave_kernel(GraphView g, const int32_t* aoff,
-                                                               const int32_t* len, int32_t* A) {
+                                                               const int32_t* len, int32_t* A, int32_t* alen) {
   const int32_t v = static_cast<int32_t>((blockIdx.x * kBlock + threadIdx.x) / kWave);
   if (v >= g.n) return;
   const int32_t q0 = g.rp[v], q1 = g.rp[v + 1];
@@ -824,6 +829,7 @@ __global__ __launch_bounds__(kBlock) void inc_fill_wave_kernel(GraphView g, cons
     }
     out += __shfl(incl, kWave - 1, kWave);
   }
+  if (lane_id() == 0) st_dev(&alen[v], min(out, end) - ld_dev(&aoff[v]));
 }
 
 // Two-hop lists of the heavy (deferred) vertices: a workgroup per vertex;
@@ -833,7 +839,7 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void inc_fill_heavy_kernel(GraphView g, const int32_t* aoff,
                                                                 const int32_t* len, int32_t* A,
                                                                 const int32_t* deferred, const int32_t* nd_ptr,
-                                                                int32_t* grab) {
+                                                                int32_t* grab, int32_t* alen) {
   __shared__ int32_t s_i;
   __shared__ int32_t s_wt[kWavesPerBlock];
   const int32_t nd = ld_dev(nd_ptr);
@@ -882,6 +888,7 @@ __global__ __launch_bounds__(kBlock) void inc_fill_heavy_kernel(GraphView g, con
       out += tot;
       __syncthreads();
     }
+    if (tid == 0) st_dev(&alen[v], min(out, end) - base);
   }
 }
 
@@ -1039,16 +1046,16 @@ __global__ __launch_bounds__(kBlock) void inc_bitmap_list_kernel(const int32_t* 
 }
 
 template <int MODE>
-void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A,
+void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A, int32_t* alen,
                      const int32_t* deferred, const int32_t* nd, int32_t* grab, bool heavy, hipStream_t st) {
   if (g.n <= 0) return;
-  hipLaunchKernelGGL(inc_fill_kernel<MODE>, dim3(blocks_for(g.n)), dim3(kBlock), 0, st, g, aoff, len, A);
+  hipLaunchKernelGGL(inc_fill_kernel<MODE>, dim3(blocks_for(g.n)), dim3(kBlock), 0, st, g, aoff, len, A, alen);
   const int64_t wave_blocks = (static_cast<int64_t>(g.n) + kWavesPerBlock - 1) / kWavesPerBlock;
   hipLaunchKernelGGL(inc_fill_wave_kernel<MODE>, dim3(static_cast<uint32_t>(wave_blocks)), dim3(kBlock), 0, st, g,
-                     aoff, len, A);
+                     aoff, len, A, alen);
   if (heavy)
     hipLaunchKernelGGL(inc_fill_heavy_kernel<MODE>, dim3(std::min(blocks_for(g.n), 512)), dim3(kBlock), 0, st, g,
-                       aoff, len, A, deferred, nd, grab);
+                       aoff, len, A, deferred, nd, grab, alen);
 }
 
 template <int MODE>
@@ -1086,10 +1093,10 @@ template void launch_inc_bitmap_sets<kD2>(const GraphView&, const int32_t*, int3
                                           const int32_t*, int32_t*, int32_t*, hipStream_t);
 template void launch_inc_bitmap_sets<kPD2>(const GraphView&, const int32_t*, int32_t, int32_t, uint32_t*, int32_t,
                                            const int32_t*, int32_t*, int32_t*, hipStream_t);
-template void launch_inc_fill<kD2>(const GraphView&, const int32_t*, const int32_t*, int32_t*, const int32_t*,
-                                   const int32_t*, int32_t*, bool, hipStream_t);
-template void launch_inc_fill<kPD2>(const GraphView&, const int32_t*, const int32_t*, int32_t*, const int32_t*,
-                                    const int32_t*, int32_t*, bool, hipStream_t);
+template void launch_inc_fill<kD2>(const GraphView&, const int32_t*, const int32_t*, int32_t*, int32_t*,
+                                   const int32_t*, const int32_t*, int32_t*, bool, hipStream_t);
+template void launch_inc_fill<kPD2>(const GraphView&, const int32_t*, const int32_t*, int32_t*, int32_t*,
+                                    const int32_t*, const int32_t*, int32_t*, bool, hipStream_t);
 
 int exclusive_scan_i32(const int32_t* in, int32_t* out, int32_t n_plus_1, void* tmp, size_t* tmp_bytes,
                        hipStream_t st) {

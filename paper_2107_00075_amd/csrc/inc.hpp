@@ -85,7 +85,7 @@ void launch_inc_sizes(const GraphView& g, const int32_t* work, int32_t* len, int
 // one workgroup per deferred vertex.
 constexpr int32_t kFillThread = 16;
 template <int MODE>
-void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A,
+void launch_inc_fill(const GraphView& g, const int32_t* aoff, const int32_t* len, int32_t* A, int32_t* alen,
                      const int32_t* deferred, const int32_t* nd, int32_t* grab, bool heavy, hipStream_t st);
 // The lists of deferred vertices i0 .. i0+nb-1 as duplicate-free sets, through
 // bitmaps of `words` words each (bm: nb x words, zeroed by the caller); alen
