@@ -113,7 +113,10 @@ typedef struct color_params {
                                no run reaches: each round commits at least one vertex) */
     int32_t rounds_per_poll;/* rounds enqueued between host checks of the worklist size */
     int32_t tail_threshold; /* INCREMENTAL: worklist size at or below which one cooperative launch
-                               runs all remaining rounds (grid barriers between the steps) */
+                               runs all remaining rounds (grid barriers between the steps;
+                               default 32768).  A grid barrier that stalls for 30 s ends the
+                               call with COLOR_EHIP; if the runtime refuses the cooperative
+                               launch, the rounds continue as per-round launches. */
     int32_t max_workgroups; /* cap on the grid of the round kernels */
     uint32_t flags;         /* COLOR_FLAG_* */
     int32_t engine;         /* COLOR_ENGINE_*: 0 = library choice */
@@ -124,8 +127,11 @@ typedef struct color_params {
  * forbidden-color bitsets that committing neighbours push into, and per-vertex
  * active-neighbour lists compacted as neighbours commit; it needs extra
  * device memory of about 8 bytes per list entry (D1: per adjacency entry;
- * D2/PD2: per two-hop walk entry) and falls back to PULL when the lists do
- * not fit int32 offsets. */
+ * D2/PD2: per two-hop walk entry) plus worklists of up to 4n entries, falls
+ * back to PULL when the lists do not fit int32 offsets, and returns
+ * COLOR_EOVERFLOW when its worklists would not.  Unless the caller sets
+ * bin_hi, it uses its own bin bounds (D1 16/96/1024, D2 and PD2
+ * 64/256/1024). */
 #define COLOR_ENGINE_AUTO        0
 #define COLOR_ENGINE_PULL        1
 #define COLOR_ENGINE_INCREMENTAL 2
