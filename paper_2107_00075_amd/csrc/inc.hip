@@ -50,10 +50,10 @@ __device__ __forceinline__ int inc_bin_of(const BinLayout& L, int32_t len) {
   return len <= L.hi[0] ? 0 : len <= L.hi[1] ? 1 : len <= L.hi[2] ? 2 : kBlockBin;
 }
 
-__device__ __forceinline__ void make_inc_map(const IncBufs& b, const BinLayout& L, IncMap& m) {
+__device__ __forceinline__ void make_inc_map_from(const int32_t* cnt, const BinLayout& L, IncMap& m) {
   int32_t lt = 0, tot = 0;
   for (int i = 0; i < kBins; ++i) {
-    m.cnt[i] = ld_dev(&b.cnt_in[i]);
+    m.cnt[i] = ld_dev(&cnt[i]);
     tot += m.cnt[i];
   }
   for (int i = 0; i < 3; ++i) {
@@ -64,6 +64,10 @@ __device__ __forceinline__ void make_inc_map(const IncBufs& b, const BinLayout& 
   m.light_total = lt;
   m.heavy_total = m.cnt[kBlockBin] + m.cnt[kSplitBin];
   m.total = tot;
+}
+
+__device__ __forceinline__ void make_inc_map(const IncBufs& b, const BinLayout& L, IncMap& m) {
+  make_inc_map_from(b.cnt_in, L, m);
 }
 
 __device__ __forceinline__ int32_t xcd_block() {
@@ -120,12 +124,20 @@ struct IncColorShared {
   unsigned long long acc[3];
 };
 
+// pre (tail kernel): the round's map and largest committed color, already
+// read by the workgroup at the end of the previous round.
+struct IncPre {
+  IncMap M;
+  int32_t maxc;
+};
+
 __device__ __forceinline__ void inc_color_phase(const IncBufs& b, const BinLayout& L, int round,
-                                                IncColorShared& sh) {
+                                                IncColorShared& sh, const IncPre* pre = nullptr) {
   IncMap& M = sh.M;
   unsigned long long* s_acc = sh.acc;
   if (threadIdx.x == 0) {
-    make_inc_map(b, L, M);
+    if (pre) M = pre->M;
+    else make_inc_map(b, L, M);
     s_acc[0] = s_acc[1] = s_acc[2] = 0ull;
     if (blockIdx.x == 0) {
       for (int i = 0; i < kBins; ++i) atomic_reset_i32(&b.cnt_out[i]);
@@ -138,7 +150,7 @@ __device__ __forceinline__ void inc_color_phase(const IncBufs& b, const BinLayou
     }
   }
   __syncthreads();
-  const int32_t mc = ld_dev(b.maxc);
+  const int32_t mc = pre ? pre->maxc : ld_dev(b.maxc);
   const int32_t wmax = mc / 32 + 1;  // words that can hold a committed color
   uint64_t work = 0, lists = 0, bytes = 0;
   const int32_t stride = gridDim.x * kBlock;
@@ -537,7 +549,7 @@ struct IncDetectShared {
 };
 
 __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBufs& b, const BinLayout& L,
-                                                 int round, IncDetectShared& sh) {
+                                                 int round, IncDetectShared& sh, const IncPre* pre = nullptr) {
   int32_t& s_unit = sh.unit;
   int32_t& s_max = sh.max;
   int32_t* s_ent = sh.ent;
@@ -546,7 +558,8 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
   unsigned long long* s_acc = sh.acc;
   IncMap& M = sh.M;
   if (threadIdx.x == 0) {
-    make_inc_map(b, L, M);
+    if (pre) M = pre->M;
+    else make_inc_map(b, L, M);
     s_max = 0;
     s_acc[0] = s_acc[1] = 0ull;
   }
@@ -680,21 +693,21 @@ __global__ __launch_bounds__(kBlock) void inc_tail_kernel(KeySource k, IncRoundS
     IncColorShared c;
     IncDetectShared d;
   } sh;
-  __shared__ int32_t s_ok, s_total;
+  __shared__ int32_t s_ok;
+  __shared__ IncPre s_pre;  // next round's map and largest color, read once per round
   for (int r = round0; r <= round_cap; ++r) {
     const IncBufs& b = r == 1 ? set.b[0] : set.b[1 + ((r - 1) & 1)];
-    inc_color_phase(b, L, r, sh.c);
+    const bool first = r == round0;
+    inc_color_phase(b, L, r, sh.c, first ? nullptr : &s_pre);
     if (!grid_sync(bar, err, deadline, &s_ok)) return;
-    inc_detect_phase(k, b, L, r, sh.d);
+    inc_detect_phase(k, b, L, r, sh.d, first ? nullptr : &s_pre);
     if (!grid_sync(bar, err, deadline, &s_ok)) return;
     if (threadIdx.x == 0) {
-      int32_t t = 0;
-      for (int i = 0; i < kBins; ++i) t += ld_dev(&b.cnt_out[i]);
-      s_total = t;
+      make_inc_map_from(b.cnt_out, L, s_pre.M);  // the next round's worklist counts
+      s_pre.maxc = ld_dev(b.maxc);
     }
     __syncthreads();
-    const bool done = s_total == 0;
-    __syncthreads();
+    const bool done = s_pre.M.total == 0;
     if (done) return;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) st_dev(left, 1);
