@@ -1,0 +1,82 @@
+"""Host logic of bench.py (no GPU): the bench contract's guard for several
+GPUs, the counter summary read from a rocprofv3 database, and the rule that
+a traffic figure is reported only for the workload and kernel sources it
+was measured on."""
+import importlib.util
+import json
+import os
+import sqlite3
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _fake_db(path, rows):
+    """A database with the `counters_collection` columns summarize_pmc reads."""
+    con = sqlite3.connect(path)
+    con.execute("create table counters_collection (kernel_name text, counter_name text, value real)")
+    con.executemany("insert into counters_collection values (?, ?, ?)", rows)
+    con.commit()
+    con.close()
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT)
+    assert r.returncode != 0
+    assert "GPU" in (r.stdout + r.stderr)
+
+
+def test_counter_summary_from_database(bench, tmp_path):
+    gib_kib = 1024.0 * 1024.0  # 1 GiB in KiB
+    fetch = tmp_path / "fetch"
+    write = tmp_path / "write"
+    fetch.mkdir()
+    write.mkdir()
+    # the calibration copy reads 1 GiB and writes 1 GiB; FETCH_SIZE reads half
+    _fake_db(str(fetch / "run_results.db"), [
+        ("__amd_rocclr_copyBuffer", "FETCH_SIZE", gib_kib / 2),
+        ("gcol::inc_detect_kernel(gcol::KeySource, gcol::IncBufs)", "FETCH_SIZE", 1000.0),
+        ("gcol::inc_detect_kernel(gcol::KeySource, gcol::IncBufs)", "FETCH_SIZE", 3000.0),
+    ])
+    _fake_db(str(write / "run_results.db"), [
+        ("__amd_rocclr_copyBuffer", "WRITE_SIZE", gib_kib),
+        ("gcol::inc_detect_kernel(gcol::KeySource, gcol::IncBufs)", "WRITE_SIZE", 10.0),
+        ("gcol::inc_detect_kernel(gcol::KeySource, gcol::IncBufs)", "WRITE_SIZE", 30.0),
+    ])
+    out = tmp_path / "traffic.json"
+    bench.summarize_pmc(str(fetch), str(write), "d1", str(out))
+    t = json.loads(out.read_text())
+    assert t["workload"] == "d1"
+    assert abs(t["copy_calibration"]["fetch_scale"] - 2.0) < 1e-9
+    assert abs(t["copy_calibration"]["write_scale"] - 1.0) < 1e-9
+    k = t["kernels"]["inc_detect_kernel"]
+    assert k["dispatches"] == 2
+    assert k["fetch_bytes_per_launch"] == int(2000.0 * 1024 * 2.0)   # mean 2000 KiB, scaled x2
+    assert k["write_bytes_per_launch"] == int(20.0 * 1024)
+    assert k["hbm_bytes_per_launch"] == k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
+def test_traffic_only_for_its_workload_and_sources(bench, tmp_path, monkeypatch):
+    from paper_2107_00075_amd.build import source_hash
+    good = {"source_hash": source_hash(), "workload": "d1",
+            "kernels": {"inc_detect_kernel": {"hbm_bytes_per_launch": 1234}}}
+    path = tmp_path / "pmc_traffic.json"
+    path.write_text(json.dumps(good))
+    monkeypatch.setattr(bench, "traffic_file", lambda w: str(path))
+    assert bench.load_traffic("inc_detect_kernel", "d1") == 1234
+    assert bench.load_traffic("inc_detect_kernel", "d2pd2") is None      # another workload's figure
+    assert bench.load_traffic("inc_color_kernel", "d1") is None          # not measured
+    path.write_text(json.dumps(dict(good, source_hash="0" * 16)))
+    assert bench.load_traffic("inc_detect_kernel", "d1") is None          # kernels changed since
