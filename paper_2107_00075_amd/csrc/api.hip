@@ -73,7 +73,8 @@ void Workspace::release() {
   events.clear();
   for (DevBuf* b : {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
                     &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
-                    &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &inc_wl0, &inc_wl1, &scan_tmp})
+                    &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &inc_wl0, &inc_wl1, &scan_tmp,
+                    &deferred_work, &deferred_done})
     b->release();
   if (host) (void)hipHostFree(host);
   host = nullptr;
@@ -263,6 +264,13 @@ int setup_bins(Call& c, const GraphView& g, const int32_t* init, int32_t* C, int
   int e0;
   if ((e0 = w->deferred.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n, 1)), false, c.st))) return e0;
   s.deferred = w->deferred.as<int32_t>();
+  if ((e0 = w->deferred_work.ensure(sizeof(unsigned long long) * static_cast<size_t>(std::max(n, 1)), false,
+                                    c.st)))
+    return e0;
+  if ((e0 = w->deferred_done.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n, 1)), false, c.st)))
+    return e0;
+  s.deferred_work = w->deferred_work.as<unsigned long long>();
+  s.deferred_done = w->deferred_done.as<int32_t>();
   s.deferred_cnt = &S->deferred_cnt;
   s.deferred_grab = &S->deferred_grab[0];
   s.total_work = &S->total_work;

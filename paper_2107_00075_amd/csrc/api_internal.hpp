@@ -55,6 +55,7 @@ struct Workspace {
   DevBuf T, C, work, bin, wl0, wl1, small, trace, split_vertex, split_ctr, split_flag, split_mask, aux0, aux1;
   DevBuf deferred, inc_len, inc_words, inc_fwoff, inc_aoff, inc_F, inc_L0, inc_Ll, inc_B0, inc_B1, inc_bm, scan_tmp;
   DevBuf inc_wl0, inc_wl1;  // incremental engine: worklists binned by active-list length
+  DevBuf deferred_work, deferred_done;  // setup: per heavy D2/PD2 vertex, its work and slices done
   Scalars* host = nullptr;  // pinned staging for read-backs
   std::vector<hipEvent_t> events;  // pool for COLOR_FLAG_KERNEL_TIMING
   ~Workspace();

@@ -1018,10 +1018,12 @@ __global__ __launch_bounds__(kBlock) void inc_mark_kernel(GraphView g, const int
   for (int32_t q = g.rp[v] + static_cast<int32_t>(blockIdx.x * kBlock + threadIdx.x); q < q1;
        q += static_cast<int32_t>(gridDim.x * kBlock)) {
     const int32_t u = g.ci[q];
-    if (MODE == kD2 && u != v) atomicOr(&m[u >> 5], 1u << (u & 31));
+    // a plain (cacheable) read first skips most atomics of bits already set;
+    // a stale read only costs an atomic that was not needed
+    if (MODE == kD2 && u != v && !(m[u >> 5] & (1u << (u & 31)))) atomicOr(&m[u >> 5], 1u << (u & 31));
     for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
       const int32_t x = g.ci2[p];
-      if (x != v) atomicOr(&m[x >> 5], 1u << (x & 31));
+      if (x != v && !(m[x >> 5] & (1u << (x & 31)))) atomicOr(&m[x >> 5], 1u << (x & 31));
     }
   }
 }

@@ -168,7 +168,12 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
       int32_t b0 = 0;
       if (lane_id() == first) b0 = atomicAdd(s.deferred_cnt, static_cast<int32_t>(__popcll(dbal)));
       b0 = __shfl(b0, first, kWave);
-      if (defer) st_dev(&s.deferred[b0 + static_cast<int32_t>(lanes_below(dbal))], v);
+      if (defer) {
+        const int32_t di = b0 + static_cast<int32_t>(lanes_below(dbal));
+        st_dev(&s.deferred[di], v);
+        st_dev(&s.deferred_work[di], 0ull);
+        st_dev(&s.deferred_done[di], 0);
+      }
     }
     active = active && !defer;
     if (active) record_vertex(s, v, vertex_work<MODE>(g, v), acc);
@@ -176,31 +181,50 @@ __global__ __launch_bounds__(kBlock) void bin_kernel(GraphView g, BinSetup s) {
   flush_acc(s, acc);
 }
 
-// Deferred heavy vertices: the workgroup sums the first hop's contributions.
+// Deferred heavy vertices: each is cut into kHeavySlices equal ranges of its
+// first hop, handed out as units; a unit's workgroup adds its range's
+// contributions to the vertex's sum, and the workgroup that completes the
+// last range records the vertex.  (One workgroup per vertex left the
+// longest first hop on one workgroup: 2.6 ms on the 4M x 1M PD2 pattern.)
+constexpr int kHeavySlices = 16;
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void heavy_work_kernel(GraphView g, BinSetup s) {
-  __shared__ int32_t s_i;
+  __shared__ int32_t s_u, s_last;
   __shared__ unsigned long long s_sum;
   const int32_t nd = ld_dev(s.deferred_cnt);
+  const int64_t units = static_cast<int64_t>(nd) * kHeavySlices;
   while (true) {
     if (threadIdx.x == 0) {
-      s_i = atomicAdd(s.deferred_grab, 1);
+      s_u = atomicAdd(s.deferred_grab, 1);
       s_sum = 0ull;
     }
     __syncthreads();
-    const int32_t i = s_i;
-    if (i >= nd) break;
+    const int32_t u = s_u;
+    if (u >= units) break;
+    const int32_t i = u / kHeavySlices, j = u % kHeavySlices;
     const int32_t v = ld_dev(&s.deferred[i]);
+    const int32_t q0 = g.rp[v], len = g.rp[v + 1] - q0;
+    const int32_t a = q0 + static_cast<int32_t>(static_cast<int64_t>(len) * j / kHeavySlices);
+    const int32_t z = q0 + static_cast<int32_t>(static_cast<int64_t>(len) * (j + 1) / kHeavySlices);
     uint64_t w = 0;
-    for (int32_t q = g.rp[v] + threadIdx.x; q < g.rp[v + 1]; q += kBlock) {
-      const int32_t u = g.ci[q];
-      w += 1 + static_cast<uint64_t>(g.rp2[u + 1] - g.rp2[u]);
+    for (int32_t q = a + static_cast<int32_t>(threadIdx.x); q < z; q += kBlock) {
+      const int32_t x = g.ci[q];
+      w += 1 + static_cast<uint64_t>(g.rp2[x + 1] - g.rp2[x]);
     }
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) w += __shfl_xor(w, off, kWave);
     if (lane_id() == 0 && w) atomicAdd(&s_sum, static_cast<unsigned long long>(w));
     __syncthreads();
-    if (threadIdx.x < kWave) account_vertex(s, v, static_cast<int64_t>(s_sum), threadIdx.x == 0);
+    if (threadIdx.x == 0) {
+      if (s_sum) atomicAdd(&s.deferred_work[i], s_sum);
+      __threadfence();
+      s_last = atomicAdd(&s.deferred_done[i], 1) == kHeavySlices - 1 ? 1 : 0;
+      __threadfence();
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x < kWave)
+      account_vertex(s, v, static_cast<int64_t>(ld_dev(&s.deferred_work[i])), threadIdx.x == 0);
     __syncthreads();
   }
 }

@@ -25,6 +25,8 @@ struct BinSetup {
   int32_t* deferred;                 // out: heavy D2/PD2 vertices (workgroup setup)
   int32_t* deferred_cnt;             // out: their number
   int32_t* deferred_grab;            // work counter of heavy_work_kernel
+  unsigned long long* deferred_work; // per deferred vertex: its work, summed over slices
+  int32_t* deferred_done;            // per deferred vertex: slices done
 };
 
 template <int MODE>
