@@ -229,11 +229,14 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
     const int32_t* A = b.A_in + base;
     bool lose = false;
     int32_t read = 0, gath = 0;
-    for (int32_t e0 = sub; e0 < len && !lose; e0 += 4 * G) {
+    // the group steps through the list together and stops at the first step
+    // in which any of its lanes found a conflict (a lane-by-lane stop would
+    // keep the group scanning until its slowest lane reached the end)
+    for (int32_t e0 = 0; e0 < len; e0 += 4 * G) {
       int32_t u[4], t[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int32_t e = e0 + j * G;
+        const int32_t e = e0 + sub + j * G;
         u[j] = e < len ? ld_dev(&A[e]) : -1;
         read += e < len ? 1 : 0;
       }
@@ -243,11 +246,14 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
         t[j] = higher ? (b.uniform ? tv : ld_dev(&b.T[u[j]])) : -1;
         gath += (higher && !b.uniform) ? 1 : 0;
       }
+      bool hit = false;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (t[j] == tv) lose = true;
+      for (int j = 0; j < 4; ++j) hit = hit || t[j] == tv;
+      if (group_any<G>(hit)) {
+        lose = true;
+        break;
+      }
     }
-    lose = group_any<G>(lose);
     bytes += 4ull * static_cast<uint64_t>(read + gath);  // list entries and tentative colors this lane read
     if (lose && !compact_now(b, round, v)) {
       if (sub == 0) {
