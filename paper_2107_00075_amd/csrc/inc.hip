@@ -229,26 +229,28 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
     const int32_t* A = b.A_in + base;
     bool lose = false;
     int32_t read = 0, gath = 0;
-    // the group steps through the list together and stops at the first step
-    // in which any of its lanes found a conflict (a lane-by-lane stop would
-    // keep the group scanning until its slowest lane reached the end)
-    for (int32_t e0 = 0; e0 < len; e0 += 4 * G) {
-      int32_t u[4], t[4];
+    // the group steps through the list together, two entries per lane per
+    // step, and stops at the first step in which any of its lanes found a
+    // conflict (a lane-by-lane stop would keep the group scanning until its
+    // slowest lane reached the end; measured on MI355X, two entries per step
+    // beat four: R-MAT 22 D1 39.3 -> 38.4 ms)
+    for (int32_t e0 = 0; e0 < len; e0 += 2 * G) {
+      int32_t u[2], t[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 2; ++j) {
         const int32_t e = e0 + sub + j * G;
         u[j] = e < len ? ld_dev(&A[e]) : -1;
         read += e < len ? 1 : 0;
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 2; ++j) {
         const bool higher = u[j] >= 0 && (!first_pass || key_of(k, u[j]) > kv);
         t[j] = higher ? (b.uniform ? tv : ld_dev(&b.T[u[j]])) : -1;
         gath += (higher && !b.uniform) ? 1 : 0;
       }
       bool hit = false;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) hit = hit || t[j] == tv;
+      for (int j = 0; j < 2; ++j) hit = hit || t[j] == tv;
       if (group_any<G>(hit)) {
         lose = true;
         break;
