@@ -114,9 +114,13 @@ typedef struct color_params {
     int32_t rounds_per_poll;/* rounds enqueued between host checks of the worklist size */
     int32_t tail_threshold; /* INCREMENTAL: worklist size at or below which one cooperative launch
                                runs all remaining rounds (grid barriers between the steps;
-                               default 32768).  A grid barrier that stalls for 30 s ends the
-                               call with COLOR_EHIP; if the runtime refuses the cooperative
-                               launch, the rounds continue as per-round launches. */
+                               default 32768).  Its workgroups wait on each other, so they
+                               must all be resident: a caller whose other streams keep
+                               device-filling kernels running at the same time sets
+                               COLOR_FLAG_NO_TAIL (the server's heavy lane does).  A grid
+                               barrier that stalls for 30 s ends the call with COLOR_EHIP;
+                               if the runtime refuses the cooperative launch, the rounds
+                               continue as per-round launches. */
     int32_t max_workgroups; /* cap on the grid of the round kernels */
     uint32_t flags;         /* COLOR_FLAG_* */
     int32_t engine;         /* COLOR_ENGINE_*: 0 = library choice */

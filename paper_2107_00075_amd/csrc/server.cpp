@@ -387,9 +387,16 @@ int run_heavy(color_server* s, ServedJob& J) {
     if (!cp || (J.nnz > 0 && !ri)) return COLOR_EHIP;
   }
   int32_t* colors = reinterpret_cast<int32_t*>(p);
+  // Per-round launches only: the light lane's persistent kernel fills the
+  // device at the same time, so the workgroups of a cooperative tail launch
+  // need not all be resident, and its grid barriers could wait on workgroups
+  // that only start when an epoch ends (up to the barrier's deadline).
+  color_params prm;
+  std::memset(&prm, 0, sizeof(prm));
+  prm.flags = COLOR_FLAG_NO_TAIL;
   int rc = d.kind == COLOR_KIND_D2
-               ? color_d2(d.n, rp, ci, d.seed, nullptr, nullptr, colors, &J.stats, nullptr, s->heavy_stream)
-               : color_pd2(J.n_csr_rows, d.n, rp, ci, cp, ri, d.seed, nullptr, nullptr, colors, &J.stats, nullptr,
+               ? color_d2(d.n, rp, ci, d.seed, nullptr, nullptr, colors, &J.stats, &prm, s->heavy_stream)
+               : color_pd2(J.n_csr_rows, d.n, rp, ci, cp, ri, d.seed, nullptr, nullptr, colors, &J.stats, &prm,
                            s->heavy_stream);
   if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
   J.rc = rc;
