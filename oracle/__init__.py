@@ -16,6 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 TRACE_ROUNDS = 4096
+RECOLOR_DEGREES = 1   # key(v) = (deg(v), p(v), gid(v)): recolorDegrees (Section 3.3, Algorithm 4)
 
 
 def build(force: bool = False) -> str:
@@ -64,16 +65,17 @@ def lib():
         l.orc_priority.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         l.orc_priorities.restype = None
         l.orc_priorities.argtypes = [ctypes.c_int32, ctypes.c_uint32, P]
-        sig = [ctypes.c_int32, P, P, ctypes.c_uint32, P, P, ctypes.c_int32, P, P]
+        sig = [ctypes.c_int32, P, P, ctypes.c_uint32, P, P, ctypes.c_int32, P, P, ctypes.c_int]
         for name in ("orc_color_d1", "orc_color_d2"):
             getattr(l, name).restype = ctypes.c_int
             getattr(l, name).argtypes = sig
         l.orc_color_pd2.restype = ctypes.c_int
         l.orc_color_pd2.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, ctypes.c_uint32,
-                                    P, P, ctypes.c_int32, P, P]
+                                    P, P, ctypes.c_int32, P, P, ctypes.c_int]
         l.orc_color_d1_ghost.restype = ctypes.c_int
         l.orc_color_d1_ghost.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                         ctypes.c_int32, P, P, P, P, ctypes.c_uint32, P, P, P]
+                                         ctypes.c_int32, P, P, P, P, ctypes.c_uint32, P, P, P, P, P,
+                                         ctypes.c_int]
         l.orc_serial_greedy.restype = None
         l.orc_serial_greedy.argtypes = [ctypes.c_int32, P, P, P, P]
         _lib = l
@@ -110,50 +112,66 @@ def priorities(n: int, seed: int) -> np.ndarray:
     return out
 
 
+def _flags(recolor_degrees):
+    return RECOLOR_DEGREES if recolor_degrees else 0
+
+
 def _prio_init(prio, init):
     p = None if prio is None else np.ascontiguousarray(prio, dtype=np.uint32)
     i = None if init is None else _i32(init)
     return p, i
 
 
-def color_d1(g, seed: int = 1, prio=None, init=None, max_rounds: int = 0) -> Result:
+def color_d1(g, seed: int = 1, prio=None, init=None, max_rounds: int = 0,
+             recolor_degrees: bool = False) -> Result:
     rp, col = _i32(g.row_ptr), _i32(g.col)
     p, i = _prio_init(prio, init)
     out = np.zeros(g.n, dtype=np.int32)
     st = _Stats()
     ret = lib().orc_color_d1(g.n, _ptr(rp), _ptr(col), seed & 0xFFFFFFFF, _ptr(p), _ptr(i),
-                             max_rounds, _ptr(out), ctypes.byref(st))
+                             max_rounds, _ptr(out), ctypes.byref(st), _flags(recolor_degrees))
     return _result(out, st, ret)
 
 
-def color_d2(g, seed: int = 1, prio=None, init=None, max_rounds: int = 0) -> Result:
+def color_d2(g, seed: int = 1, prio=None, init=None, max_rounds: int = 0,
+             recolor_degrees: bool = False) -> Result:
     rp, col = _i32(g.row_ptr), _i32(g.col)
     p, i = _prio_init(prio, init)
     out = np.zeros(g.n, dtype=np.int32)
     st = _Stats()
     ret = lib().orc_color_d2(g.n, _ptr(rp), _ptr(col), seed & 0xFFFFFFFF, _ptr(p), _ptr(i),
-                             max_rounds, _ptr(out), ctypes.byref(st))
+                             max_rounds, _ptr(out), ctypes.byref(st), _flags(recolor_degrees))
     return _result(out, st, ret)
 
 
-def color_pd2(b, seed: int = 1, prio=None, init=None, max_rounds: int = 0) -> Result:
+def color_pd2(b, seed: int = 1, prio=None, init=None, max_rounds: int = 0,
+              recolor_degrees: bool = False) -> Result:
     arrs = [_i32(x) for x in (b.row_ptr, b.col_idx, b.col_ptr, b.row_idx)]
     p, i = _prio_init(prio, init)
     out = np.zeros(b.n_cols, dtype=np.int32)
     st = _Stats()
     ret = lib().orc_color_pd2(b.n_rows, b.n_cols, *[_ptr(a) for a in arrs], seed & 0xFFFFFFFF,
-                              _ptr(p), _ptr(i), max_rounds, _ptr(out), ctypes.byref(st))
+                              _ptr(p), _ptr(i), max_rounds, _ptr(out), ctypes.byref(st),
+                              _flags(recolor_degrees))
     return _result(out, st, ret)
 
 
-def color_d1_ghost(lg, seed: int = 1) -> Result:
+def color_d1_ghost(lg, seed: int = 1, init_owned=None, recolor_degrees: bool = False,
+                   ghost_degree=None) -> Result:
+    """One rank's step.  init_owned: committed owned colors to start from (a
+    later iteration of Algorithm 2); ghost_degree: the ghosts' degrees, needed
+    with recolor_degrees."""
     rp, col, gid, gc = (_i32(x) for x in (lg.row_ptr, lg.col, lg.gid, lg.ghost_colors))
+    init = None if init_owned is None else _i32(init_owned)
+    gdeg = None if ghost_degree is None else _i32(ghost_degree)
+    if recolor_degrees and lg.n_ghost > 0 and gdeg is None:
+        raise ValueError("recolor_degrees needs the ghosts' degrees")
     out = np.zeros(lg.n_owned, dtype=np.int32)
     remote = np.zeros(max(lg.n_ghost, 1), dtype=np.uint8)
     st = _Stats()
     ret = lib().orc_color_d1_ghost(lg.n_owned, lg.n_ghost, lg.layers, lg.n_g1, _ptr(rp), _ptr(col),
-                                   _ptr(gid), _ptr(gc), seed & 0xFFFFFFFF, _ptr(out), _ptr(remote),
-                                   ctypes.byref(st))
+                                   _ptr(gid), _ptr(gc), seed & 0xFFFFFFFF, _ptr(init), _ptr(gdeg),
+                                   _ptr(out), _ptr(remote), ctypes.byref(st), _flags(recolor_degrees))
     return _result(out, st, ret, remote[:lg.n_ghost].copy())
 
 

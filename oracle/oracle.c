@@ -41,7 +41,14 @@
  *       need ghost information); phase 2 compares every owned-ghost edge
  *       against the ghosts' fixed colors with the key rule (Algorithm 3/4);
  *       phase 3 recolors the owned losers with the ghost colors as
- *       constraints; ghost colors are never written (save/restore of gc).
+ *       constraints; ghost colors are never written (save/restore of gc);
+ *   R7  recolorDegrees (Section 3.3; Algorithm 4 with recolorDegrees true):
+ *       when asked for, key(v) = (deg(v), p(v), gid(v)), so that of two
+ *       conflicting vertices the one of lower degree is uncolored and the
+ *       random key only decides between equal degrees.  deg(v) is the number
+ *       of stored neighbours of v in the graph being colored (D1, D2: its
+ *       adjacency row; PD2: the rows of column v; a ghost: the degree its
+ *       owner reports), computed once before the rounds.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -76,11 +83,20 @@ void orc_priorities(int32_t n, uint32_t seed, uint32_t *out)
     for (int32_t i = 0; i < n; i++) out[i] = orc_priority((uint32_t)i, seed);
 }
 
-/* 1 if key(a) > key(b); key = (p, gid) lexicographic (reading R2). */
-static int key_greater(uint32_t pa, uint32_t ga, uint32_t pb, uint32_t gb)
+/* Keys of the vertices the rules may compare: p(v), gid(v) and, with
+ * recolorDegrees (reading R7), deg(v). */
+typedef struct {
+    const uint32_t *p;
+    const uint32_t *gid;
+    const int64_t *deg;       /* nullable: keys without degrees (reading R2) */
+} keys_t;
+
+/* 1 if key(a) > key(b): (deg, p, gid) or (p, gid), lexicographic. */
+static int key_greater(const keys_t *k, int32_t a, int32_t b)
 {
-    if (pa != pb) return pa > pb;
-    return ga > gb;
+    if (k->deg && k->deg[a] != k->deg[b]) return k->deg[a] > k->deg[b];
+    if (k->p[a] != k->p[b]) return k->p[a] > k->p[b];
+    return k->gid[a] > k->gid[b];
 }
 
 /* ---------------------------------------------------------------------- */
@@ -182,8 +198,7 @@ typedef struct {
     int32_t n_base;           /* ids >= n_base are fixed-color ghosts */
     const int32_t *ghost_col; /* colors of ids >= n_base */
     int32_t ignore_from;      /* neighbours with id >= ignore_from are ignored */
-    const uint32_t *pkey;     /* p(v) for every id the rules may read */
-    const uint32_t *gkey;     /* gid(v) */
+    keys_t keys;              /* keys of every id the rules may read */
     int32_t max_rounds;
 } rounds_t;
 
@@ -226,7 +241,7 @@ static int32_t run_rounds(const rounds_t *rc, int32_t *colors, orc_stats *st,
                 int32_t u = nb.ids[k];
                 if (u >= rc->ignore_from || u >= n) continue;  /* ghosts are never in the worklist */
                 if (!in_w[u]) continue;
-                if (T[u] == T[v] && key_greater(rc->pkey[u], rc->gkey[u], rc->pkey[v], rc->gkey[v])) {
+                if (T[u] == T[v] && key_greater(&rc->keys, u, v)) {
                     lost[v] = 1;
                     break;
                 }
@@ -256,14 +271,38 @@ static int32_t run_rounds(const rounds_t *rc, int32_t *colors, orc_stats *st,
     return r;
 }
 
-static void fill_keys(int32_t m, const int32_t *gid, uint32_t seed, const uint32_t *prio,
-                      uint32_t *pkey, uint32_t *gkey)
+/* Fills the keys of ids [0, m): gid (identity when gid is NULL), p from the
+ * hash or from prio, and with recolorDegrees (reading R7) the degrees: for
+ * ids below n_rows the length of their row in (deg_ptr), for the others
+ * extra_deg[id - n_rows].  Returns the arrays to free through *owned. */
+static keys_t make_keys(int32_t m, const int32_t *gid, uint32_t seed, const uint32_t *prio,
+                        int degrees, const int32_t *deg_ptr, int32_t n_rows, const int32_t *extra_deg)
 {
+    keys_t k;
+    size_t cnt = (size_t)(m > 0 ? m : 1);
+    uint32_t *p = (uint32_t *)malloc(cnt * sizeof(uint32_t));
+    uint32_t *g = (uint32_t *)malloc(cnt * sizeof(uint32_t));
+    int64_t *d = NULL;
     for (int32_t v = 0; v < m; v++) {
-        uint32_t g = gid ? (uint32_t)gid[v] : (uint32_t)v;
-        gkey[v] = g;
-        pkey[v] = prio ? prio[v] : orc_priority(g, seed);
+        g[v] = gid ? (uint32_t)gid[v] : (uint32_t)v;
+        p[v] = prio ? prio[v] : orc_priority(g[v], seed);
     }
+    if (degrees) {
+        d = (int64_t *)malloc(cnt * sizeof(int64_t));
+        for (int32_t v = 0; v < m; v++)
+            d[v] = v < n_rows ? (int64_t)deg_ptr[v + 1] - deg_ptr[v] : (int64_t)extra_deg[v - n_rows];
+    }
+    k.p = p;
+    k.gid = g;
+    k.deg = d;
+    return k;
+}
+
+static void free_keys(keys_t *k)
+{
+    free((void *)k->p);
+    free((void *)k->gid);
+    free((void *)k->deg);
 }
 
 static void finish_stats(orc_stats *st, const int32_t *colors, int32_t n, int32_t rounds)
@@ -277,28 +316,27 @@ static void finish_stats(orc_stats *st, const int32_t *colors, int32_t n, int32_
 }
 
 static int color_common(const graph_t *g, uint32_t seed, const uint32_t *prio,
-                        const int32_t *init, int32_t max_rounds, int32_t *colors, orc_stats *st)
+                        const int32_t *init, int32_t max_rounds, int32_t *colors, orc_stats *st,
+                        int flags)
 {
     int32_t n = g->n;
-    uint32_t *pkey = (uint32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
-    uint32_t *gkey = (uint32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    /* the degree of a vertex being colored: its adjacency row (D1, D2) or
+     * its column's rows (PD2) */
+    const int32_t *deg_ptr = g->kind == 3 ? g->col_ptr : g->row_ptr;
     rounds_t rc;
     int32_t rounds;
     if (st) memset(st, 0, sizeof(*st));
-    fill_keys(n, NULL, seed, prio, pkey, gkey);
+    rc.keys = make_keys(n, NULL, seed, prio, flags & ORC_RECOLOR_DEGREES, deg_ptr, n, NULL);
     for (int32_t v = 0; v < n; v++) colors[v] = init ? init[v] : 0;
     rc.g = g;
     rc.n = n;
     rc.n_base = n;
     rc.ghost_col = NULL;
     rc.ignore_from = n;
-    rc.pkey = pkey;
-    rc.gkey = gkey;
     rc.max_rounds = max_rounds > 0 ? max_rounds : INT32_MAX;
     rounds = run_rounds(&rc, colors, st, 0);
     finish_stats(st, colors, n, rounds);
-    free(pkey);
-    free(gkey);
+    free_keys(&rc.keys);
     for (int32_t v = 0; v < n; v++)
         if (colors[v] == 0) return 1;   /* round cap reached: partial state */
     return 0;
@@ -306,39 +344,41 @@ static int color_common(const graph_t *g, uint32_t seed, const uint32_t *prio,
 
 int orc_color_d1(int32_t n, const int32_t *row_ptr, const int32_t *col, uint32_t seed,
                  const uint32_t *prio, const int32_t *init, int32_t max_rounds,
-                 int32_t *colors, orc_stats *st)
+                 int32_t *colors, orc_stats *st, int flags)
 {
     graph_t g = {1, n, row_ptr, col, NULL, NULL};
-    return color_common(&g, seed, prio, init, max_rounds, colors, st);
+    return color_common(&g, seed, prio, init, max_rounds, colors, st, flags);
 }
 
 int orc_color_d2(int32_t n, const int32_t *row_ptr, const int32_t *col, uint32_t seed,
                  const uint32_t *prio, const int32_t *init, int32_t max_rounds,
-                 int32_t *colors, orc_stats *st)
+                 int32_t *colors, orc_stats *st, int flags)
 {
     graph_t g = {2, n, row_ptr, col, NULL, NULL};
-    return color_common(&g, seed, prio, init, max_rounds, colors, st);
+    return color_common(&g, seed, prio, init, max_rounds, colors, st, flags);
 }
 
 int orc_color_pd2(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
                   const int32_t *col_ptr, const int32_t *row_idx, uint32_t seed,
                   const uint32_t *prio, const int32_t *init, int32_t max_rounds,
-                  int32_t *col_colors, orc_stats *st)
+                  int32_t *col_colors, orc_stats *st, int flags)
 {
     (void)n_rows;
     graph_t g = {3, n_cols, row_ptr, col_idx, col_ptr, row_idx};
-    return color_common(&g, seed, prio, init, max_rounds, col_colors, st);
+    return color_common(&g, seed, prio, init, max_rounds, col_colors, st, flags);
 }
 
-/* One rank's step of Algorithm 2 for distance-1 (reading R6). */
+/* One rank's step of Algorithm 2 for distance-1 (reading R6).  init_owned
+ * (nullable) holds committed owned colors to start from (a later iteration
+ * of Algorithm 2's loop: phase 1 then only colors the owned vertices init
+ * leaves at 0). */
 int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1,
                        const int32_t *row_ptr, const int32_t *col, const int32_t *gid,
-                       const int32_t *ghost_colors, uint32_t seed,
-                       int32_t *owned_colors, unsigned char *remote_loser, orc_stats *st)
+                       const int32_t *ghost_colors, uint32_t seed, const int32_t *init_owned,
+                       const int32_t *ghost_degree, int32_t *owned_colors,
+                       unsigned char *remote_loser, orc_stats *st, int flags)
 {
     int32_t m = n_owned + n_ghost;
-    uint32_t *pkey = (uint32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(uint32_t));
-    uint32_t *gkey = (uint32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(uint32_t));
     unsigned char *loser = (unsigned char *)calloc((size_t)(n_owned > 0 ? n_owned : 1), 1);
     graph_t g = {1, n_owned, row_ptr, col, NULL, NULL};
     rounds_t rc;
@@ -346,8 +386,10 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
     (void)layers;
     (void)n_g1;   /* second-layer rows are carried but never read (ghosts are fixed) */
     if (st) memset(st, 0, sizeof(*st));
-    fill_keys(m, gid, seed, NULL, pkey, gkey);
-    for (int32_t v = 0; v < n_owned; v++) owned_colors[v] = 0;
+    /* an owned vertex's row holds all its edges; a ghost's degree comes from
+     * its owner */
+    rc.keys = make_keys(m, gid, seed, NULL, flags & ORC_RECOLOR_DEGREES, row_ptr, n_owned, ghost_degree);
+    for (int32_t v = 0; v < n_owned; v++) owned_colors[v] = init_owned ? init_owned[v] : 0;
     if (remote_loser)
         for (int32_t j = 0; j < n_ghost; j++) remote_loser[j] = 0;
 
@@ -357,8 +399,6 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
     rc.n_base = n_owned;
     rc.ghost_col = ghost_colors;
     rc.ignore_from = n_owned;
-    rc.pkey = pkey;
-    rc.gkey = gkey;
     rc.max_rounds = INT32_MAX;
     r1 = run_rounds(&rc, owned_colors, st, 0);
 
@@ -370,7 +410,7 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
             if (u < n_owned) continue;
             if (owned_colors[v] != ghost_colors[u - n_owned]) continue;
             if (st) st->boundary_conflicts++;
-            if (key_greater(pkey[u], gkey[u], pkey[v], gkey[v]))
+            if (key_greater(&rc.keys, u, v))
                 loser[v] = 1;
             else if (remote_loser)
                 remote_loser[u - n_owned] = 1;
@@ -387,8 +427,7 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
     if (st && remote_loser) {
         for (int32_t j = 0; j < n_ghost; j++) st->remote_losers += remote_loser[j];
     }
-    free(pkey);
-    free(gkey);
+    free_keys(&rc.keys);
     free(loser);
     return 0;
 }

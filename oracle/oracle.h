@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #define ORC_TRACE_ROUNDS 4096
+#define ORC_RECOLOR_DEGREES 1   /* key(v) = (deg(v), p(v), gid(v)): recolorDegrees */
 
 typedef struct {
     int32_t num_colors;          /* largest color used */
@@ -25,18 +26,19 @@ void orc_priorities(int32_t n, uint32_t seed, uint32_t *out);  /* out[i] = p(i) 
  * loop first (colors then hold the committed partial state, 0 = uncolored). */
 int orc_color_d1(int32_t n, const int32_t *row_ptr, const int32_t *col, uint32_t seed,
                  const uint32_t *prio, const int32_t *init, int32_t max_rounds,
-                 int32_t *colors, orc_stats *st);
+                 int32_t *colors, orc_stats *st, int flags);
 int orc_color_d2(int32_t n, const int32_t *row_ptr, const int32_t *col, uint32_t seed,
                  const uint32_t *prio, const int32_t *init, int32_t max_rounds,
-                 int32_t *colors, orc_stats *st);
+                 int32_t *colors, orc_stats *st, int flags);
 int orc_color_pd2(int32_t n_rows, int32_t n_cols, const int32_t *row_ptr, const int32_t *col_idx,
                   const int32_t *col_ptr, const int32_t *row_idx, uint32_t seed,
                   const uint32_t *prio, const int32_t *init, int32_t max_rounds,
-                  int32_t *col_colors, orc_stats *st);
+                  int32_t *col_colors, orc_stats *st, int flags);
 int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1,
                        const int32_t *row_ptr, const int32_t *col, const int32_t *gid,
-                       const int32_t *ghost_colors, uint32_t seed,
-                       int32_t *owned_colors, unsigned char *remote_loser, orc_stats *st);
+                       const int32_t *ghost_colors, uint32_t seed, const int32_t *init_owned,
+                       const int32_t *ghost_degree, int32_t *owned_colors,
+                       unsigned char *remote_loser, orc_stats *st, int flags);
 void orc_serial_greedy(int32_t n, const int32_t *row_ptr, const int32_t *col,
                        const int32_t *order, int32_t *colors);
 #endif

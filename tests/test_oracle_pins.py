@@ -254,19 +254,60 @@ def test_dense_twin_agrees(seed):
     assert np.array_equal(r.colors, C) and r.rounds == rounds
 
 
-def test_all_graphs_on_four_vertices_all_orders():
-    """Every labelled graph on 4 vertices under every priority order:
-    the oracle agrees with the dense twin and gives a first-fit coloring."""
-    pairs = list(itertools.combinations(range(4), 2))
-    for mask in range(1 << len(pairs)):
-        edges = [p for k, p in enumerate(pairs) if mask >> k & 1]
-        g = gg.from_edge_list(4, edges)
-        a = gg.to_dense(g)
-        for perm in itertools.permutations(range(4)):
-            prio = np.array(perm, np.uint32)
-            r = oracle.color_d1(g, prio=prio)
-            C, rounds = _dense_twin_d1(a, prio.astype(np.int64))
-            assert np.array_equal(r.colors, C) and r.rounds == rounds
+def _sets_twin_d1(n, adj, keys):
+    """The synchronous rounds written with Python sets, straight from the
+    definition (a second, independent formulation for tiny graphs): every
+    worklist vertex takes the smallest color absent from its neighbours'
+    committed colors; it loses when a worklist neighbour drew the same color
+    and has the greater key; winners commit."""
+    C = [0] * n
+    W = set(range(n))
+    rounds = 0
+    while W:
+        rounds += 1
+        T = {}
+        for v in W:
+            used = {C[u] for u in adj[v]}
+            t = 1
+            while t in used:
+                t += 1
+            T[v] = t
+        L = {v for v in W if any(u in W and T[u] == T[v] and keys[u] > keys[v] for u in adj[v])}
+        for v in W - L:
+            C[v] = T[v]
+        W = L
+    return C, rounds
+
+
+def test_all_graphs_up_to_five_vertices_all_orders():
+    """Every labelled graph on 1..5 vertices under every priority order
+    (1 + 2*2 + 8*6 + 64*24 + 1024*120 = 124,469 cases): the oracle equals the
+    set-based twin; the result is a first-fit (Grundy) coloring; it equals
+    serial greedy (Algorithm 1) in descending key order exactly where the
+    order is forced, which differs in 240 of the cases."""
+    cases = differ = 0
+    for n in range(1, 6):
+        pairs = list(itertools.combinations(range(n), 2))
+        for mask in range(1 << len(pairs)):
+            edges = [p for k, p in enumerate(pairs) if mask >> k & 1]
+            g = gg.from_edge_list(n, edges)
+            adj = [set() for _ in range(n)]
+            for a, b in edges:
+                adj[a].add(b)
+                adj[b].add(a)
+            for perm in itertools.permutations(range(n)):
+                prio = np.array(perm, np.uint32)
+                r = oracle.color_d1(g, prio=prio)
+                C, rounds = _sets_twin_d1(n, adj, perm)
+                assert r.colors.tolist() == C and r.rounds == rounds, (n, edges, perm)
+                for v in range(n):
+                    nb = {C[u] for u in adj[v]}
+                    assert all(c in nb for c in range(1, C[v])), (n, edges, perm, v)
+                order = np.argsort(-prio.astype(np.int64), kind="stable").astype(np.int32)
+                differ += not np.array_equal(oracle.serial_greedy(g, order), r.colors)
+                cases += 1
+    assert cases == 124469
+    assert differ == 240
 
 
 # --------------------------------------------------------------------------
@@ -393,6 +434,148 @@ def test_pd2_powerlaw_small_proper():
         cols = b.col_idx[b.row_ptr[row]:b.row_ptr[row + 1]]
         assert len(set(c[cols].tolist())) == cols.size
     assert np.array_equal(c, oracle.color_d1(_column_intersection(b), seed=1).colors)
+
+
+# --------------------------------------------------------------------------
+# work counters: edge_visits is the adjacency entries read per visit
+# --------------------------------------------------------------------------
+
+def _work_d1(g):
+    return np.diff(g.row_ptr).astype(np.int64)
+
+
+def _work_d2(g):
+    """sum over u in N(v) of (1 + deg u): the hop-1 entry plus u's row."""
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    src = np.repeat(np.arange(g.n), deg)
+    return np.bincount(src, weights=1 + deg[g.col], minlength=g.n).astype(np.int64)
+
+
+def _work_pd2(b):
+    """sum over the rows r of column c of (1 + deg r): the CSC entry plus the row."""
+    rdeg = np.diff(b.row_ptr).astype(np.int64)
+    cdeg = np.diff(b.col_ptr).astype(np.int64)
+    src = np.repeat(np.arange(b.n_cols), cdeg)
+    return np.bincount(src, weights=1 + rdeg[b.row_idx], minlength=b.n_cols).astype(np.int64)
+
+
+@pytest.mark.parametrize("kind", ["d1", "d2", "pd2"])
+def test_visit_counters_count_the_walk_of_every_round(kind):
+    """Round by round, vertex_visits grows by the uncolored vertices and
+    edge_visits by their work, counted here with numpy from the CSR/CSC
+    alone (D2: each neighbour entry plus its row; PD2: each CSC entry plus
+    the row's CSR entries).  The partial states come from the round cap."""
+    if kind == "pd2":
+        obj = gg.bipartite_powerlaw(3000, 800, 5, 2.1, seed=4)
+        work, n, run = _work_pd2(obj), obj.n_cols, oracle.color_pd2
+    else:
+        obj = gg.erdos_renyi(1500, 9, 3)
+        work, n = (_work_d1(obj) if kind == "d1" else _work_d2(obj)), obj.n
+        run = oracle.color_d1 if kind == "d1" else oracle.color_d2
+    full = run(obj, seed=2)
+    assert full.vertex_visits == sum(full.worklist)
+    prev_colors = np.zeros(n, dtype=np.int32)
+    prev_v = prev_e = 0
+    for k in range(1, full.rounds + 1):
+        r = run(obj, seed=2, max_rounds=k)
+        unc = prev_colors == 0
+        assert r.vertex_visits - prev_v == int(unc.sum())
+        assert r.edge_visits - prev_e == int(work[unc].sum()), f"round {k}"
+        prev_colors, prev_v, prev_e = r.colors, r.vertex_visits, r.edge_visits
+    assert (prev_v, prev_e) == (full.vertex_visits, full.edge_visits)
+    # closed forms of one full pass: D2 nnz + sum deg^2, PD2 nnz + sum row-deg^2
+    if kind == "d2":
+        assert int(work.sum()) == obj.nnz + int((np.diff(obj.row_ptr).astype(np.int64) ** 2).sum())
+    if kind == "pd2":
+        assert int(work.sum()) == obj.nnz + int((np.diff(obj.row_ptr).astype(np.int64) ** 2).sum())
+
+
+# --------------------------------------------------------------------------
+# recolorDegrees (Section 3.3; Algorithm 4): key = (deg, p, gid)
+# --------------------------------------------------------------------------
+
+def test_golden_path_recolor_degrees():
+    with open(os.path.join(GOLDEN, "path6_recolor_degrees.json")) as f:
+        fx = json.load(f)
+    g = gg.from_edge_list(fx["n"], fx["edges"])
+    r = oracle.color_d1(g, prio=np.array(fx["prio"], np.uint32), recolor_degrees=True)
+    assert r.colors.tolist() == fx["colors"]
+    assert r.rounds == fx["rounds"] and r.worklist == fx["worklist"]
+
+
+@pytest.mark.parametrize("m", [2, 3, 9])
+def test_recolor_degrees_star_center_wins(m):
+    """The center has the lowest priority but the highest degree: it keeps
+    color 1 in round 1 and every leaf takes 2 in round 2 (without degrees
+    the leaves take 1 and the center 2)."""
+    g = gg.star(m)
+    prio = np.arange(m + 1, dtype=np.uint32)[::-1].copy()   # vertex 0 (center) lowest
+    prio[0] = 0
+    r = oracle.color_d1(g, prio=prio, recolor_degrees=True)
+    assert r.colors.tolist() == [1] + [2] * m and r.rounds == 2
+    base = oracle.color_d1(g, prio=prio)
+    assert base.colors.tolist() == [2] + [1] * m
+
+
+@pytest.mark.parametrize("m,k", [(1, 3), (2, 5), (4, 7)])
+def test_recolor_degrees_complete_bipartite(m, k):
+    """K_{m,k} with m < k: the m-side has degree k > m, so whatever the
+    priorities it keeps color 1 and the k-side takes 2, in two rounds."""
+    edges = [(a, m + b) for a in range(m) for b in range(k)]
+    g = gg.from_edge_list(m + k, edges)
+    for seed in range(4):
+        r = oracle.color_d1(g, seed=seed, recolor_degrees=True)
+        assert r.colors.tolist() == [1] * m + [2] * k and r.rounds == 2
+
+
+@pytest.mark.parametrize("make", [lambda: gg.complete(7), lambda: gg.cycle(31), lambda: gg.matching(9)])
+def test_recolor_degrees_regular_graph_is_the_baseline(make):
+    g = make()
+    for seed in range(3):
+        a = oracle.color_d1(g, seed=seed, recolor_degrees=True)
+        b = oracle.color_d1(g, seed=seed)
+        assert np.array_equal(a.colors, b.colors) and a.rounds == b.rounds
+
+
+def _rank_priority(deg, p):
+    """Explicit priorities that order vertices by (deg, p, id): the baseline
+    rule with these priorities must equal recolorDegrees."""
+    order = np.lexsort((np.arange(deg.size), p.astype(np.int64), deg.astype(np.int64)))
+    rank = np.empty(deg.size, np.uint32)
+    rank[order] = np.arange(deg.size, dtype=np.uint32)
+    return rank
+
+
+@pytest.mark.parametrize("kind", ["d1", "d2", "pd2"])
+def test_recolor_degrees_is_baseline_with_degree_ranked_priorities(kind):
+    """Degrees counted here with numpy (D1/D2: adjacency row lengths; PD2:
+    rows per column), priorities from the pinned hash: the degree rule equals
+    the baseline rule under the (deg, p, id) rank, on graphs with many equal
+    degrees and with hubs."""
+    for seed in range(3):
+        if kind == "pd2":
+            b = gg.bipartite_powerlaw(2500, 600, 5, 2.1, seed=seed)
+            deg = np.diff(b.col_ptr)
+            p = oracle.priorities(b.n_cols, seed)
+            a = oracle.color_pd2(b, seed=seed, recolor_degrees=True)
+            c = oracle.color_pd2(b, prio=_rank_priority(deg, p))
+        else:
+            g = gg.rmat(10, 8, seed=seed) if seed else gg.erdos_renyi(1200, 7, seed)
+            deg = np.diff(g.row_ptr)
+            p = oracle.priorities(g.n, seed)
+            run = oracle.color_d1 if kind == "d1" else oracle.color_d2
+            a = run(g, seed=seed, recolor_degrees=True)
+            c = run(g, prio=_rank_priority(deg, p))
+        assert np.array_equal(a.colors, c.colors) and a.rounds == c.rounds and a.worklist == c.worklist
+
+
+def test_recolor_degrees_certificates():
+    """Proper, first-fit complete, at most deg + 1, rounds >= colors."""
+    for seed in range(4):
+        g = gg.rmat(11, 8, seed=seed + 10)
+        r = oracle.color_d1(g, seed=seed, recolor_degrees=True)
+        # key-local maxima under (deg, p, id) take color 1
+        _check_d1_certificate(g, r, prio=_rank_priority(np.diff(g.row_ptr), oracle.priorities(g.n, seed)))
 
 
 # --------------------------------------------------------------------------
