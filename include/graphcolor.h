@@ -72,6 +72,19 @@ extern "C" {
 #define COLOR_FLAG_NO_TAIL  0x2u  /* incremental engine: run every round as its own pair of
                                      launches, never finish with the cooperative tail kernel */
 #define COLOR_FLAG_KERNEL_TIMING 0x4u  /* time every round kernel with HIP events on `stream` */
+/* recolorDegrees (Section 3.3; Algorithm 4 with recolorDegrees set): the one
+ * flag that CHANGES the coloring.  The key becomes key(v) = (deg(v), p(v),
+ * gid(v)), compared lexicographically, so that of two conflicting vertices the
+ * one of LOWER degree is uncolored and p, then gid, only decide between equal
+ * degrees.  deg(v) is computed once, before the rounds: the length of v's row
+ * in row_ptr (color_d1, color_d2), the number of rows of column v in col_ptr
+ * (color_pd2), and for the ghost step an owned vertex's row and a ghost's
+ * ghost_degree entry.  Honoured by color_d1, color_d2, color_pd2 and
+ * color_d1_ghost_step (color_d1_ghost has no ghost degrees and returns
+ * COLOR_EINVAL with it when n_ghost > 0); color_batch and the server return
+ * COLOR_EINVAL.  The library sorts the vertices by this key once per call
+ * (about 36 bytes of workspace per vertex). */
+#define COLOR_FLAG_RECOLOR_DEGREES 0x8u
 
 /* Per-call statistics (HOST struct, every pointer argument of this type is
  * nullable). */
@@ -103,8 +116,9 @@ typedef struct color_stats {
 } color_stats;
 
 /* Tuning knobs (HOST struct, nullable = library defaults / autotuned).  None
- * of them changes a coloring; they only change how the work is mapped onto
- * the GPU.  A zero field means "default". */
+ * of them changes a coloring, except the COLOR_FLAG_RECOLOR_DEGREES flag, which
+ * selects the recolorDegrees key; the rest only change how the work is mapped
+ * onto the GPU.  A zero field means "default". */
 typedef struct color_params {
     int32_t bin_hi[4];      /* work bounds of degree bins 0..3 (bin 4 = above bin_hi[3]) */
     int32_t lanes[3];       /* lanes per vertex of bins 0..2: 1,2,4,8,16,32 or 64 */
@@ -203,6 +217,31 @@ int color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g
                    const int32_t* ghost_colors, uint32_t seed, int32_t* owned_colors,
                    uint8_t* remote_loser, color_stats* stats, const color_params* params,
                    void* stream);
+
+/* The ghost step of color_d1_ghost for every iteration of Algorithm 2's loop
+ * (Section 3, Algorithm 2; Sections 3.2 and 3.3), with two more inputs:
+ *   ghost_colors int32[n_ghost], each >= 0: the ghosts' current colors as
+ *                their owners last communicated them; 0 = not known yet (the
+ *                ghost constrains nothing and conflicts with nothing, as color
+ *                zero means uncolored in Section 3.2)
+ *   ghost_degree nullable int32[n_ghost]: the ghosts' degrees in the global
+ *                graph, as their owners report them; required with
+ *                COLOR_FLAG_RECOLOR_DEGREES when n_ghost > 0 (else
+ *                COLOR_EINVAL)
+ *   init_owned   nullable int32[n_owned]: committed owned colors to start from
+ *                (the previous iteration's output); phase 1 then colors only
+ *                the owned vertices it leaves at 0, ghost-blind, and phases 2
+ *                and 3 judge and repair the boundary against ghost_colors
+ * With init_owned NULL and ghost_degree NULL this is color_d1_ghost.  One
+ * iteration of Algorithm 2's while loop is one call per rank with
+ * init_owned = that rank's colors and ghost_colors = what its neighbours
+ * sent; the loop ends when the calls' boundary_conflicts sum to 0.  Same
+ * errors as color_d1_ghost. */
+int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1,
+                        const int32_t* row_ptr, const int32_t* col_idx, const int32_t* gid,
+                        const int32_t* ghost_colors, const int32_t* ghost_degree, uint32_t seed,
+                        const int32_t* init_owned, int32_t* owned_colors, uint8_t* remote_loser,
+                        color_stats* stats, const color_params* params, void* stream);
 
 /* The priority p of Algorithm 4's rand(GID) as the kernels compute it:
  * out[i] = p(gid ? gid[i] : i) for i < n.  gid nullable (identity).

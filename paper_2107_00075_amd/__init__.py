@@ -13,14 +13,15 @@ import ctypes
 
 from ._binding import (COLOR_E2BIG, COLOR_EGRAPH, COLOR_EINVAL, COLOR_EMISMATCH, COLOR_ENOCONVERGE,
                        COLOR_EPENDING, COLOR_EQUEUED, COLOR_FLAG_KERNEL_TIMING, COLOR_FLAG_NO_TAIL,
-                       COLOR_FLAG_VALIDATE, COLOR_OK, ENGINE_AUTO, ENGINE_BATCH, ENGINE_INCREMENTAL, ENGINE_PULL,
+                       COLOR_FLAG_RECOLOR_DEGREES, COLOR_FLAG_VALIDATE, COLOR_OK, ENGINE_AUTO, ENGINE_BATCH, ENGINE_INCREMENTAL, ENGINE_PULL,
                        EXPORTED, KIND_D1, KIND_D2, KIND_PD2, CHostJob, CJob, ColorError, CParams, CStats, Params,
                        Stats, lib, strerror)
 
 __all__ = [
-    "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_priority", "color_batch",
+    "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_d1_ghost_step", "color_priority", "color_batch",
     "color_autotune", "color_autotune_reset", "ColorServer", "Params", "Stats", "ColorError", "lib",
     "strerror", "EXPORTED", "COLOR_FLAG_VALIDATE", "COLOR_FLAG_NO_TAIL", "COLOR_FLAG_KERNEL_TIMING",
+    "COLOR_FLAG_RECOLOR_DEGREES",
     "ENGINE_AUTO", "ENGINE_PULL", "ENGINE_INCREMENTAL", "ENGINE_BATCH", "KIND_D1", "KIND_D2", "KIND_PD2",
 ]
 
@@ -179,6 +180,32 @@ def color_d1_ghost(n_owned, n_ghost, layers, n_g1, row_ptr, col_idx, gid, ghost_
                               _dev_ptr(rl, "remote_loser") if rl is not None else None,
                               ctypes.byref(st), _params(params), _stream(stream))
     _check(rc, "color_d1_ghost")
+    return out, (rl[:n_ghost] if rl is not None else None), _to_stats(st, buf)
+
+
+def color_d1_ghost_step(n_owned, n_ghost, layers, n_g1, row_ptr, col_idx, gid, ghost_colors, seed=1,
+                        ghost_degree=None, init_owned=None, out=None, remote_loser=True, params=None,
+                        stream=None, trace_cap=0):
+    """One iteration of Algorithm 2 for one rank: color_d1_ghost with the
+    ghosts' current colors (0 = not known yet), their degrees (needed with
+    COLOR_FLAG_RECOLOR_DEGREES) and the rank's committed owned colors to
+    start from.  Returns (owned colors, remote-loser flags or None, Stats)."""
+    torch = _torch()
+    i32 = torch.int32
+    dev = row_ptr.device
+    if out is None:
+        out = torch.empty(max(n_owned, 0), dtype=i32, device=dev)
+    rl = torch.empty(max(n_ghost, 1), dtype=torch.uint8, device=dev) if remote_loser else None
+    st, buf = _stats(trace_cap)
+    rc = lib().color_d1_ghost_step(n_owned, n_ghost, layers, n_g1, _dev_ptr(row_ptr, "row_ptr", i32),
+                                   _dev_ptr(col_idx, "col_idx", i32), _dev_ptr(gid, "gid", i32),
+                                   _dev_ptr(ghost_colors, "ghost_colors", i32, n_ghost) if n_ghost > 0 else None,
+                                   _dev_ptr(ghost_degree, "ghost_degree", i32, n_ghost) if n_ghost > 0 else None,
+                                   seed & 0xFFFFFFFF, _dev_ptr(init_owned, "init_owned", i32, n_owned),
+                                   _dev_ptr(out, "owned_colors", i32, n_owned),
+                                   _dev_ptr(rl, "remote_loser") if rl is not None else None,
+                                   ctypes.byref(st), _params(params), _stream(stream))
+    _check(rc, "color_d1_ghost_step")
     return out, (rl[:n_ghost] if rl is not None else None), _to_stats(st, buf)
 
 

@@ -29,12 +29,13 @@ COLOR_EPENDING = 2
 COLOR_FLAG_VALIDATE = 0x1
 COLOR_FLAG_NO_TAIL = 0x2
 COLOR_FLAG_KERNEL_TIMING = 0x4
+COLOR_FLAG_RECOLOR_DEGREES = 0x8
 
 KIND_D1, KIND_D2, KIND_PD2 = 1, 2, 3
 ENGINE_AUTO, ENGINE_PULL, ENGINE_INCREMENTAL, ENGINE_BATCH = 0, 1, 2, 3
 
 EXPORTED = [
-    "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_priority",
+    "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_d1_ghost_step", "color_priority",
     "color_batch", "color_server_create", "color_server_submit", "color_server_poll",
     "color_server_drain", "color_server_destroy", "color_release_workspace", "color_strerror",
     "color_autotune", "color_autotune_reset",
@@ -108,7 +109,9 @@ class Stats:
 
 @dataclass
 class Params:
-    """Tuning knobs (never change a coloring).  0 = library default."""
+    """Tuning knobs (none changes a coloring, except the flag
+    COLOR_FLAG_RECOLOR_DEGREES, which selects the recolorDegrees key).
+    0 = library default."""
     bin_hi: tuple = (0, 0, 0, 0)
     lanes: tuple = (0, 0, 0)
     split_chunks: int = 0
@@ -157,6 +160,8 @@ def lib():
         l.color_pd2.argtypes = [I32, I32, P, P, P, P, U32, P, P, P, SP, PP, P]
         l.color_d1_ghost.restype = ctypes.c_int
         l.color_d1_ghost.argtypes = [I32, I32, I32, I32, P, P, P, P, U32, P, P, SP, PP, P]
+        l.color_d1_ghost_step.restype = ctypes.c_int
+        l.color_d1_ghost_step.argtypes = [I32, I32, I32, I32, P, P, P, P, P, U32, P, P, P, SP, PP, P]
         l.color_priority.restype = ctypes.c_int
         l.color_priority.argtypes = [I32, P, U32, P, P]
         l.color_batch.restype = ctypes.c_int

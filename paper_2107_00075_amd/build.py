@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgraphcolor.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["rounds.hip", "inc.hip", "setup.hip", "api.hip", "batch.hip", "server.cpp"]
+SOURCES = ["rounds.hip", "inc.hip", "setup.hip", "keys.hip", "api.hip", "batch.hip", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -28,7 +28,7 @@ FLAGS = [
 # Files that define the round and setup kernels the benchmark times (the
 # host-side drivers, the batched and served forms are not among them).
 KERNEL_SOURCES = ["device_common.hpp", "rounds.hpp", "round_steps.hpp", "rounds.hip", "setup.hpp",
-                  "setup.hip", "inc.hpp", "inc.hip"]
+                  "setup.hip", "inc.hpp", "inc.hip", "keys.hpp", "keys.hip"]
 
 
 def source_hash() -> str:

@@ -74,7 +74,8 @@ void Workspace::release() {
   for (DevBuf* b : {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
                     &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
                     &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &inc_wl0, &inc_wl1, &scan_tmp,
-                    &deferred_work, &deferred_done})
+                    &deferred_work, &deferred_done, &rank, &rk_key0, &rk_key1, &rk_val0, &rk_val1, &rk_deg0,
+                    &rk_deg1, &rk_tmp})
     b->release();
   if (host) (void)hipHostFree(host);
   host = nullptr;
@@ -179,6 +180,32 @@ int merge_params(int mode, const color_params* user, color_params* out) {
   if (user->engine < 0 || user->engine > COLOR_ENGINE_INCREMENTAL) return COLOR_EINVAL;
   out->engine = user->engine;
   out->flags = user->flags;
+  return COLOR_OK;
+}
+
+// recolorDegrees (Section 3.3; Algorithm 4 with recolorDegrees set): every
+// vertex's rank in (deg, p, gid) order, built once per call in the workspace;
+// k.rank then replaces the (p, gid) key in every kernel of the call.
+int degree_rank(Call& c, int32_t m, const int32_t* deg_ptr, int32_t n_rows, const int32_t* extra_deg,
+                KeySource& k) {
+  if (m <= 0) return COLOR_OK;
+  Workspace* w = c.ws;
+  const size_t mm = static_cast<size_t>(m);
+  const size_t tb = rank_tmp_bytes(m);
+  if (tb == 0) return COLOR_EHIP;
+  int e;
+  if ((e = w->rank.ensure(4 * mm, false, c.st)) || (e = w->rk_key0.ensure(8 * mm, false, c.st)) ||
+      (e = w->rk_key1.ensure(8 * mm, false, c.st)) || (e = w->rk_val0.ensure(4 * mm, false, c.st)) ||
+      (e = w->rk_val1.ensure(4 * mm, false, c.st)) || (e = w->rk_deg0.ensure(4 * mm, false, c.st)) ||
+      (e = w->rk_deg1.ensure(4 * mm, false, c.st)) || (e = w->rk_tmp.ensure(tb, false, c.st)))
+    return e;
+  RankBufs b{w->rk_key0.as<uint64_t>(), w->rk_key1.as<uint64_t>(), w->rk_val0.as<int32_t>(),
+             w->rk_val1.as<int32_t>(), w->rk_deg0.as<uint32_t>(), w->rk_deg1.as<uint32_t>(), w->rk_tmp.p,
+             w->rk_tmp.bytes};
+  if (build_degree_rank(m, deg_ptr, n_rows, extra_deg, k.gid, k.prio, k.hs, b, w->rank.as<uint32_t>(), c.st))
+    return COLOR_EHIP;
+  c.launches += k.prio ? 5 : 3;
+  k.rank = w->rank.as<uint32_t>();
   return COLOR_OK;
 }
 
@@ -754,7 +781,12 @@ static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32
     g.rp2 = rp;
     g.ci2 = ci;
   }
-  KeySource k{prio, nullptr, hash_seed(seed)};
+  KeySource k{prio, nullptr, hash_seed(seed), nullptr};
+  // recolorDegrees: deg(v) is v's hop-1 row (D1/D2: adjacency; PD2: the
+  // column's rows)
+  if (c.P.flags & COLOR_FLAG_RECOLOR_DEGREES) {
+    if ((e = degree_rank(c, n, g.rp, n, nullptr, k))) return e;
+  }
   BinLayout L;
   RoundBufs rb;
   int32_t known[kBins];
@@ -826,15 +858,18 @@ int color_pd2(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr, const int3
                            col_colors, stats, params, stream);
 }
 
-int color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1, const int32_t* row_ptr,
-                   const int32_t* col_idx, const int32_t* gid, const int32_t* ghost_colors, uint32_t seed,
-                   int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats, const color_params* params,
-                   void* stream) {
+int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1, const int32_t* row_ptr,
+                        const int32_t* col_idx, const int32_t* gid, const int32_t* ghost_colors,
+                        const int32_t* ghost_degree, uint32_t seed, const int32_t* init_owned,
+                        int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats,
+                        const color_params* params, void* stream) {
   if (n_owned < 0 || n_ghost < 0 || n_g1 < 0 || n_g1 > n_ghost) return COLOR_EINVAL;
   if (layers != 1 && layers != 2) return COLOR_EINVAL;
   if (static_cast<int64_t>(n_owned) + n_ghost >= INT_MAX) return COLOR_EOVERFLOW;
   if (n_owned > 0 && (!row_ptr || !col_idx || !gid || !owned_colors)) return COLOR_EINVAL;
   if (n_ghost > 0 && (!ghost_colors || !gid)) return COLOR_EINVAL;
+  const bool degrees = params && (params->flags & COLOR_FLAG_RECOLOR_DEGREES);
+  if (degrees && n_ghost > 0 && !ghost_degree) return COLOR_EINVAL;
   const int32_t m = n_owned + n_ghost;
   Call c;
   int e = begin_call(c, kD1, params, stats, stream, n_owned, m);
@@ -857,13 +892,19 @@ int color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g
     if (c.H->err) return COLOR_EGRAPH;
     if (hipMemsetAsync(&c.S->err, 0, sizeof(int32_t), c.st) != hipSuccess) return COLOR_EHIP;
   }
-  KeySource k{nullptr, gid, hash_seed(seed)};
-  // phase 1: ghost-blind rounds on the owned-induced subgraph
+  KeySource k{nullptr, gid, hash_seed(seed), nullptr};
+  // recolorDegrees: an owned vertex's degree is its row (all its edges are
+  // local), a ghost's is the one its owner reports
+  if (degrees) {
+    if ((e = degree_rank(c, m, row_ptr, n_owned, ghost_degree, k))) return e;
+  }
+  // phase 1: ghost-blind rounds on the owned-induced subgraph (with
+  // init_owned: only over the owned vertices it leaves uncolored)
   GraphView g{n_owned, n_owned, row_ptr, col_idx, row_ptr, col_idx};
   BinLayout L;
   RoundBufs rb;
   int32_t known[kBins];
-  if ((e = setup_bins<kD1>(c, g, nullptr, Cint, m, L, rb, known))) return e;
+  if ((e = setup_bins<kD1>(c, g, init_owned, Cint, m, L, rb, known))) return e;
   int rc = run_phase<kD1>(c, g, k, L, rb, known, 0, c.P.max_rounds);
   if (rc != COLOR_OK) return rc == COLOR_ENOCONVERGE ? finish_call(c, stats, -1, rc) : rc;
   if (hipMemcpyAsync(&c.H->rounds_done, &c.S->rounds_done, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) !=
@@ -900,6 +941,14 @@ int color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g
     return COLOR_EHIP;
   if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
   return finish_call(c, stats, c.H->aux_max, rc);
+}
+
+int color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1, const int32_t* row_ptr,
+                   const int32_t* col_idx, const int32_t* gid, const int32_t* ghost_colors, uint32_t seed,
+                   int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats, const color_params* params,
+                   void* stream) {
+  return color_d1_ghost_step(n_owned, n_ghost, layers, n_g1, row_ptr, col_idx, gid, ghost_colors, nullptr, seed,
+                             nullptr, owned_colors, remote_loser, stats, params, stream);
 }
 
 int color_priority(int32_t n, const int32_t* gid, uint32_t seed, uint32_t* out, void* stream) {

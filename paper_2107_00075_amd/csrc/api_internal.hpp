@@ -6,6 +6,7 @@
 
 #include "graphcolor.h"
 #include "inc.hpp"
+#include "keys.hpp"
 #include "setup.hpp"
 
 namespace gcol {
@@ -56,6 +57,7 @@ struct Workspace {
   DevBuf deferred, inc_len, inc_words, inc_fwoff, inc_aoff, inc_F, inc_L0, inc_Ll, inc_B0, inc_B1, inc_bm, scan_tmp;
   DevBuf inc_wl0, inc_wl1;  // incremental engine: worklists binned by active-list length
   DevBuf deferred_work, deferred_done;  // setup: per heavy D2/PD2 vertex, its work and slices done
+  DevBuf rank, rk_key0, rk_key1, rk_val0, rk_val1, rk_deg0, rk_deg1, rk_tmp;  // recolorDegrees ranks
   Scalars* host = nullptr;  // pinned staging for read-backs
   std::vector<hipEvent_t> events;  // pool for COLOR_FLAG_KERNEL_TIMING
   ~Workspace();
@@ -87,6 +89,7 @@ struct Call {
 };
 
 void default_params(int mode, color_params* p);
+int degree_rank(Call& c, int32_t m, const int32_t* deg_ptr, int32_t n_rows, const int32_t* extra_deg, KeySource& k);
 void incremental_bins(int mode, int32_t bin_hi[4]);
 int validate_job(const color_job& j, void* stream);
 int merge_params(int mode, const color_params* user, color_params* out);

@@ -344,7 +344,7 @@ __device__ __forceinline__ void run_grab(BatchJob* J, const JobView& V, const Ba
   } else if (e == 2) {
     for (uint32_t q = 0; q < count; ++q) setup_b_unit(J, V, t, static_cast<int32_t>(first + q), s_bc, s_base);
   } else {
-    const KeySource k{nullptr, nullptr, V.hs};
+    const KeySource k{nullptr, nullptr, V.hs, nullptr};
     const bool detect = (e & 1u) == 0;
     const int r = static_cast<int>(detect ? (e - 2) / 2 : (e - 1) / 2);
     round_units<MODE, LD>(J, V, k, t, r, detect, first, count, sh, work_acc, maxc_acc);
@@ -777,6 +777,8 @@ int run_batch(int32_t num_jobs, const color_job* jobs, color_stats* per_job, con
 
 extern "C" int color_batch(int32_t num_jobs, const color_job* jobs, color_stats* per_job,
                            const color_params* params, void* stream) {
+  // jobs carry no degree option: the batched engine keys by (p, gid) only
+  if (params && (params->flags & COLOR_FLAG_RECOLOR_DEGREES)) return COLOR_EINVAL;
   return gcol::run_batch(num_jobs, jobs, per_job, params, stream, true);
 }
 

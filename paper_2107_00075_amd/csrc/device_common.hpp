@@ -37,16 +37,36 @@ inline uint32_t host_fmix32(uint32_t h) {
 
 inline uint32_t hash_seed(uint32_t seed) { return host_fmix32(seed ^ 0x9E3779B9u); }
 
+// Device-coherent accesses.  Arrays that the library's kernels write and
+// later kernels read (colors, tentative colors, worklists, per-call setup
+// arrays) are written and read with device-scope (sc1) loads and stores.
+// Measured on MI355X: plain loads of such data written by an earlier kernel on
+// another XCD could return stale values (agent- or system-scope fences issued
+// by every wavefront at kernel start and end did not prevent it), while
+// device-scope accesses gave bit-exact results in every run.
+template <typename X>
+__device__ __forceinline__ X ld_dev(const X* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename X>
+__device__ __forceinline__ void st_dev(X* p, X v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Where a vertex's key comes from.  key(v) = (p(v), gid(v)) packed into 64
 // bits so that one unsigned compare is the lexicographic compare; the lower
-// key loses a conflict.
+// key loses a conflict.  With recolorDegrees (Section 3.3) the key is
+// (deg(v), p(v), gid(v)); the library then passes each vertex's rank in that
+// order, which compares the same way and never ties.
 struct KeySource {
   const uint32_t* prio;  // nullable: explicit p(v)
   const int32_t* gid;    // nullable: gid(v) = v
   uint32_t hs;           // hash_seed(seed)
+  const uint32_t* rank;  // nullable: recolorDegrees rank (written by an earlier kernel of the call)
 };
 
 __device__ __forceinline__ uint64_t key_of(const KeySource& k, int32_t v) {
+  if (k.rank) return ld_dev(&k.rank[v]);
   const uint32_t g = k.gid ? static_cast<uint32_t>(k.gid[v]) : static_cast<uint32_t>(v);
   const uint32_t p = k.prio ? k.prio[v] : fmix32(g ^ k.hs);
   return (static_cast<uint64_t>(p) << 32) | g;
@@ -96,22 +116,6 @@ __device__ __forceinline__ uint32_t atomic_load_u32(const uint32_t* p) {
 }
 __device__ __forceinline__ int32_t atomic_load_i32(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Device-coherent accesses.  Arrays that the library's kernels write and
-// later kernels read (colors, tentative colors, worklists, per-call setup
-// arrays) are written and read with device-scope (sc1) loads and stores.
-// Measured on MI355X: plain loads of such data written by an earlier kernel on
-// another XCD could return stale values (agent- or system-scope fences issued
-// by every wavefront at kernel start and end did not prevent it), while
-// device-scope accesses gave bit-exact results in every run.
-template <typename X>
-__device__ __forceinline__ X ld_dev(const X* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename X>
-__device__ __forceinline__ void st_dev(X* p, X v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Resets of words that other workgroups update with atomics in the same

@@ -60,6 +60,18 @@ def test_bad_arguments_rejected_on_host(lib):
     assert lib.color_d1_ghost(4, 2, 1, 5, None, None, None, None, 1, None, None, None, None, None) == b.COLOR_EINVAL
     assert lib.color_priority(-1, None, 1, None, None) == b.COLOR_EINVAL
     assert lib.color_batch(-1, None, None, None, None) == b.COLOR_EINVAL
+    step = lib.color_d1_ghost_step
+    assert step(4, 2, 3, 0, None, None, None, None, None, 1, None, None, None, None, None, None) == b.COLOR_EINVAL
+    assert step(-1, 0, 1, 0, None, None, None, None, None, 1, None, None, None, None, None, None) == b.COLOR_EINVAL
+    # recolorDegrees with ghosts but no ghost degrees
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the checks come first
+    pr = b.CParams()
+    pr.flags = b.COLOR_FLAG_RECOLOR_DEGREES
+    assert step(4, 2, 1, 0, fake, fake, fake, fake, None, 1, None, fake, None, None, ctypes.byref(pr),
+                None) == b.COLOR_EINVAL
+    assert lib.color_d1_ghost(4, 2, 1, 0, fake, fake, fake, fake, 1, fake, None, None, ctypes.byref(pr),
+                              None) == b.COLOR_EINVAL
+    assert lib.color_batch(1, None, None, ctypes.byref(pr), None) == b.COLOR_EINVAL
 
 
 def test_batch_and_server_arguments_rejected_on_host(lib):
