@@ -10,6 +10,13 @@ color_d1 through the C-ABI.  Inputs are generated (seeded), uploaded and
 resident in HBM before timing.
 
     value  = (nnz_mesh + nnz_rmat) / seconds per step   [edges colored / s]
+    d2pd2: the same measurement of the D2 + PD2 workload (--workload d2pd2),
+           timed separately after the D1 steps, with its own roofline and
+           CPU baseline
+    stream_copy: a 1 GiB device copy's GB/s, the practical HBM ceiling
+    recolor_degrees: the R-MAT leg colored with the recolorDegrees key
+           (Section 3.3) beside the hash key's colors
+    cpu_baseline_all_cores: the oracle built with OpenMP, every core
     roofline: the dominant kernel's algorithmic bytes / its HIP-event time;
               traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE and
               WRITE_SIZE runs (profiles/pmc_traffic.json, taken on the same
@@ -93,19 +100,58 @@ def make_d1_workload():
     return [("stencil27_128", mesh), ("rmat22_ef16", rm)]
 
 
-def cpu_baseline(sample):
-    """The oracle (plain single-threaded C) on the sample graphs."""
+def cpu_baseline(sample, omp=False):
+    """The oracle on the sample graphs: plain single-threaded C, or (omp) the
+    same source built with OpenMP on the per-vertex loops of each round, on
+    every core the process may use."""
     import oracle
-    oracle.build()
+    oracle.build(omp=omp)
     tot_e, tot_t = 0, 0.0
     for name, g in sample:
         t = time.perf_counter()
-        r = oracle.color_d1(g, seed=1)
+        r = oracle.color_d1(g, seed=1, omp=omp)
         dt = time.perf_counter() - t
-        log(f"[bench] cpu oracle {name}: {dt:.2f}s colors={r.num_colors} rounds={r.rounds}")
+        log(f"[bench] cpu oracle{' (all cores)' if omp else ''} {name}: {dt:.2f}s colors={r.num_colors} "
+            f"rounds={r.rounds}")
         tot_e += g.nnz
         tot_t += dt
     return tot_e / tot_t, tot_t
+
+
+def host_cpu():
+    """The host's CPU model and the cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0))}
+
+
+def stream_copy(torch, dev, reps=5):
+    """STREAM-copy ceiling of this GPU: a 1 GiB device-to-device copy (1 GiB
+    read + 1 GiB written), best of `reps`, timed with events on the current
+    stream."""
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    gbs = 2 * COPY_BYTES / (best / 1e3) / 1e9
+    log(f"[bench] stream copy: {gbs:.0f} GB/s ({best:.3f} ms for 2 GiB moved)")
+    return {"gb_per_s": round(gbs, 1), "bytes_moved": 2 * COPY_BYTES, "ms": round(best, 4),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def load_traffic(kernel, workload):
@@ -219,14 +265,46 @@ def bench_d1(args, torch, gc, dev):
     for name, pg in per_graph.items():
         pg["edges_per_s_kernels_only"] = round(pg["nnz"] / (pg["kernel_ms"] / 1e3), 1) if pg["kernel_ms"] else None
 
-    cpu = None
+    # recolorDegrees (Section 3.3) on the R-MAT leg: colors and time against
+    # the hash key of the timed steps
+    rd = None
+    name, g, rp, ci, colors = graphs[1]
+    rd_params = gc.Params(flags=gc.COLOR_FLAG_RECOLOR_DEGREES)
+    gc.color_d1(rp, ci, seed=1, out=colors, params=rd_params)
+    rd_ms = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = gc.color_d1(rp, ci, seed=1, out=colors, params=rd_params)
+        torch.cuda.synchronize()
+        rd_ms.append((time.perf_counter() - t0) * 1e3)
+    hash_st = stats[-1][1]
+    rd = {"graph": name, "colors": st.num_colors, "rounds": st.rounds, "ms": round(sorted(rd_ms)[1], 3),
+          "hash_key_colors": hash_st.num_colors, "hash_key_rounds": hash_st.rounds,
+          "hash_key_kernel_ms": round(per_graph[name]["kernel_ms"], 3)}
+    log(f"[bench] recolorDegrees on {name}: {st.num_colors} colors in {rd['ms']:.1f} ms "
+        f"(hash key: {hash_st.num_colors} colors)")
+
+    copy = stream_copy(torch, dev)
+
+    cpu = cpu_all = None
     if not args.no_cpu_baseline:
         import graphgen as gg
-        sample = [("stencil27_128", work[0][1]), ("rmat19_ef16", gg.rmat(19, 16, seed=1))]
+        import oracle
+        sample = [("stencil27_128", work[0][1]), ("rmat20_ef16", gg.rmat(20, 16, seed=1))]
+        what = "27-pt stencil 128^3 (full) + R-MAT scale 20 ef16 (1/4 of the R-MAT leg)"
         v, secs = cpu_baseline(sample)
         cpu = {"value": round(v, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
-               "sample": f"27-pt stencil 128^3 (full) + R-MAT scale 19 ef16 (1/8 of the R-MAT leg), "
-                         f"single-threaded C oracle, {secs:.1f}s"}
+               "sample": f"{what}, single-threaded C oracle, {secs:.1f}s"}
+        v, secs = cpu_baseline(sample, omp=True)
+        cpu_all = {"value": round(v, 1), "unit": "edges/s", "cores": oracle.threads(omp=True), "kind": "oracle",
+                   "sample": f"{what}, the same C oracle built with OpenMP on the per-vertex loops of each "
+                             f"round, {secs:.1f}s", "host": host_cpu()}
+
+    sub = None
+    if not args.no_d2pd2:
+        r = bench_d2pd2(args, torch, gc, dev)
+        sub = {k: r[k] for k in ("metric", "value", "unit", "ms_per_step", "config", "roofline", "cpu_baseline")}
 
     return {
         "metric": "edges colored/s (D1)",
@@ -246,6 +324,10 @@ def bench_d1(args, torch, gc, dev):
                    "graphs": per_graph},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
+        "stream_copy": copy,
+        "recolor_degrees": rd,
+        "d2pd2": sub,
     }
 
 
@@ -684,6 +766,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-d2pd2", action="store_true", help="d1: skip the D2 + PD2 block of the line")
     ap.add_argument("--workload", default="d1", choices=["d1", "d2pd2", "batch", "serve", "ghost"])
     ap.add_argument("--ghost-scale", type=int, default=24, help="ghost: R-MAT scale of the partitioned graph")
     ap.add_argument("--jobs", type=int, default=300, help="batch/serve: jobs in the stream")

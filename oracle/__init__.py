@@ -19,15 +19,22 @@ TRACE_ROUNDS = 4096
 RECOLOR_DEGREES = 1   # key(v) = (deg(v), p(v), gid(v)): recolorDegrees (Section 3.3, Algorithm 4)
 
 
-def build(force: bool = False) -> str:
-    """Compile oracle.c with gcc (plain -O2, single thread)."""
+_SO_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def build(force: bool = False, omp: bool = False) -> str:
+    """Compile oracle.c with gcc: plain -O2, single thread (what the tests
+    use), or with omp=True the same source with -fopenmp (the benchmark's
+    all-core CPU baseline; identical results)."""
     src = os.path.join(_HERE, "oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
-        tmp = _SO + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared",
+    so = _SO_OMP if omp else _SO
+    if force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+        tmp = so + f".tmp{os.getpid()}"
+        flags = ["-fopenmp"] if omp else ["-Wno-unknown-pragmas"]
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", *flags, "-fPIC", "-shared",
                                "-o", tmp, src])
-        os.replace(tmp, _SO)
-    return _SO
+        os.replace(tmp, so)
+    return so
 
 
 class _Stats(ctypes.Structure):
@@ -51,14 +58,15 @@ class Result:
     converged: bool = True
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        l = ctypes.CDLL(build())
+def lib(omp: bool = False):
+    if omp not in _libs:
+        l = ctypes.CDLL(build(omp=omp))
         P = ctypes.c_void_p
+        l.orc_threads.restype = ctypes.c_int
+        l.orc_threads.argtypes = []
         l.orc_fmix32.restype = ctypes.c_uint32
         l.orc_fmix32.argtypes = [ctypes.c_uint32]
         l.orc_priority.restype = ctypes.c_uint32
@@ -78,8 +86,8 @@ def lib():
                                          ctypes.c_int]
         l.orc_serial_greedy.restype = None
         l.orc_serial_greedy.argtypes = [ctypes.c_int32, P, P, P, P]
-        _lib = l
-    return _lib
+        _libs[omp] = l
+    return _libs[omp]
 
 
 def _i32(a):
@@ -95,6 +103,11 @@ def _result(colors, st, ret, remote=None) -> Result:
     return Result(colors, st.num_colors, st.rounds, st.vertex_visits, st.edge_visits,
                   st.boundary_conflicts, st.remote_losers, remote,
                   list(st.worklist_trace[:nr]), ret == 0)
+
+
+def threads(omp: bool = False) -> int:
+    """Threads the oracle's per-vertex loops use (1 for the plain build)."""
+    return int(lib(omp).orc_threads())
 
 
 def fmix32(h: int) -> int:
@@ -123,34 +136,34 @@ def _prio_init(prio, init):
 
 
 def color_d1(g, seed: int = 1, prio=None, init=None, max_rounds: int = 0,
-             recolor_degrees: bool = False) -> Result:
+             recolor_degrees: bool = False, omp: bool = False) -> Result:
     rp, col = _i32(g.row_ptr), _i32(g.col)
     p, i = _prio_init(prio, init)
     out = np.zeros(g.n, dtype=np.int32)
     st = _Stats()
-    ret = lib().orc_color_d1(g.n, _ptr(rp), _ptr(col), seed & 0xFFFFFFFF, _ptr(p), _ptr(i),
+    ret = lib(omp).orc_color_d1(g.n, _ptr(rp), _ptr(col), seed & 0xFFFFFFFF, _ptr(p), _ptr(i),
                              max_rounds, _ptr(out), ctypes.byref(st), _flags(recolor_degrees))
     return _result(out, st, ret)
 
 
 def color_d2(g, seed: int = 1, prio=None, init=None, max_rounds: int = 0,
-             recolor_degrees: bool = False) -> Result:
+             recolor_degrees: bool = False, omp: bool = False) -> Result:
     rp, col = _i32(g.row_ptr), _i32(g.col)
     p, i = _prio_init(prio, init)
     out = np.zeros(g.n, dtype=np.int32)
     st = _Stats()
-    ret = lib().orc_color_d2(g.n, _ptr(rp), _ptr(col), seed & 0xFFFFFFFF, _ptr(p), _ptr(i),
+    ret = lib(omp).orc_color_d2(g.n, _ptr(rp), _ptr(col), seed & 0xFFFFFFFF, _ptr(p), _ptr(i),
                              max_rounds, _ptr(out), ctypes.byref(st), _flags(recolor_degrees))
     return _result(out, st, ret)
 
 
 def color_pd2(b, seed: int = 1, prio=None, init=None, max_rounds: int = 0,
-              recolor_degrees: bool = False) -> Result:
+              recolor_degrees: bool = False, omp: bool = False) -> Result:
     arrs = [_i32(x) for x in (b.row_ptr, b.col_idx, b.col_ptr, b.row_idx)]
     p, i = _prio_init(prio, init)
     out = np.zeros(b.n_cols, dtype=np.int32)
     st = _Stats()
-    ret = lib().orc_color_pd2(b.n_rows, b.n_cols, *[_ptr(a) for a in arrs], seed & 0xFFFFFFFF,
+    ret = lib(omp).orc_color_pd2(b.n_rows, b.n_cols, *[_ptr(a) for a in arrs], seed & 0xFFFFFFFF,
                               _ptr(p), _ptr(i), max_rounds, _ptr(out), ctypes.byref(st),
                               _flags(recolor_degrees))
     return _result(out, st, ret)

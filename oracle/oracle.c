@@ -4,9 +4,13 @@
  * benchmark's CPU-baseline leg, never by the library's product path.  It
  * shares no code, header, table or constant generator with the GPU library.
  *
- * Plain, slow, single-threaded C: every per-round loop below is written the
- * way the method is defined, with no bitmasks, no blocking and no fusion, so
- * that a reader can check it against the paper by eye.
+ * Plain, slow C: every per-round loop below is written the way the method is
+ * defined, with no bitmasks, no blocking and no fusion, so that a reader can
+ * check it against the paper by eye.  Built plainly (as the tests build it)
+ * it is single-threaded.  Built with -fopenmp (the benchmark's all-core CPU
+ * baseline only) the per-vertex loops of the color and detect steps run on
+ * several threads: each vertex of those loops reads only the previous step's
+ * arrays and writes only its own entry, so the result is the same.
  *
  * The method (Bogle et al., "Parallel Graph Coloring Algorithms for
  * Distributed GPU Environments"):
@@ -55,6 +59,19 @@
 #include <string.h>
 
 #include "oracle.h"
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the per-vertex loops may use: 1 in the plain build. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------------- */
 /* Priority: rand(GID) of Algorithm 4                                      */
@@ -212,7 +229,7 @@ static int32_t run_rounds(const rounds_t *rc, int32_t *colors, orc_stats *st,
     int32_t *T = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
     unsigned char *in_w = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
     unsigned char *lost = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
-    list_t W = {0}, nb = {0};
+    list_t W = {0};
     int32_t r = 0;
 
     for (int32_t v = 0; v < n; v++)
@@ -225,27 +242,42 @@ static int32_t run_rounds(const rounds_t *rc, int32_t *colors, orc_stats *st,
             if (round0 + r - 1 < ORC_TRACE_ROUNDS) st->worklist_trace[round0 + r - 1] = W.len;
         }
         /* color step: reads the committed snapshot only */
-        for (int64_t i = 0; i < W.len; i++) {
-            int32_t v = W.ids[i];
-            int64_t vis = neighbourhood(rc->g, v, &nb);
+        {
+            int64_t vis = 0;
+#pragma omp parallel if (W.len > 4096) reduction(+ : vis)
+            {
+                list_t nbt = {0};
+#pragma omp for schedule(dynamic, 256)
+                for (int64_t i = 0; i < W.len; i++) {
+                    int32_t v = W.ids[i];
+                    vis += neighbourhood(rc->g, v, &nbt);
+                    T[v] = first_fit(&nbt, colors, rc->n_base, rc->ghost_col, rc->ignore_from);
+                }
+                free(nbt.ids);
+            }
             if (st) st->edge_visits += vis;
-            T[v] = first_fit(&nb, colors, rc->n_base, rc->ghost_col, rc->ignore_from);
         }
         /* detect step: v loses when a worklist neighbour holds the same
          * tentative color with a greater key; judged all at once */
-        for (int64_t i = 0; i < W.len; i++) {
-            int32_t v = W.ids[i];
-            lost[v] = 0;
-            neighbourhood(rc->g, v, &nb);
-            for (int64_t k = 0; k < nb.len; k++) {
-                int32_t u = nb.ids[k];
-                if (u >= rc->ignore_from || u >= n) continue;  /* ghosts are never in the worklist */
-                if (!in_w[u]) continue;
-                if (T[u] == T[v] && key_greater(&rc->keys, u, v)) {
-                    lost[v] = 1;
-                    break;
+#pragma omp parallel if (W.len > 4096)
+        {
+            list_t nbt = {0};
+#pragma omp for schedule(dynamic, 256)
+            for (int64_t i = 0; i < W.len; i++) {
+                int32_t v = W.ids[i];
+                lost[v] = 0;
+                neighbourhood(rc->g, v, &nbt);
+                for (int64_t k = 0; k < nbt.len; k++) {
+                    int32_t u = nbt.ids[k];
+                    if (u >= rc->ignore_from || u >= n) continue;  /* ghosts are never in the worklist */
+                    if (!in_w[u]) continue;
+                    if (T[u] == T[v] && key_greater(&rc->keys, u, v)) {
+                        lost[v] = 1;
+                        break;
+                    }
                 }
             }
+            free(nbt.ids);
         }
         /* commit winners, losers form the next worklist */
         {
@@ -267,7 +299,6 @@ static int32_t run_rounds(const rounds_t *rc, int32_t *colors, orc_stats *st,
     free(in_w);
     free(lost);
     free(W.ids);
-    free(nb.ids);
     return r;
 }
 

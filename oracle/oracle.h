@@ -18,6 +18,7 @@ typedef struct {
     int64_t worklist_trace[ORC_TRACE_ROUNDS];  /* |W_r| per round */
 } orc_stats;
 
+int orc_threads(void);   /* threads of the per-vertex loops (1 unless built with -fopenmp) */
 uint32_t orc_fmix32(uint32_t h);
 uint32_t orc_priority(uint32_t gid, uint32_t seed);
 void orc_priorities(int32_t n, uint32_t seed, uint32_t *out);  /* out[i] = p(i) */

@@ -1,14 +1,14 @@
 """Full-size parity on the benchmark graphs, in the launch configuration the
-benchmark times (library defaults, both engines):
+benchmark times (library defaults, both engines where the library has two),
+against the oracle's results stored as SHA-256 digests of the color arrays
+plus the round statistics by tests/golden/make_golden.py, which calls only
+the oracle:
 
-* 27-point stencil 128^3 (D1), R-MAT scale 22 (D1) and 7-point stencil 96^3
-  (D2) against the oracle's results, stored as SHA-256 digests of the color
-  arrays plus the round statistics by tests/golden/make_golden.py, which
-  calls only the oracle;
-* the 4,000,000 x 1,000,000 PD2 pattern, which the oracle cannot finish in
-  reasonable time, through properties that hold at any size: every column
-  colored, no two columns of a row alike, the first-fit certificate on
-  sampled columns, rounds >= colors, and identical results on both engines.
+* 27-point stencil 128^3 (D1), R-MAT scale 22 (D1), 7-point stencil 96^3 (D2);
+* the 4,000,000 x 1,000,000 power-law PD2 pattern (about half an hour of
+  oracle time on one core), plus properties that hold at any size;
+* one rank's ghost step on part 0 of R-MAT scale 24 split 16 ways, with one
+  and with two ghost layers (colors, remote-loser flags, conflict counts).
 """
 import hashlib
 import json
@@ -81,15 +81,17 @@ def test_stencil7_96_d2(gc, engine):
     check_golden(c.cpu().numpy(), st, ref, f"7pt 96^3 D2 engine {engine}")
 
 
-def test_pd2_4m_by_1m_properties(gc):
+def test_pd2_4m_by_1m(gc):
     b = gg.bipartite_powerlaw(4_000_000, 1_000_000, 8, 2.1, seed=1)
+    ref = golden("pd2_4m_1m_seed1")
+    assert (b.n_rows, b.n_cols, b.nnz) == (ref["n_rows"], ref["n"], ref["nnz"])
     args = (dev(b.row_ptr), dev(b.col_idx), dev(b.col_ptr), dev(b.row_idx))
     out = {}
     for engine in (1, 2):
-        c, st = gc.color_pd2(*args, seed=1, params=gc.Params(engine=engine))
+        c, st = gc.color_pd2(*args, seed=1, params=gc.Params(engine=engine), trace_cap=4096)
         out[engine] = (c.cpu().numpy(), st)
+        check_golden(out[engine][0], st, ref, f"PD2 4M x 1M engine {engine}")
     (c1, s1), (c2, s2) = out[1], out[2]
-    assert np.array_equal(c1, c2), "engines disagree"
     assert (s1.rounds, s1.num_colors, s1.vertex_visits, s1.edge_visits) == \
         (s2.rounds, s2.num_colors, s2.vertex_visits, s2.edge_visits)
     colors = c1
@@ -108,3 +110,28 @@ def test_pd2_4m_by_1m_properties(gc):
         nb = nb[nb != c]
         seen = set(colors[nb].tolist())
         assert all(x in seen for x in range(1, colors[c])), f"column {c}: color {colors[c]} not first fit"
+
+
+@pytest.fixture(scope="module")
+def rmat24_parts():
+    """R-MAT 24 ef16 seed 1 split 16 ways by hash, ghost colors per global id
+    (the workload the golden digests were written for)."""
+    g = gg.rmat(24, 16, seed=1)
+    delta = int(g.degrees().max())
+    owner = gg.hash_partition(g.n, 16, seed=7)
+    gcol = gg.ghost_colors_uniform(g.n, delta, seed=11)
+    return g, owner, gcol
+
+
+@pytest.mark.parametrize("layers", [1, 2])
+def test_rmat24_part0_ghost(gc, rmat24_parts, layers):
+    g, owner, gcol = rmat24_parts
+    lg = gg.ghost_local_graph(g, owner, 0, layers, gcol, sort_rows=False)
+    ref = golden(f"rmat24_part0_l{layers}")
+    assert (lg.n_owned, lg.n_ghost, lg.n_g1, lg.nnz) == (ref["n"], ref["n_ghost"], ref["n_g1"], ref["nnz"])
+    colors, rl, st = gc.color_d1_ghost(lg.n_owned, lg.n_ghost, lg.layers, lg.n_g1, dev(lg.row_ptr), dev(lg.col),
+                                       dev(lg.gid), dev(lg.ghost_colors), seed=1, trace_cap=4096)
+    check_golden(colors.cpu().numpy(), st, ref, f"R-MAT 24 part 0, {layers} layer(s)")
+    flags = hashlib.sha256(np.ascontiguousarray(rl.cpu().numpy(), dtype=np.uint8).tobytes()).hexdigest()
+    assert flags == ref["remote_loser_sha256"]
+    assert (st.boundary_conflicts, st.remote_losers) == (ref["boundary_conflicts"], ref["remote_losers"])
