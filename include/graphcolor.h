@@ -65,6 +65,7 @@ extern "C" {
 #define COLOR_ENOCONVERGE  -6   /* params->max_rounds reached: outputs hold the partial state */
 #define COLOR_E2BIG        -7   /* server: the job can never fit the HBM budget */
 #define COLOR_EMISMATCH    -8   /* autotune: two mappings gave different colorings (a library defect) */
+#define COLOR_ESCRATCH     -9   /* color_d1_noalloc: n above COLOR_NOALLOC_MAX_N */
 #define COLOR_EQUEUED       1   /* server: job accepted, waiting for memory/slots */
 #define COLOR_EPENDING      2   /* server: job not finished yet */
 
@@ -242,6 +243,27 @@ int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_
                         const int32_t* ghost_colors, const int32_t* ghost_degree, uint32_t seed,
                         const int32_t* init_owned, int32_t* owned_colors, uint8_t* remote_loser,
                         color_stats* stats, const color_params* params, void* stream);
+
+/* color_d1 for callers that cannot allocate memory (serving loops and
+ * harnesses that forbid hipMalloc between requests): same arguments, same
+ * coloring and statistics as color_d1, and the call allocates no device or
+ * host memory.  Its workspace is a static device array of about 17 MiB that
+ * each GPU the library runs on holds until the process ends; its address is
+ * taken once per device on the device's first call.  It always runs the pull
+ * engine with workgroup-wide heavy vertices (the layouts that fit that array),
+ * which gives the same coloring as every other engine.  Limits and errors:
+ * n above COLOR_NOALLOC_MAX_N returns COLOR_ESCRATCH; COLOR_FLAG_KERNEL_TIMING,
+ * COLOR_FLAG_RECOLOR_DEGREES, engine = COLOR_ENGINE_INCREMENTAL and a
+ * stats->trace_cap above 4096 return COLOR_EINVAL; otherwise as color_d1.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents; calls on one device are serialized by an internal lock
+ * (calls that overlapped on one device would race on the array).  Blocking
+ * like color_d1 (it synchronizes `stream` to read the worklist sizes), so it
+ * cannot be recorded into a graph. */
+#define COLOR_NOALLOC_MAX_N (1 << 20)
+int color_d1_noalloc(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t seed,
+                     const uint32_t* prio, const int32_t* init_colors, int32_t* colors,
+                     color_stats* stats, const color_params* params, void* stream);
 
 /* The priority p of Algorithm 4's rand(GID) as the kernels compute it:
  * out[i] = p(gid ? gid[i] : i) for i < n.  gid nullable (identity).

@@ -11,7 +11,8 @@ from __future__ import annotations
 
 import ctypes
 
-from ._binding import (COLOR_E2BIG, COLOR_EGRAPH, COLOR_EINVAL, COLOR_EMISMATCH, COLOR_ENOCONVERGE,
+from ._binding import (COLOR_E2BIG, COLOR_EGRAPH, COLOR_EINVAL, COLOR_EMISMATCH, COLOR_ENOCONVERGE, COLOR_ESCRATCH,
+                       NOALLOC_MAX_N,
                        COLOR_EPENDING, COLOR_EQUEUED, COLOR_FLAG_KERNEL_TIMING, COLOR_FLAG_NO_TAIL,
                        COLOR_FLAG_RECOLOR_DEGREES, COLOR_FLAG_VALIDATE, COLOR_OK, ENGINE_AUTO, ENGINE_BATCH, ENGINE_INCREMENTAL, ENGINE_PULL,
                        EXPORTED, KIND_D1, KIND_D2, KIND_PD2, CHostJob, CJob, ColorError, CParams, CStats, Params,
@@ -19,6 +20,7 @@ from ._binding import (COLOR_E2BIG, COLOR_EGRAPH, COLOR_EINVAL, COLOR_EMISMATCH,
 
 __all__ = [
     "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_d1_ghost_step", "color_priority", "color_batch",
+    "color_d1_noalloc", "NOALLOC_MAX_N", "COLOR_ESCRATCH",
     "color_autotune", "color_autotune_reset", "ColorServer", "Params", "Stats", "ColorError", "lib",
     "strerror", "EXPORTED", "COLOR_FLAG_VALIDATE", "COLOR_FLAG_NO_TAIL", "COLOR_FLAG_KERNEL_TIMING",
     "COLOR_FLAG_RECOLOR_DEGREES",
@@ -128,6 +130,15 @@ def color_d1(row_ptr, col_idx, seed=1, prio=None, init_colors=None, out=None, pa
     """Distance-1 coloring of a symmetric int32 CSR graph on the GPU.
     Returns (colors int32 tensor, Stats)."""
     return _color_sym(lib().color_d1, row_ptr, col_idx, seed, prio, init_colors, out, params, stream,
+                      trace_cap, allow_partial)
+
+
+def color_d1_noalloc(row_ptr, col_idx, seed=1, prio=None, init_colors=None, out=None, params=None,
+                     stream=None, trace_cap=0, allow_partial=False):
+    """color_d1 without any allocation inside the library (graphs of up to
+    NOALLOC_MAX_N vertices; `out` should be passed by callers that cannot
+    allocate either).  Returns (colors int32 tensor, Stats)."""
+    return _color_sym(lib().color_d1_noalloc, row_ptr, col_idx, seed, prio, init_colors, out, params, stream,
                       trace_cap, allow_partial)
 
 

@@ -23,6 +23,8 @@ COLOR_EHIP = -5
 COLOR_ENOCONVERGE = -6
 COLOR_E2BIG = -7
 COLOR_EMISMATCH = -8
+COLOR_ESCRATCH = -9
+NOALLOC_MAX_N = 1 << 20
 COLOR_EQUEUED = 1
 COLOR_EPENDING = 2
 
@@ -38,7 +40,7 @@ EXPORTED = [
     "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_d1_ghost_step", "color_priority",
     "color_batch", "color_server_create", "color_server_submit", "color_server_poll",
     "color_server_drain", "color_server_destroy", "color_release_workspace", "color_strerror",
-    "color_autotune", "color_autotune_reset",
+    "color_autotune", "color_autotune_reset", "color_d1_noalloc",
 ]
 
 
@@ -152,7 +154,7 @@ def lib():
         P, I32, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
         SP = ctypes.POINTER(CStats)
         PP = ctypes.POINTER(CParams)
-        for name in ("color_d1", "color_d2"):
+        for name in ("color_d1", "color_d2", "color_d1_noalloc"):
             f = getattr(l, name)
             f.restype = ctypes.c_int
             f.argtypes = [I32, P, P, U32, P, P, P, SP, PP, P]

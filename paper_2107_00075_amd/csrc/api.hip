@@ -27,6 +27,7 @@ namespace gcol {
 int DevBuf::ensure(size_t need, bool zero, hipStream_t st) {
   if (need == 0) need = 1;
   if (bytes >= need) return COLOR_OK;
+  if (fixed) return COLOR_EOVERFLOW;
   if (p) {
     if (hipFree(p) != hipSuccess) return COLOR_EHIP;
     p = nullptr;
@@ -48,7 +49,7 @@ int DevBuf::ensure(size_t need, bool zero, hipStream_t st) {
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p && !fixed) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
 }
@@ -68,15 +69,18 @@ int Call::record_event(int kind_of_next) {
   return COLOR_OK;
 }
 
+std::array<DevBuf*, Workspace::kNumBuffers> Workspace::buffers() {
+  return {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
+          &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
+          &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &inc_wl0, &inc_wl1, &scan_tmp,
+          &deferred_work, &deferred_done, &rank, &rk_key0, &rk_key1, &rk_val0, &rk_val1, &rk_deg0,
+          &rk_deg1, &rk_tmp};
+}
+
 void Workspace::release() {
   for (hipEvent_t e : events) (void)hipEventDestroy(e);
   events.clear();
-  for (DevBuf* b : {&T, &C, &work, &bin, &wl0, &wl1, &small, &trace, &split_vertex, &split_ctr,
-                    &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
-                    &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &inc_wl0, &inc_wl1, &scan_tmp,
-                    &deferred_work, &deferred_done, &rank, &rk_key0, &rk_key1, &rk_val0, &rk_val1, &rk_deg0,
-                    &rk_deg1, &rk_tmp})
-    b->release();
+  for (DevBuf* b : buffers()) b->release();
   if (host) (void)hipHostFree(host);
   host = nullptr;
 }
@@ -288,16 +292,22 @@ int setup_bins(Call& c, const GraphView& g, const int32_t* init, int32_t* C, int
   s.maxc = &S->maxc;
   s.max_split_work = &S->max_split_work;
   s.max_work = &S->max_work;
-  int e0;
-  if ((e0 = w->deferred.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n, 1)), false, c.st))) return e0;
-  s.deferred = w->deferred.as<int32_t>();
-  if ((e0 = w->deferred_work.ensure(sizeof(unsigned long long) * static_cast<size_t>(std::max(n, 1)), false,
-                                    c.st)))
-    return e0;
-  if ((e0 = w->deferred_done.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n, 1)), false, c.st)))
-    return e0;
-  s.deferred_work = w->deferred_work.as<unsigned long long>();
-  s.deferred_done = w->deferred_done.as<int32_t>();
+  // heavy D2/PD2 vertices are set up by workgroups; D1 has none
+  s.deferred = nullptr;
+  s.deferred_work = nullptr;
+  s.deferred_done = nullptr;
+  if (MODE != kD1) {
+    int e0;
+    if ((e0 = w->deferred.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n, 1)), false, c.st))) return e0;
+    if ((e0 = w->deferred_work.ensure(sizeof(unsigned long long) * static_cast<size_t>(std::max(n, 1)), false,
+                                      c.st)))
+      return e0;
+    if ((e0 = w->deferred_done.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n, 1)), false, c.st)))
+      return e0;
+    s.deferred = w->deferred.as<int32_t>();
+    s.deferred_work = w->deferred_work.as<unsigned long long>();
+    s.deferred_done = w->deferred_done.as<int32_t>();
+  }
   s.deferred_cnt = &S->deferred_cnt;
   s.deferred_grab = &S->deferred_grab[0];
   s.total_work = &S->total_work;
@@ -357,8 +367,21 @@ template int setup_bins<kD2>(Call&, const GraphView&, const int32_t*, int32_t*, 
 template int setup_bins<kPD2>(Call&, const GraphView&, const int32_t*, int32_t*, int32_t, BinLayout&,
                               RoundBufs&, int32_t*);
 
+// Clears `words` 32-bit words with a fill kernel (not hipMemsetAsync, so that
+// the clear is an ordinary kernel node wherever a caller records the stream).
+__global__ void zero_words_kernel(uint32_t* p, size_t words) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < words) p[i] = 0u;
+}
+
+void launch_zero_words(void* p, size_t words, hipStream_t st) {
+  if (words == 0) return;
+  hipLaunchKernelGGL(zero_words_kernel, dim3(static_cast<unsigned>((words + 255) / 256)), dim3(256), 0, st,
+                     static_cast<uint32_t*>(p), words);
+}
+
 int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, void* stream, int32_t n,
-               int32_t n_total) {
+               int32_t n_total, Workspace* fixed_ws) {
   int e = merge_params(mode, user, &c.P);
   if (e) return e;
   c.user_bins = false;
@@ -369,7 +392,7 @@ int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, 
   // COLOR_ENOCONVERGE instead of an endless loop.
   if (c.P.max_rounds == 0) c.P.max_rounds = n_total < INT_MAX ? n_total + 1 : INT_MAX;
   c.st = static_cast<hipStream_t>(stream);
-  c.ws = workspace_for_current_device(&e);
+  c.ws = fixed_ws ? fixed_ws : workspace_for_current_device(&e);
   if (!c.ws) return e;
   c.trace_cap = (stats && stats->worklist_trace && stats->trace_cap > 0) ? stats->trace_cap : 0;
   c.timing = (c.P.flags & COLOR_FLAG_KERNEL_TIMING) != 0 && stats != nullptr;
@@ -386,8 +409,10 @@ int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, 
   c.H = w->host;
   c.wl[0] = w->wl0.as<int32_t>();
   c.wl[1] = w->wl1.as<int32_t>();
-  if (hipMemsetAsync(c.S, 0, sizeof(Scalars), c.st) != hipSuccess) return COLOR_EHIP;
-  return COLOR_OK;
+  static_assert(sizeof(Scalars) % 4 == 0, "Scalars is cleared in 32-bit words");
+  launch_zero_words(c.S, sizeof(Scalars) / 4, c.st);
+  c.launches += 1;
+  return hipGetLastError() == hipSuccess ? COLOR_OK : COLOR_EHIP;
 }
 
 int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc) {
@@ -427,15 +452,15 @@ int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc) {
       }
     }
     if (c.trace_cap > 0) {
+      // through a stack buffer: the no-allocation entry point shares this path
       const int nr = std::min(c.trace_cap, c.H->rounds_done);
-      if (nr > 0) {
-        int32_t* tmp = new int32_t[nr];
-        if (hipMemcpy(tmp, c.ws->trace.p, sizeof(int32_t) * nr, hipMemcpyDeviceToHost) != hipSuccess) {
-          delete[] tmp;
+      int32_t tmp[256];
+      for (int i0 = 0; i0 < nr; i0 += 256) {
+        const int k = std::min(256, nr - i0);
+        if (hipMemcpy(tmp, c.ws->trace.as<int32_t>() + i0, sizeof(int32_t) * k, hipMemcpyDeviceToHost) !=
+            hipSuccess)
           return COLOR_EHIP;
-        }
-        for (int i = 0; i < nr; ++i) stats->worklist_trace[i] = tmp[i];
-        delete[] tmp;
+        for (int i = 0; i < k; ++i) stats->worklist_trace[i0 + i] = tmp[i];
       }
     }
   }
@@ -760,17 +785,25 @@ int validate_job(const color_job& j, void* stream) {
   return validate_graph<kPD2>(c, j.n, j.n_rows, j.col_ptr, j.row_idx, j.row_ptr, j.col_idx);
 }
 
+// fixed_ws: the no-allocation entry point's workspace (regions of its static
+// scratch array); the call then runs the pull engine without split vertices,
+// whose buffers that workspace holds, and allocates nothing.
 template <int MODE>
 static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32_t* ci, const int32_t* rp2,
                        const int32_t* ci2, uint32_t seed, const uint32_t* prio, const int32_t* init,
-                       int32_t* colors, color_stats* stats, const color_params* params, void* stream) {
+                       int32_t* colors, color_stats* stats, const color_params* params, void* stream,
+                       Workspace* fixed_ws = nullptr) {
   if (n < 0 || n_rows < 0) return COLOR_EINVAL;
   if (n > 0 && (!rp || !ci || !colors)) return COLOR_EINVAL;
   if (MODE == kPD2 && n > 0 && (!rp2 || !ci2)) return COLOR_EINVAL;
   if (n == INT_MAX || n_rows == INT_MAX) return COLOR_EOVERFLOW;
   Call c;
-  int e = begin_call(c, MODE, params, stats, stream, n, n);
+  int e = begin_call(c, MODE, params, stats, stream, n, n, fixed_ws);
   if (e) return e;
+  if (fixed_ws) {
+    c.P.engine = COLOR_ENGINE_PULL;
+    c.P.bin_hi[3] = INT_MAX;
+  }
   std::unique_lock<std::mutex> lk(c.ws->mu);
   if (n == 0) return finish_call(c, stats, 0, COLOR_OK);
   if (c.P.flags & COLOR_FLAG_VALIDATE) {
@@ -826,6 +859,13 @@ static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32
   const int rc = run_phase<MODE>(c, g, k, L, rb, known, 0, c.P.max_rounds);
   if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
   return finish_call(c, stats, -1, rc);
+}
+
+int color_d1_fixed(Workspace* ws, int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t seed,
+                   const uint32_t* prio, const int32_t* init_colors, int32_t* colors, color_stats* stats,
+                   const color_params* params, void* stream) {
+  return color_graph<kD1>(n, n, row_ptr, col_idx, row_ptr, col_idx, seed, prio, init_colors, colors, stats, params,
+                          stream, ws);
 }
 
 }  // namespace gcol
@@ -983,6 +1023,7 @@ const char* color_strerror(int code) {
     case COLOR_ENOCONVERGE: return "round limit reached (partial coloring returned)";
     case COLOR_E2BIG: return "job exceeds the server's memory budget";
     case COLOR_EMISMATCH: return "two work mappings gave different colorings";
+    case COLOR_ESCRATCH: return "graph exceeds the no-allocation entry point's scratch (COLOR_NOALLOC_MAX_N)";
     case COLOR_EQUEUED: return "job queued";
     case COLOR_EPENDING: return "job pending";
     default: return "unknown error";

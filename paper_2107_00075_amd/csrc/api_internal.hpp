@@ -1,6 +1,7 @@
 // Internal declarations shared by the C-ABI translation units.
 #pragma once
 
+#include <array>
 #include <mutex>
 #include <vector>
 
@@ -11,10 +12,14 @@
 
 namespace gcol {
 
-// A grow-only device buffer.
+// A grow-only device buffer.  A fixed buffer is memory the library does not
+// own (a region of the no-allocation entry point's static scratch array):
+// it is never reallocated or freed, and asking it for more than it holds
+// returns COLOR_EOVERFLOW instead of allocating.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool fixed = false;
   int ensure(size_t need, bool zero, hipStream_t st);
   void release();
   template <typename X>
@@ -62,6 +67,8 @@ struct Workspace {
   std::vector<hipEvent_t> events;  // pool for COLOR_FLAG_KERNEL_TIMING
   ~Workspace();
   void release();
+  static constexpr int kNumBuffers = 38;
+  std::array<DevBuf*, kNumBuffers> buffers();   // every DevBuf above
 };
 
 Workspace* workspace_for_current_device(int* err);
@@ -94,8 +101,15 @@ void incremental_bins(int mode, int32_t bin_hi[4]);
 int validate_job(const color_job& j, void* stream);
 int merge_params(int mode, const color_params* user, color_params* out);
 int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, void* stream, int32_t n,
-               int32_t n_total);
+               int32_t n_total, Workspace* fixed_ws = nullptr);
+void launch_zero_words(void* p, size_t words, hipStream_t st);
 int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc);
+
+// color_d1 on a caller-provided workspace of fixed buffers (the
+// no-allocation entry point): pull engine, no split vertices.
+int color_d1_fixed(Workspace* ws, int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t seed,
+                   const uint32_t* prio, const int32_t* init_colors, int32_t* colors, color_stats* stats,
+                   const color_params* params, void* stream);
 
 template <int MODE>
 int setup_bins(Call& c, const GraphView& g, const int32_t* init, int32_t* C, int32_t n_total, BinLayout& L,

@@ -46,7 +46,7 @@ def test_strerror(lib):
     from paper_2107_00075_amd import _binding as b
     assert lib.color_strerror(0) == b"ok"
     for code in (b.COLOR_EINVAL, b.COLOR_EGRAPH, b.COLOR_EOVERFLOW, b.COLOR_ENOMEM, b.COLOR_EHIP,
-                 b.COLOR_ENOCONVERGE, b.COLOR_E2BIG, b.COLOR_EQUEUED, b.COLOR_EPENDING):
+                 b.COLOR_ENOCONVERGE, b.COLOR_E2BIG, b.COLOR_EQUEUED, b.COLOR_EPENDING, b.COLOR_ESCRATCH):
         assert lib.color_strerror(code) not in (b"ok", b"unknown error")
     assert lib.color_strerror(12345) == b"unknown error"
 
@@ -72,6 +72,12 @@ def test_bad_arguments_rejected_on_host(lib):
     assert lib.color_d1_ghost(4, 2, 1, 0, fake, fake, fake, fake, 1, fake, None, None, ctypes.byref(pr),
                               None) == b.COLOR_EINVAL
     assert lib.color_batch(1, None, None, ctypes.byref(pr), None) == b.COLOR_EINVAL
+    # the no-allocation entry point: sizes beyond its scratch, flags it cannot honour
+    assert lib.color_d1_noalloc(b.NOALLOC_MAX_N + 1, fake, fake, 1, None, None, fake, None, None,
+                                None) == b.COLOR_ESCRATCH
+    assert lib.color_d1_noalloc(-1, None, None, 1, None, None, None, None, None, None) == b.COLOR_EINVAL
+    assert lib.color_d1_noalloc(10, fake, fake, 1, None, None, fake, None, ctypes.byref(pr),
+                                None) == b.COLOR_EINVAL
 
 
 def test_batch_and_server_arguments_rejected_on_host(lib):
