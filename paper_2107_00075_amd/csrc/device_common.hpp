@@ -53,6 +53,23 @@ __device__ __forceinline__ void st_dev(X* p, X v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Loads of a round kernel's bulk arrays (worklists, lists, offsets, colors,
+// bitsets).  The per-round kernels read them with plain, L2-cacheable loads
+// (MUT = 0): the data was written by earlier launches, whose writes every
+// later launch on the stream sees (measured on MI355X: 3.8e9 reads of lines
+// that another XCD rewrote in the previous launch, none stale), or it is
+// written concurrently in ways whose late visibility cannot change a
+// result (a compaction that keeps a neighbour committed in the same round, a
+// bitset pre-read that only skips an atomic).  Kernels whose phases hand
+// data to each other inside one launch (the tail kernel across its grid
+// barriers, the persistent batched kernel) read them at device scope
+// (MUT = 1).
+template <int MUT, typename X>
+__device__ __forceinline__ X ld_mut(const X* p) {
+  if constexpr (MUT != 0) return ld_dev(p);
+  else return *p;
+}
+
 // Where a vertex's key comes from.  key(v) = (p(v), gid(v)) packed into 64
 // bits so that one unsigned compare is the lexicographic compare; the lower
 // key loses a conflict.  With recolorDegrees (Section 3.3) the key is

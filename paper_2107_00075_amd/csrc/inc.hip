@@ -86,14 +86,15 @@ __device__ __forceinline__ uint64_t wsum(uint64_t x) {
 
 // Sets bit c-1 of F[x] unless it is already set (read first: most pushes
 // repeat a small color that an earlier neighbour already pushed).
+template <int MUT>
 __device__ __forceinline__ void push_color(const IncBufs& b, int32_t x, int32_t c, uint64_t& pushes) {
-  const int32_t w0 = ld_dev(&b.fw_off[x]);
-  const int32_t nw = ld_dev(&b.fw_off[x + 1]) - w0;
+  const int32_t w0 = ld_mut<MUT>(&b.fw_off[x]);
+  const int32_t nw = ld_mut<MUT>(&b.fw_off[x + 1]) - w0;
   const int32_t w = (c - 1) >> 5;
   if (w >= nw) return;  // beyond any color x can take: irrelevant to its first fit
   uint32_t* p = b.F + w0 + w;
   const uint32_t bit = 1u << ((c - 1) & 31);
-  if (!(ld_dev(p) & bit)) {
+  if (!(ld_mut<MUT>(p) & bit)) {
     atomicOr(p, bit);
     ++pushes;
   }
@@ -131,6 +132,7 @@ struct IncPre {
   int32_t maxc;
 };
 
+template <int MUT>
 __device__ __forceinline__ void inc_color_phase(const IncBufs& b, const BinLayout& L, int round,
                                                 IncColorShared& sh, const IncPre* pre = nullptr) {
   IncMap& M = sh.M;
@@ -161,21 +163,21 @@ __device__ __forceinline__ void inc_color_phase(const IncBufs& b, const BinLayou
       j -= M.cnt[bin];
       ++bin;
     }
-    const int32_t v = ld_dev(&b.wl_in[L.off[bin] + j]);
-    const int32_t w0 = ld_dev(&b.fw_off[v]);
-    const int32_t nw = min(ld_dev(&b.fw_off[v + 1]) - w0, wmax);
+    const int32_t v = ld_mut<MUT>(&b.wl_in[L.off[bin] + j]);
+    const int32_t w0 = ld_mut<MUT>(&b.fw_off[v]);
+    const int32_t nw = min(ld_mut<MUT>(&b.fw_off[v + 1]) - w0, wmax);
     int32_t t = 32 * nw + 1;
     int32_t w = 0;
     for (; w < nw; ++w) {
-      const uint32_t x = ld_dev(&b.F[w0 + w]);
+      const uint32_t x = ld_mut<MUT>(&b.F[w0 + w]);
       if (x != ~0u) {
         t = 32 * w + __builtin_ctz(~x) + 1;
         break;
       }
     }
     st_dev(&b.T[v], t);
-    work += static_cast<uint64_t>(ld_dev(&b.work[v]));
-    lists += static_cast<uint64_t>(ld_dev(&b.alen_in[v]));
+    work += static_cast<uint64_t>(ld_mut<MUT>(&b.work[v]));
+    lists += static_cast<uint64_t>(ld_mut<MUT>(&b.alen_in[v]));
     // worklist id, two bitset offsets, the words scanned, static work, T write
     bytes += 4 + 8 + 4 * static_cast<uint64_t>(min(w + 1, max(nw, 1))) + 4 + 4;
   }
@@ -197,7 +199,7 @@ __device__ __forceinline__ void inc_color_phase(const IncBufs& b, const BinLayou
 
 __global__ __launch_bounds__(kBlock) void inc_color_kernel(IncBufs b, BinLayout L, int round) {
   __shared__ IncColorShared sh;
-  inc_color_phase(b, L, round, sh);
+  inc_color_phase<0>(b, L, round, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void inc_color_kernel(IncBufs b, BinLayout 
 // lower ones at the back of the vertex's list region (length llen).  Only a
 // higher-key neighbour can beat v, so later detect scans read the front part
 // only; the one push a winner makes reads both parts.
-template <int G>
+template <int G, int MUT>
 __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBufs& b, const BinLayout& L, int round,
                                                  const int32_t* wl, int32_t count, int32_t* s_ent, int8_t* s_tb,
                                                  int32_t* s_wc, int32_t& maxc_acc, uint64_t& bytes,
@@ -221,11 +223,11 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
   const uint64_t gm = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
   const bool first_pass = b.A_in != b.A_out;
   for (int32_t idx = gi; idx < count; idx += per_pass) {
-    const int32_t v = ld_dev(&wl[idx]);
-    const int32_t tv = ld_dev(&b.T[v]);
+    const int32_t v = ld_mut<MUT>(&wl[idx]);
+    const int32_t tv = ld_mut<MUT>(&b.T[v]);
     const uint64_t kv = key_of(k, v);
-    const int32_t base = ld_dev(&b.aoff[v]);
-    const int32_t len = ld_dev(&b.alen_in[v]);
+    const int32_t base = ld_mut<MUT>(&b.aoff[v]);
+    const int32_t len = ld_mut<MUT>(&b.alen_in[v]);
     const int32_t* A = b.A_in + base;
     bool lose = false;
     int32_t read = 0, gath = 0;
@@ -239,13 +241,13 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int32_t e = e0 + sub + j * G;
-        u[j] = e < len ? ld_dev(&A[e]) : -1;
+        u[j] = e < len ? ld_mut<MUT>(&A[e]) : -1;
         read += e < len ? 1 : 0;
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const bool higher = u[j] >= 0 && (!first_pass || key_of(k, u[j]) > kv);
-        t[j] = higher ? (b.uniform ? tv : ld_dev(&b.T[u[j]])) : -1;
+        t[j] = higher ? (b.uniform ? tv : ld_mut<MUT>(&b.T[u[j]])) : -1;
         gath += (higher && !b.uniform) ? 1 : 0;
       }
       bool hit = false;
@@ -260,21 +262,21 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
     if (lose && !compact_now(b, round, v)) {
       if (sub == 0) {
         s_ent[idx] = v;
-        s_tb[idx] = static_cast<int8_t>(inc_bin_of(L, len + ld_dev(&b.llen[v])));  // not the first pass
+        s_tb[idx] = static_cast<int8_t>(inc_bin_of(L, len + ld_mut<MUT>(&b.llen[v])));  // not the first pass
         bytes += 24;
       }
     } else if (lose) {
       // keep the neighbours that are not committed (yet); the first pass
       // also splits them by key
-      const int32_t cap = ld_dev(&b.aoff[v + 1]) - base;
+      const int32_t cap = ld_mut<MUT>(&b.aoff[v + 1]) - base;
       int32_t kept = 0, kept_lo = 0;
       for (int32_t e0 = 0; e0 < len; e0 += G) {
         const int32_t e = e0 + sub;
         int32_t u = -1;
         bool keep = false, hi = true;
         if (e < len) {
-          u = ld_dev(&A[e]);
-          keep = b.uniform || ld_dev(&b.C[u]) == 0;  // round 1: nobody was committed before it
+          u = ld_mut<MUT>(&A[e]);
+          keep = b.uniform || ld_mut<MUT>(&b.C[u]) == 0;  // round 1: nobody was committed before it
           if (first_pass) hi = key_of(k, u) > kv;
         }
         const uint64_t bal_h = (__ballot(keep && hi) >> first) & gm;
@@ -288,7 +290,7 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
       if (sub == 0) {
         st_dev(&b.alen_out[v], kept);
         if (first_pass) st_dev(&b.llen[v], kept_lo);
-        else kept_lo = ld_dev(&b.llen[v]);
+        else kept_lo = ld_mut<MUT>(&b.llen[v]);
         s_ent[idx] = v;
         s_tb[idx] = static_cast<int8_t>(inc_bin_of(L, kept + kept_lo));
         bytes += 28 + 8ull * static_cast<uint64_t>(len) + 4ull * static_cast<uint64_t>(kept + kept_lo);
@@ -299,8 +301,8 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
       // neighbour's bitset is never read again, so a push into it is
       // harmless, and a list was compacted a few rounds ago at most
       // (measured on MI355X: R-MAT 22 D1 40.9 -> 39.9 ms, PD2 unchanged).
-      const int32_t cap = first_pass ? len : ld_dev(&b.aoff[v + 1]) - base;
-      const int32_t lo_len = first_pass ? 0 : ld_dev(&b.llen[v]);
+      const int32_t cap = first_pass ? len : ld_mut<MUT>(&b.aoff[v + 1]) - base;
+      const int32_t lo_len = first_pass ? 0 : ld_mut<MUT>(&b.llen[v]);
       for (int part = 0; part < 2; ++part) {
         const int32_t pb = part == 0 ? 0 : cap - lo_len;
         const int32_t pe = part == 0 ? len : cap;
@@ -309,11 +311,11 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int32_t e = e0 + j * G;
-            x[j] = e < pe ? ld_dev(&A[e]) : -1;
+            x[j] = e < pe ? ld_mut<MUT>(&A[e]) : -1;
           }
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            if (x[j] >= 0) push_color(b, x[j], tv, pushes);
+            if (x[j] >= 0) push_color<MUT>(b, x[j], tv, pushes);
         }
       }
       if (sub == 0) {
@@ -365,16 +367,17 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
 // at a barrier once per kBlock * kIncBatch entries.
 constexpr int kIncBatch = 8;
 
+template <int MUT>
 __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBufs& b, const BinLayout& L, int round,
                                                  int32_t v, int32_t* s_wc, int32_t& maxc_acc, uint64_t& bytes,
                                                  uint64_t& pushes) {
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const bool first_pass = b.A_in != b.A_out;
-  const int32_t tv = ld_dev(&b.T[v]);
+  const int32_t tv = ld_mut<MUT>(&b.T[v]);
   const uint64_t kv = key_of(k, v);
-  const int32_t base = ld_dev(&b.aoff[v]);
-  const int32_t len = ld_dev(&b.alen_in[v]);
+  const int32_t base = ld_mut<MUT>(&b.aoff[v]);
+  const int32_t len = ld_mut<MUT>(&b.alen_in[v]);
   const int32_t* A = b.A_in + base;
   constexpr int32_t step = kBlock * kIncBatch;
   bool lose = false;
@@ -384,7 +387,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j) {
       const int32_t e = e0 + j * kBlock + tid;
-      u[j] = e < len ? ld_dev(&A[e]) : -1;
+      u[j] = e < len ? ld_mut<MUT>(&A[e]) : -1;
       read += e < len ? 1u : 0u;
     }
     // only a higher-key neighbour can beat v: before the lists are split by
@@ -392,7 +395,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j) {
       const bool higher = u[j] >= 0 && (!first_pass || key_of(k, u[j]) > kv);
-      t[j] = higher ? (b.uniform ? tv : ld_dev(&b.T[u[j]])) : -1;
+      t[j] = higher ? (b.uniform ? tv : ld_mut<MUT>(&b.T[u[j]])) : -1;
       read += (higher && !b.uniform) ? 1u : 0u;
     }
 #pragma unroll
@@ -406,7 +409,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
   bytes += 4ull * read;  // list entries and tentative colors this thread read
   if (lose && !compact_now(b, round, v)) {
     if (tid == 0) {
-      const int nb = inc_bin_of(L, len + ld_dev(&b.llen[v]));  // not the first pass
+      const int nb = inc_bin_of(L, len + ld_mut<MUT>(&b.llen[v]));  // not the first pass
       const int32_t p = atomicAdd(&b.cnt_out[nb], 1);
       st_dev(&b.wl_out[L.off[nb] + p], v);
       bytes += 28;
@@ -417,7 +420,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
     // back).  Later passes compact the front part in place: every entry of a
     // step is read before the barrier that precedes the step's writes, and
     // writes land below the step's first entry or inside it.
-    const int32_t cap = ld_dev(&b.aoff[v + 1]) - base;
+    const int32_t cap = ld_mut<MUT>(&b.aoff[v + 1]) - base;
     int32_t kept = 0, kept_lo = 0;
     int32_t* s_lo = s_wc + kWavesPerBlock;
     for (int32_t e0 = 0; e0 < len; e0 += step) {
@@ -426,11 +429,11 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
 #pragma unroll
       for (int j = 0; j < kIncBatch; ++j) {
         const int32_t e = e0 + j * kBlock + tid;
-        u[j] = e < len ? ld_dev(&A[e]) : -1;
+        u[j] = e < len ? ld_mut<MUT>(&A[e]) : -1;
       }
 #pragma unroll
       for (int j = 0; j < kIncBatch; ++j) {
-        const bool keep = u[j] >= 0 && (b.uniform || ld_dev(&b.C[u[j]]) == 0);
+        const bool keep = u[j] >= 0 && (b.uniform || ld_mut<MUT>(&b.C[u[j]]) == 0);
         const bool hi = !first_pass || (u[j] >= 0 && key_of(k, u[j]) > kv);
         keep_hi |= (keep && hi) ? (1u << j) : 0u;
         keep_lo |= (keep && !hi) ? (1u << j) : 0u;
@@ -475,17 +478,17 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
     // late would push over every lower-key neighbour it had in round 1).
     // Back index q = 0, 1, ... is list position cap-1-q; kept entries move
     // to back indices below or at their own, in step order as above.
-    const int32_t lo_len = first_pass ? 0 : ld_dev(&b.llen[v]);
+    const int32_t lo_len = first_pass ? 0 : ld_mut<MUT>(&b.llen[v]);
     for (int32_t q0 = 0; q0 < lo_len; q0 += step) {
       int32_t u[kIncBatch];
       uint32_t keep = 0;
 #pragma unroll
       for (int j = 0; j < kIncBatch; ++j) {
         const int32_t q = q0 + j * kBlock + tid;
-        u[j] = q < lo_len ? ld_dev(&A[cap - 1 - q]) : -1;
+        u[j] = q < lo_len ? ld_mut<MUT>(&A[cap - 1 - q]) : -1;
       }
 #pragma unroll
-      for (int j = 0; j < kIncBatch; ++j) keep |= (u[j] >= 0 && ld_dev(&b.C[u[j]]) == 0) ? (1u << j) : 0u;
+      for (int j = 0; j < kIncBatch; ++j) keep |= (u[j] >= 0 && ld_mut<MUT>(&b.C[u[j]]) == 0) ? (1u << j) : 0u;
       const int32_t cnt = __builtin_popcount(keep);
       int32_t incl = cnt;
 #pragma unroll
@@ -518,8 +521,8 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
     // push the color to every list entry (as in the lane-group path: no
     // committed-color gather first): the whole list on the first pass, else
     // both parts
-    const int32_t cap = first_pass ? len : ld_dev(&b.aoff[v + 1]) - base;
-    const int32_t lo_len = first_pass ? 0 : ld_dev(&b.llen[v]);
+    const int32_t cap = first_pass ? len : ld_mut<MUT>(&b.aoff[v + 1]) - base;
+    const int32_t lo_len = first_pass ? 0 : ld_mut<MUT>(&b.llen[v]);
     for (int part = 0; part < 2; ++part) {
       const int32_t pb = part == 0 ? 0 : cap - lo_len;
       const int32_t pe = part == 0 ? len : cap;
@@ -528,11 +531,11 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
 #pragma unroll
         for (int j = 0; j < kIncBatch; ++j) {
           const int32_t e = e0 + j * kBlock + tid;
-          x[j] = e < pe ? ld_dev(&A[e]) : -1;
+          x[j] = e < pe ? ld_mut<MUT>(&A[e]) : -1;
         }
 #pragma unroll
         for (int j = 0; j < kIncBatch; ++j)
-          if (x[j] >= 0) push_color(b, x[j], tv, pushes);
+          if (x[j] >= 0) push_color<MUT>(b, x[j], tv, pushes);
       }
     }
     if (tid == 0) {
@@ -554,6 +557,7 @@ struct IncDetectShared {
   IncMap M;
 };
 
+template <int MUT>
 __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBufs& b, const BinLayout& L,
                                                  int round, IncDetectShared& sh, const IncPre* pre = nullptr) {
   int32_t& s_unit = sh.unit;
@@ -586,13 +590,13 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
     const int32_t count = min(M.csize[bin], M.cnt[bin] - firstc);
     const int32_t* wl = b.wl_in + L.off[bin] + firstc;
     switch (L.lanes[bin]) {
-      case 1: inc_detect_chunk<1>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
-      case 2: inc_detect_chunk<2>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
-      case 4: inc_detect_chunk<4>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
-      case 8: inc_detect_chunk<8>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
-      case 16: inc_detect_chunk<16>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
-      case 32: inc_detect_chunk<32>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
-      default: inc_detect_chunk<64>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 1: inc_detect_chunk<1, MUT>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 2: inc_detect_chunk<2, MUT>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 4: inc_detect_chunk<4, MUT>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 8: inc_detect_chunk<8, MUT>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 16: inc_detect_chunk<16, MUT>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      case 32: inc_detect_chunk<32, MUT>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
+      default: inc_detect_chunk<64, MUT>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
     }
   }
   // heavy units: the first one of every workgroup is its own (no atomic),
@@ -600,8 +604,8 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
   for (int32_t u = lb; u < M.heavy_total;) {
     const int bin = u < M.cnt[kBlockBin] ? kBlockBin : kSplitBin;
     const int32_t j = bin == kBlockBin ? u : u - M.cnt[kBlockBin];
-    const int32_t v = ld_dev(&b.wl_in[L.off[bin] + j]);
-    inc_detect_block(k, b, L, round, v, s_wc, maxc_acc, bytes, pushes);
+    const int32_t v = ld_mut<MUT>(&b.wl_in[L.off[bin] + j]);
+    inc_detect_block<MUT>(k, b, L, round, v, s_wc, maxc_acc, bytes, pushes);
     if (threadIdx.x == 0) s_unit = static_cast<int32_t>(gridDim.x) + atomicAdd(&b.tile_ctr[1], 1);
     __syncthreads();
     u = s_unit;
@@ -630,7 +634,7 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
 
 __global__ __launch_bounds__(kBlock) void inc_detect_kernel(KeySource k, IncBufs b, BinLayout L, int round) {
   __shared__ IncDetectShared sh;
-  inc_detect_phase(k, b, L, round, sh);
+  inc_detect_phase<0>(k, b, L, round, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -704,9 +708,9 @@ __global__ __launch_bounds__(kBlock) void inc_tail_kernel(KeySource k, IncRoundS
   for (int r = round0; r <= round_cap; ++r) {
     const IncBufs& b = r == 1 ? set.b[0] : set.b[1 + ((r - 1) & 1)];
     const bool first = r == round0;
-    inc_color_phase(b, L, r, sh.c, first ? nullptr : &s_pre);
+    inc_color_phase<1>(b, L, r, sh.c, first ? nullptr : &s_pre);
     if (!grid_sync(bar, err, deadline, &s_ok)) return;
-    inc_detect_phase(k, b, L, r, sh.d, first ? nullptr : &s_pre);
+    inc_detect_phase<1>(k, b, L, r, sh.d, first ? nullptr : &s_pre);
     if (!grid_sync(bar, err, deadline, &s_ok)) return;
     if (threadIdx.x == 0) {
       make_inc_map_from(b.cnt_out, L, s_pre.M);  // the next round's worklist counts
@@ -922,7 +926,7 @@ __global__ __launch_bounds__(kBlock) void inc_init_push_kernel(IncBufs b, int32_
   const int32_t len = ld_dev(&b.alen_in[v]);
   for (int32_t e = 0; e < len; ++e) {
     const int32_t x = ld_dev(&A0[base + e]);
-    if (ld_dev(&b.C[x]) == 0) push_color(b, x, c, pushes);
+    if (ld_dev(&b.C[x]) == 0) push_color<1>(b, x, c, pushes);
   }
 }
 
