@@ -114,6 +114,8 @@ typedef struct color_stats {
     int64_t detect_bytes;        /* algorithmic bytes of the per-round detect kernels (INCREMENTAL; PULL: 0) */
     int64_t tail_kernel_ns;      /* COLOR_FLAG_KERNEL_TIMING: HIP-event duration of the tail kernel */
     int64_t tail_bytes;          /* algorithmic bytes of the tail kernel's rounds (color + detect) */
+    int32_t tail_fallbacks;      /* INCREMENTAL: tail launches whose workgroups were not all resident
+                                    (they ran nothing; the rounds went on as per-round launches) */
 } color_stats;
 
 /* Tuning knobs (HOST struct, nullable = library defaults / autotuned).  None
@@ -130,15 +132,21 @@ typedef struct color_params {
     int32_t tail_threshold; /* INCREMENTAL: worklist size at or below which one cooperative launch
                                runs all remaining rounds (grid barriers between the steps;
                                default 32768).  Its workgroups wait on each other, so they
-                               must all be resident: a caller whose other streams keep
-                               device-filling kernels running at the same time sets
-                               COLOR_FLAG_NO_TAIL (the server's heavy lane does).  A grid
-                               barrier that stalls for 30 s ends the call with COLOR_EHIP;
-                               if the runtime refuses the cooperative launch, the rounds
-                               continue as per-round launches. */
+                               must all be resident: before writing anything they check in
+                               and wait up to tail_checkin_us for each other; if they are not
+                               all resident by then (other streams keep the device full), the
+                               launch does nothing and the rounds continue as per-round
+                               launches (stats->tail_fallbacks counts this).  The same happens
+                               if the runtime refuses the cooperative launch.  A grid barrier
+                               that still stalls for 30 s makes the call start over with
+                               per-round launches only (COLOR_FLAG_NO_TAIL), which gives the
+                               same coloring. */
     int32_t max_workgroups; /* cap on the grid of the round kernels */
     uint32_t flags;         /* COLOR_FLAG_* */
     int32_t engine;         /* COLOR_ENGINE_*: 0 = library choice */
+    int32_t tail_checkin_us;/* INCREMENTAL: how long the tail kernel's workgroups wait for each other
+                               at entry (0: 2000 us; -1: no wait, so every tail launch falls back
+                               to per-round launches) */
 } color_params;
 
 /* Engines (identical colorings).  PULL re-reads every worklist vertex's full

@@ -81,7 +81,8 @@ def _to_stats(st, buf) -> Stats:
     out = Stats(st.num_colors, st.rounds, st.vertex_visits, st.edge_visits, st.boundary_conflicts,
                 st.remote_losers, st.kernel_launches, st.color_kernel_ns, st.detect_kernel_ns,
                 st.color_launches, st.detect_launches, st.engine, st.list_visits, st.pushes,
-                st.color_bytes, st.detect_bytes, st.tail_rounds, st.tail_kernel_ns, st.tail_bytes)
+                st.color_bytes, st.detect_bytes, st.tail_rounds, st.tail_kernel_ns, st.tail_bytes,
+                st.tail_fallbacks)
     if buf is not None:
         out.worklist = list(buf[:min(st.rounds, len(buf))])
     return out

@@ -61,7 +61,7 @@ class CStats(ctypes.Structure):
                 ("tail_rounds", ctypes.c_int32), ("list_visits", ctypes.c_int64),
                 ("pushes", ctypes.c_int64), ("color_bytes", ctypes.c_int64),
                 ("detect_bytes", ctypes.c_int64), ("tail_kernel_ns", ctypes.c_int64),
-                ("tail_bytes", ctypes.c_int64)]
+                ("tail_bytes", ctypes.c_int64), ("tail_fallbacks", ctypes.c_int32)]
 
 
 class CParams(ctypes.Structure):
@@ -69,7 +69,7 @@ class CParams(ctypes.Structure):
                 ("split_chunks", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("rounds_per_poll", ctypes.c_int32), ("tail_threshold", ctypes.c_int32),
                 ("max_workgroups", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("engine", ctypes.c_int32)]
+                ("engine", ctypes.c_int32), ("tail_checkin_us", ctypes.c_int32)]
 
 
 class CJob(ctypes.Structure):
@@ -105,6 +105,7 @@ class Stats:
     tail_rounds: int = 0
     tail_kernel_ns: int = 0
     tail_bytes: int = 0
+    tail_fallbacks: int = 0
     converged: bool = True
     worklist: list = field(default_factory=list)
 
@@ -123,6 +124,7 @@ class Params:
     max_workgroups: int = 0
     flags: int = 0
     engine: int = 0
+    tail_checkin_us: int = 0
 
     def to_c(self) -> CParams:
         p = CParams()
@@ -137,6 +139,7 @@ class Params:
         p.max_workgroups = self.max_workgroups
         p.flags = self.flags
         p.engine = self.engine
+        p.tail_checkin_us = self.tail_checkin_us
         return p
 
 

@@ -158,6 +158,7 @@ void default_params(int mode, color_params* p) {
   p->tail_threshold = 0;
   p->max_workgroups = resident_round_blocks(mode);
   p->flags = 0;
+  p->tail_checkin_us = kTailCheckinDefaultUs;
 }
 
 int merge_params(int mode, const color_params* user, color_params* out) {
@@ -183,6 +184,8 @@ int merge_params(int mode, const color_params* user, color_params* out) {
   if (user->tail_threshold > 0) out->tail_threshold = user->tail_threshold;
   if (user->engine < 0 || user->engine > COLOR_ENGINE_INCREMENTAL) return COLOR_EINVAL;
   out->engine = user->engine;
+  if (user->tail_checkin_us < -1) return COLOR_EINVAL;
+  if (user->tail_checkin_us != 0) out->tail_checkin_us = user->tail_checkin_us;
   out->flags = user->flags;
   return COLOR_OK;
 }
@@ -434,6 +437,7 @@ int finish_call(Call& c, color_stats* stats, int32_t num_colors_hint, int rc) {
     stats->tail_rounds = c.tail_rounds;
     stats->tail_kernel_ns = 0;
     stats->tail_bytes = static_cast<int64_t>(c.H->visits[6] + c.H->visits[7]);
+    stats->tail_fallbacks = c.tail_fallbacks;
     stats->list_visits = static_cast<int64_t>(c.H->visits[2]);
     stats->color_bytes = static_cast<int64_t>(c.H->visits[3]);
     stats->detect_bytes = static_cast<int64_t>(c.H->visits[4]);
@@ -684,7 +688,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
       const int cap = max_rounds > 0 ? max_rounds : INT_MAX;
       if (c.timing && c.record_event(2)) return COLOR_EHIP;
       if (launch_inc_tail(k, set, IL, local + 1, cap, S->bar, &S->tail_err, &S->tail_left,
-                          static_cast<int>(std::max<int64_t>(1, g)), c.st)) {
+                          static_cast<int>(std::max<int64_t>(1, g)), c.P.tail_checkin_us, c.st)) {
         if (c.timing && c.record_event(-1)) return COLOR_EHIP;
         c.launches += 1;
         if (hipMemcpyAsync(&H->tail_err, &S->tail_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c.st) !=
@@ -693,7 +697,14 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
                 hipSuccess)
           return COLOR_EHIP;
         if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
-        if (H->tail_err) return COLOR_EHIP;  // a grid barrier gave up: the outputs are not valid
+        if (H->tail_err == kErrTailCheckin) {
+          // its workgroups were not all resident: it ran nothing, so the
+          // rounds go on from the same state as per-round launches
+          c.tail_fallbacks += 1;
+          tail_on = false;
+          continue;
+        }
+        if (H->tail_err) return kRcRetryNoTail;  // a grid barrier gave up: the outputs are not valid
         c.tail_rounds = std::max(0, H->rounds_done - local);
         return H->tail_left ? COLOR_ENOCONVERGE : COLOR_OK;
       }
@@ -789,7 +800,7 @@ int validate_job(const color_job& j, void* stream) {
 // scratch array); the call then runs the pull engine without split vertices,
 // whose buffers that workspace holds, and allocates nothing.
 template <int MODE>
-static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32_t* ci, const int32_t* rp2,
+static int color_graph_once(int32_t n, int32_t n_rows, const int32_t* rp, const int32_t* ci, const int32_t* rp2,
                        const int32_t* ci2, uint32_t seed, const uint32_t* prio, const int32_t* init,
                        int32_t* colors, color_stats* stats, const color_params* params, void* stream,
                        Workspace* fixed_ws = nullptr) {
@@ -859,6 +870,25 @@ static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32
   const int rc = run_phase<MODE>(c, g, k, L, rb, known, 0, c.P.max_rounds);
   if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
   return finish_call(c, stats, -1, rc);
+}
+
+// A call whose tail kernel's grid barrier gave up starts over with
+// per-round launches only: the setup re-initializes every array, so the
+// repeated call computes the same coloring.
+template <int MODE>
+static int color_graph(int32_t n, int32_t n_rows, const int32_t* rp, const int32_t* ci, const int32_t* rp2,
+                       const int32_t* ci2, uint32_t seed, const uint32_t* prio, const int32_t* init,
+                       int32_t* colors, color_stats* stats, const color_params* params, void* stream,
+                       Workspace* fixed_ws = nullptr) {
+  const int rc = color_graph_once<MODE>(n, n_rows, rp, ci, rp2, ci2, seed, prio, init, colors, stats, params,
+                                        stream, fixed_ws);
+  if (rc != kRcRetryNoTail) return rc;
+  color_params p;
+  if (params) p = *params;
+  else std::memset(&p, 0, sizeof(p));
+  p.flags |= COLOR_FLAG_NO_TAIL;
+  return color_graph_once<MODE>(n, n_rows, rp, ci, rp2, ci2, seed, prio, init, colors, stats, &p, stream,
+                                fixed_ws);
 }
 
 int color_d1_fixed(Workspace* ws, int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t seed,

@@ -90,10 +90,15 @@ struct Call {
   std::vector<int> event_kind;  // per event pair start index: 0 color, 1 detect, 2 tail, -1 none
   int color_launches = 0, detect_launches = 0;
   int tail_rounds = 0;  // rounds run by the incremental engine's tail kernel
+  int tail_fallbacks = 0;  // tail launches that found their workgroups not all resident
   bool user_bins = false;  // the caller set degree-bin bounds
   int engine = 1;
   int record_event(int kind_of_next);  // records the next pool event on st
 };
+
+// run_incremental: a grid barrier of the tail kernel gave up; the call is
+// repeated with per-round launches only (never returned to callers)
+constexpr int kRcRetryNoTail = -1000;
 
 void default_params(int mode, color_params* p);
 int degree_rank(Call& c, int32_t m, const int32_t* deg_ptr, int32_t n_rows, const int32_t* extra_deg, KeySource& k);

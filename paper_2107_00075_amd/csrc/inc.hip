@@ -692,19 +692,52 @@ __device__ __forceinline__ bool grid_sync(uint32_t* bar, int32_t* err, uint64_t 
   return *s_ok != 0;
 }
 
+// Entry check-in of the tail kernel.  Its grid barriers need every workgroup
+// resident at once, which the cooperative launch provides only while no
+// other kernel fills the device.  So before writing anything, every
+// workgroup arrives and waits until either all gridDim.x workgroups have
+// arrived (then all are resident: none leaves before the decision) or
+// `ticks` have passed.  The decision is one compare-and-swap on a state word
+// (the last arrival sets GO, a workgroup whose wait ran out sets ABORT), so
+// every workgroup takes the same one, including those that start after it.
+// On ABORT the launch changes nothing and the host runs the rounds as
+// per-round launches.
+constexpr uint32_t kCheckinGo = 1u, kCheckinAbort = 2u;
+
+__device__ __forceinline__ bool tail_checkin(uint32_t* bar, int32_t* err, uint64_t ticks, int32_t* s_ok) {
+  if (threadIdx.x == 0) {
+    uint32_t* state = &bar[kBarState];
+    if (atomicAdd(&bar[kBarCheckin], 1u) + 1u == gridDim.x) (void)atomicCAS(state, 0u, kCheckinGo);
+    const uint64_t t0 = static_cast<uint64_t>(wall_clock64());
+    uint32_t s;
+    while ((s = atomic_load_u32(state)) == 0u) {
+      if (static_cast<uint64_t>(wall_clock64()) - t0 >= ticks) {
+        if (atomicCAS(state, 0u, kCheckinAbort) == 0u) atomicOr(err, kErrTailCheckin);
+      } else {
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    *s_ok = s == kCheckinGo ? 1 : 0;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
 // Rounds round0 .. round_cap of one call: color phase, barrier, detect phase,
 // barrier, stop when the next worklist is empty.  set.b[0] holds the buffers
 // of round 1, set.b[1] and set.b[2] those of later odd and even rounds.
 // *left receives 1 if the cap was reached with vertices left.
 __global__ __launch_bounds__(kBlock) void inc_tail_kernel(KeySource k, IncRoundSet set, BinLayout L, int round0,
                                                           int round_cap, uint32_t* bar, int32_t* err,
-                                                          int32_t* left, uint64_t deadline) {
+                                                          int32_t* left, uint64_t deadline,
+                                                          uint64_t checkin_ticks) {
   __shared__ union {
     IncColorShared c;
     IncDetectShared d;
   } sh;
   __shared__ int32_t s_ok;
   __shared__ IncPre s_pre;  // next round's map and largest color, read once per round
+  if (!tail_checkin(bar, err, checkin_ticks, &s_ok)) return;
   for (int r = round0; r <= round_cap; ++r) {
     const IncBufs& b = r == 1 ? set.b[0] : set.b[1 + ((r - 1) & 1)];
     const bool first = r == round0;
@@ -738,21 +771,22 @@ int tail_blocks_resident() {
 }
 
 bool launch_inc_tail(const KeySource& k, const IncRoundSet& set, const BinLayout& L, int round0, int round_cap,
-                    uint32_t* bar, int32_t* err, int32_t* left, int grid, hipStream_t st) {
-  static uint64_t deadline = 0;
-  if (deadline == 0) {
-    int dev = 0, khz = 0;
+                    uint32_t* bar, int32_t* err, int32_t* left, int grid, int32_t checkin_us, hipStream_t st) {
+  static uint64_t khz = 0;
+  if (khz == 0) {
+    int dev = 0, rate = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
-      khz = 100000;
-    deadline = static_cast<uint64_t>(khz) * 1000ull * kTailBarrierSeconds;
+        hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate <= 0)
+      rate = 100000;
+    khz = static_cast<uint64_t>(rate);
   }
   KeySource kk = k;
   IncRoundSet ss = set;
   BinLayout ll = L;
   int r0 = round0, rc = round_cap;
-  uint64_t dl = deadline;
-  void* args[] = {&kk, &ss, &ll, &r0, &rc, &bar, &err, &left, &dl};
+  uint64_t dl = khz * 1000ull * kTailBarrierSeconds;
+  uint64_t ci = checkin_us < 0 ? 0ull : khz * static_cast<uint64_t>(checkin_us) / 1000ull;
+  void* args[] = {&kk, &ss, &ll, &r0, &rc, &bar, &err, &left, &dl, &ci};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(inc_tail_kernel), dim3(grid), dim3(kBlock), args, 0,
                                     st) == hipSuccess;
 }

@@ -60,19 +60,27 @@ struct IncRoundSet {
 };
 
 constexpr int32_t kErrTailBarrier = 0x100;  // error bit: a tail-kernel grid barrier gave up
-constexpr int kTailBarrierSeconds = 30;
+constexpr int32_t kErrTailCheckin = 0x200;  // the tail kernel's workgroups were not all resident: none ran a round
+constexpr int kTailBarrierSeconds = 30;     // a grid barrier of the tail kernel gives up after this long
+constexpr int32_t kTailCheckinDefaultUs = 2000;  // how long the tail's workgroups wait for each other at entry
 // tail-kernel barrier words (32 apart: one cache line each): top arrivals at
-// 0, the generation at kBarGen, group g's arrivals at kBarGroup + 32 g
+// 0, the generation at kBarGen, group g's arrivals at kBarGroup + 32 g, the
+// entry check-in's arrivals at kBarCheckin and its decision at kBarState
 constexpr int kBarGen = 32;
 constexpr int kBarGroup = 64;
-constexpr int kBarWords = kBarGroup + 32 * 8;     // a grid barrier of the tail kernel gives up after this long
+constexpr int kBarCheckin = kBarGroup + 32 * 8;
+constexpr int kBarState = kBarCheckin + 32;
+constexpr int kBarWords = kBarState + 32;
 constexpr int32_t kTailDefault = 32768;     // default worklist size at which the tail kernel takes over
 
 void launch_inc_color(const IncBufs& b, const BinLayout& L, int round, int grid, hipStream_t st);
 // All remaining rounds in one cooperative launch (grid <= tail_blocks_resident());
 // false if the runtime refused the launch.
+// checkin_us: how long the workgroups wait for each other at entry (< 0: not
+// at all); if they are not all resident by then, none runs a round and *err
+// receives kErrTailCheckin.
 bool launch_inc_tail(const KeySource& k, const IncRoundSet& set, const BinLayout& L, int round0, int round_cap,
-                    uint32_t* bar, int32_t* err, int32_t* left, int grid, hipStream_t st);
+                    uint32_t* bar, int32_t* err, int32_t* left, int grid, int32_t checkin_us, hipStream_t st);
 // Workgroups of the tail kernel that fit on the device at once (-1: unknown).
 int tail_blocks_resident();
 void launch_inc_detect(const KeySource& k, const IncBufs& b, const BinLayout& L, int round, int grid,

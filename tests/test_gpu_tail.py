@@ -138,3 +138,65 @@ def test_tail_repeated_calls_reuse_barrier_state(gc):
         got, st = run(gc, "d1", g, i, gc.Params(engine=2))
         assert np.array_equal(got, ref.colors), f"graph {i}"
         assert st.tail_rounds >= 1
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_tail_checkin_gives_up_and_rounds_continue(gc, name):
+    """tail_checkin_us = -1: the tail kernel's workgroups never wait for each
+    other, so every tail launch gives up at its entry check-in (forced from
+    the host: every kernel still exits normally), changes nothing, and the
+    remaining rounds run as per-round launches with the same result."""
+    kind, make = CASES[name]
+    g = make()
+    ref = oracle_of(kind, g, 4)
+    c, st = run(gc, kind, g, 4, gc.Params(engine=gc.ENGINE_INCREMENTAL, tail_checkin_us=-1))
+    assert st.tail_fallbacks == 1 and st.tail_rounds == 0
+    assert np.array_equal(c, ref.colors)
+    assert st.rounds == ref.rounds and st.worklist == ref.worklist[:len(st.worklist)]
+    assert st.vertex_visits == ref.vertex_visits and st.edge_visits == ref.edge_visits
+    c2, st2 = run(gc, kind, g, 4, gc.Params(engine=gc.ENGINE_INCREMENTAL))
+    assert st2.tail_fallbacks == 0 and st2.tail_rounds > 0
+    assert np.array_equal(c2, ref.colors)
+
+
+def test_tail_next_to_a_device_filling_batch_launch(gc):
+    """A single-graph call with the tail kernel on one stream while another
+    host thread runs the batched engine's persistent launch on another stream.
+    Whether the tail's workgroups find each other resident or fall back to
+    per-round launches depends on timing; either way both results equal the
+    oracle."""
+    import threading
+    jobs_graphs = [gg.erdos_renyi(20000 + 1000 * i, 24, 10 + i) for i in range(24)]
+    jobs = [dict(kind=gc.KIND_D1, row_ptr=dev(h.row_ptr), col_idx=dev(h.col), seed=1) for h in jobs_graphs]
+    g = gg.rmat(17, 16, seed=5)
+    rp, ci = dev(g.row_ptr), dev(g.col)
+    torch.cuda.synchronize()
+    out = {}
+
+    def batch():
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            cols, _ = gc.color_batch(jobs, stream=s)
+            s.synchronize()
+            out["batch"] = [c.cpu().numpy() for c in cols]
+
+    def single():
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            c, st = gc.color_d1(rp, ci, seed=3, stream=s, params=gc.Params(engine=gc.ENGINE_INCREMENTAL),
+                                trace_cap=4096)
+            s.synchronize()
+            out["single"] = (c.cpu().numpy(), st)
+
+    threads = [threading.Thread(target=batch), threading.Thread(target=single)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=300)
+    assert "batch" in out and "single" in out
+    ref = oracle.color_d1(g, seed=3)
+    c, st = out["single"]
+    assert np.array_equal(c, ref.colors) and st.rounds == ref.rounds
+    assert st.tail_rounds > 0 or st.tail_fallbacks == 1
+    for h, col in zip(jobs_graphs, out["batch"]):
+        assert np.array_equal(col, oracle.color_d1(h, seed=1).colors)
