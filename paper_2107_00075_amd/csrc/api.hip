@@ -796,9 +796,10 @@ int validate_job(const color_job& j, void* stream) {
   return validate_graph<kPD2>(c, j.n, j.n_rows, j.col_ptr, j.row_idx, j.row_ptr, j.col_idx);
 }
 
-// fixed_ws: the no-allocation entry point's workspace (regions of its static
-// scratch array); the call then runs the pull engine without split vertices,
-// whose buffers that workspace holds, and allocates nothing.
+// fixed_ws: a workspace of fixed buffers (the no-allocation entry point's
+// static scratch array, the server's heavy-lane regions of its arena): the
+// call allocates nothing, and a buffer asked for more than it holds fails
+// the call with COLOR_EOVERFLOW.
 template <int MODE>
 static int color_graph_once(int32_t n, int32_t n_rows, const int32_t* rp, const int32_t* ci, const int32_t* rp2,
                        const int32_t* ci2, uint32_t seed, const uint32_t* prio, const int32_t* init,
@@ -811,10 +812,6 @@ static int color_graph_once(int32_t n, int32_t n_rows, const int32_t* rp, const 
   Call c;
   int e = begin_call(c, MODE, params, stats, stream, n, n, fixed_ws);
   if (e) return e;
-  if (fixed_ws) {
-    c.P.engine = COLOR_ENGINE_PULL;
-    c.P.bin_hi[3] = INT_MAX;
-  }
   std::unique_lock<std::mutex> lk(c.ws->mu);
   if (n == 0) return finish_call(c, stats, 0, COLOR_OK);
   if (c.P.flags & COLOR_FLAG_VALIDATE) {
@@ -896,6 +893,105 @@ int color_d1_fixed(Workspace* ws, int32_t n, const int32_t* row_ptr, const int32
                    const color_params* params, void* stream) {
   return color_graph<kD1>(n, n, row_ptr, col_idx, row_ptr, col_idx, seed, prio, init_colors, colors, stats, params,
                           stream, ws);
+}
+
+int color_d2_fixed(Workspace* ws, int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t seed,
+                   int32_t* colors, color_stats* stats, const color_params* params, void* stream) {
+  return color_graph<kD2>(n, n, row_ptr, col_idx, row_ptr, col_idx, seed, nullptr, nullptr, colors, stats, params,
+                          stream, ws);
+}
+
+int color_pd2_fixed(Workspace* ws, int32_t n_rows, int32_t n_cols, const int32_t* row_ptr, const int32_t* col_idx,
+                    const int32_t* col_ptr, const int32_t* row_idx, uint32_t seed, int32_t* col_colors,
+                    color_stats* stats, const color_params* params, void* stream) {
+  if (n_cols > 0 && n_rows > 0 && (!row_ptr || !col_idx)) return COLOR_EINVAL;
+  return color_graph<kPD2>(n_cols, n_rows, col_ptr, row_idx, row_ptr, col_idx, seed, nullptr, nullptr, col_colors,
+                           stats, params, stream, ws);
+}
+
+// Buffer sizes of one D2/PD2 call on the incremental engine, computed on the
+// host from the graph the way the engine sizes them on the device (list
+// lengths from the hop-1 and hop-2 rows, bitset words, worklists, list-
+// building bitmaps, scan storage), with no trace and no degree key.
+size_t plan_incremental(int kind, int32_t n, const int32_t* rp1, const int32_t* ci1, const int32_t* rp2,
+                        IncPlan* p) {
+  std::memset(p, 0, sizeof(*p));
+  const size_t nn = static_cast<size_t>(std::max(n, 1));
+  const size_t n1 = static_cast<size_t>(n) + 1;
+  int64_t total = 0, fw = 0, nd = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    const int64_t d1 = rp1[v + 1] - rp1[v];
+    int64_t work = 0;
+    for (int32_t q = rp1[v]; q < rp1[v + 1]; ++q) work += 1 + (rp2[ci1[q] + 1] - rp2[ci1[q]]);
+    const int64_t len = std::max<int64_t>(0, work - (kind == COLOR_KIND_PD2 ? 2 : 1) * d1);
+    total += len;
+    fw += std::min<int64_t>(len, n) / 32 + 1;
+    if (d1 > kSetupHeavy) ++nd;
+  }
+  const size_t entries = static_cast<size_t>(std::max<int64_t>(1, std::min<int64_t>(total, INT_MAX)));
+  const size_t words = static_cast<size_t>(n) / 32 + 1;
+  const size_t bm = sizeof(uint32_t) * words * static_cast<size_t>(dedup_grid(static_cast<int32_t>(words)));
+  size_t sets = 0;
+  if (nd > 0 && nd * static_cast<int64_t>(words) <= kSetsMaxWords)
+    sets = sizeof(uint32_t) * words *
+           static_cast<size_t>(std::max<int64_t>(1, std::min<int64_t>(nd, kSetsBatchWords / static_cast<int64_t>(words))));
+  size_t scan = 0;
+  if (exclusive_scan_i32(nullptr, nullptr, n + 1, nullptr, &scan, nullptr)) return 0;
+  p->small = sizeof(Scalars);
+  p->T = p->work = p->wl0 = p->wl1 = p->deferred = p->deferred_done = 4 * nn;
+  p->bin = nn;
+  p->trace = 4;
+  p->deferred_work = 8 * nn;
+  p->inc_len = p->inc_words = p->inc_fwoff = p->inc_aoff = p->inc_L0 = p->inc_Ll = 4 * n1;
+  p->inc_F = 4 * static_cast<size_t>(std::max<int64_t>(fw, 1));
+  p->inc_B0 = p->inc_B1 = 4 * entries;
+  p->inc_bm = std::max(bm, sets);
+  p->inc_wl0 = p->inc_wl1 = 4 * 4 * nn;  // bin regions: at most 4n entries
+  p->scan_tmp = std::max<size_t>(scan, 1);
+  size_t t = 0;
+  for (size_t b : {p->small, p->T, p->work, p->bin, p->wl0, p->wl1, p->trace, p->deferred, p->deferred_work,
+                   p->deferred_done, p->inc_len, p->inc_words, p->inc_fwoff, p->inc_aoff, p->inc_L0, p->inc_Ll,
+                   p->inc_F, p->inc_B0, p->inc_B1, p->inc_bm, p->inc_wl0, p->inc_wl1, p->scan_tmp})
+    t += (b + 255) / 256 * 256;
+  return t;
+}
+
+// Points the buffers of w into [base, base + plan total), every buffer fixed.
+void carve_workspace(Workspace* w, char* base, const IncPlan& p) {
+  for (DevBuf* b : w->buffers()) {
+    b->p = nullptr;
+    b->bytes = 0;
+    b->fixed = true;
+  }
+  size_t off = 0;
+  auto take = [&](DevBuf& b, size_t bytes) {
+    b.p = base + off;
+    b.bytes = bytes;
+    off += (bytes + 255) / 256 * 256;
+  };
+  take(w->small, p.small);
+  take(w->T, p.T);
+  take(w->work, p.work);
+  take(w->bin, p.bin);
+  take(w->wl0, p.wl0);
+  take(w->wl1, p.wl1);
+  take(w->trace, p.trace);
+  take(w->deferred, p.deferred);
+  take(w->deferred_work, p.deferred_work);
+  take(w->deferred_done, p.deferred_done);
+  take(w->inc_len, p.inc_len);
+  take(w->inc_words, p.inc_words);
+  take(w->inc_fwoff, p.inc_fwoff);
+  take(w->inc_aoff, p.inc_aoff);
+  take(w->inc_L0, p.inc_L0);
+  take(w->inc_Ll, p.inc_Ll);
+  take(w->inc_F, p.inc_F);
+  take(w->inc_B0, p.inc_B0);
+  take(w->inc_B1, p.inc_B1);
+  take(w->inc_bm, p.inc_bm);
+  take(w->inc_wl0, p.inc_wl0);
+  take(w->inc_wl1, p.inc_wl1);
+  take(w->scan_tmp, p.scan_tmp);
 }
 
 }  // namespace gcol

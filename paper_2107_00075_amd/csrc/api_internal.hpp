@@ -116,6 +116,26 @@ int color_d1_fixed(Workspace* ws, int32_t n, const int32_t* row_ptr, const int32
                    const uint32_t* prio, const int32_t* init_colors, int32_t* colors, color_stats* stats,
                    const color_params* params, void* stream);
 
+int color_d2_fixed(Workspace* ws, int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t seed,
+                   int32_t* colors, color_stats* stats, const color_params* params, void* stream);
+int color_pd2_fixed(Workspace* ws, int32_t n_rows, int32_t n_cols, const int32_t* row_ptr, const int32_t* col_idx,
+                    const int32_t* col_ptr, const int32_t* row_idx, uint32_t seed, int32_t* col_colors,
+                    color_stats* stats, const color_params* params, void* stream);
+
+// Device bytes of each workspace buffer one D2/PD2 call on the incremental
+// engine uses (no trace, no degree key).
+struct IncPlan {
+  size_t small, T, work, bin, wl0, wl1, trace, deferred, deferred_work, deferred_done;
+  size_t inc_len, inc_words, inc_fwoff, inc_aoff, inc_L0, inc_Ll, inc_F, inc_B0, inc_B1, inc_bm, inc_wl0, inc_wl1,
+      scan_tmp;
+};
+// kind COLOR_KIND_D2: (rp1, ci1) = (rp2, .) = the adjacency; COLOR_KIND_PD2:
+// (rp1, ci1) = the CSC, rp2 = the CSR row offsets.  HOST arrays.  Returns
+// the total bytes (each buffer 256-byte aligned), 0 on error.
+size_t plan_incremental(int kind, int32_t n, const int32_t* rp1, const int32_t* ci1, const int32_t* rp2,
+                        IncPlan* p);
+void carve_workspace(Workspace* w, char* base, const IncPlan& p);
+
 template <int MODE>
 int setup_bins(Call& c, const GraphView& g, const int32_t* init, int32_t* C, int32_t n_total, BinLayout& L,
                RoundBufs& rb, int32_t known[kBins]);

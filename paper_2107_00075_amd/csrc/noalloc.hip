@@ -12,6 +12,7 @@
 // cleared by a fill kernel at the start of every call; the other regions are
 // fully written before they are read.
 #include <climits>
+#include <cstring>
 #include <mutex>
 #include <new>
 
@@ -99,5 +100,12 @@ extern "C" int color_d1_noalloc(int32_t n, const int32_t* row_ptr, const int32_t
   Workspace* w = nullptr;
   const int e = device_workspace(&w);
   if (e) return e;
-  return color_d1_fixed(w, n, row_ptr, col_idx, seed, prio, init_colors, colors, stats, params, stream);
+  // the pull engine with workgroup-wide heavy vertices: the layout whose
+  // buffers the scratch array holds
+  color_params p;
+  if (params) p = *params;
+  else std::memset(&p, 0, sizeof(p));
+  p.engine = COLOR_ENGINE_PULL;
+  p.bin_hi[3] = INT_MAX;
+  return color_d1_fixed(w, n, row_ptr, col_idx, seed, prio, init_colors, colors, stats, &p, stream);
 }

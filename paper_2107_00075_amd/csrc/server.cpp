@@ -99,6 +99,8 @@ struct ServedJob {
   int32_t slot = -1;
   hipEvent_t ev = nullptr;  // copy in / copy out
   bool heavy = false;       // long two-hop walks: the single-graph engine's lane
+  IncPlan plan{};           // heavy: the incremental engine's buffers, carved from the job's arena region
+  size_t plan_bytes = 0;
 };
 
 }  // namespace
@@ -133,19 +135,24 @@ struct color_server {
   std::condition_variable heavy_cv;  // wakes the heavy lane
   std::condition_variable done_cv;   // a heavy job finished
   hipStream_t heavy_stream = nullptr;
+  Workspace heavy_ws;  // fixed buffers: regions of the running heavy job's arena space
   bool stopping = false;
 };
 
 namespace {
 
-size_t job_footprint(const color_job& j, int32_t nnz, int32_t n_csr_rows) {
+// Arena bytes of a job: its CSR (+ CSC), its colors, and its workspace: the
+// batched engine's 16 bytes per vertex, or for a heavy-lane job every buffer
+// of the single-graph incremental engine (plan_bytes), so that the server's
+// device memory stays within its budget.
+size_t job_footprint(const color_job& j, int32_t nnz, int32_t n_csr_rows, bool heavy, size_t plan_bytes) {
   size_t b = align_up(sizeof(int32_t) * (static_cast<size_t>(n_csr_rows) + 1)) +
              align_up(sizeof(int32_t) * static_cast<size_t>(nnz));
   if (j.kind == COLOR_KIND_PD2)
     b += align_up(sizeof(int32_t) * (static_cast<size_t>(j.n) + 1)) +
          align_up(sizeof(int32_t) * static_cast<size_t>(nnz));
   b += align_up(sizeof(int32_t) * static_cast<size_t>(std::max(j.n, 1)));
-  b += sizeof(int32_t) * 4 * static_cast<size_t>(batch_stride(j.n));
+  b += heavy ? plan_bytes : sizeof(int32_t) * 4 * static_cast<size_t>(batch_stride(j.n));
   return b;
 }
 
@@ -387,17 +394,20 @@ int run_heavy(color_server* s, ServedJob& J) {
     if (!cp || (J.nnz > 0 && !ri)) return COLOR_EHIP;
   }
   int32_t* colors = reinterpret_cast<int32_t*>(p);
+  p += align_up(sizeof(int32_t) * static_cast<size_t>(std::max(d.n, 1)));
+  // the engine's buffers: the rest of the job's arena region
+  carve_workspace(&s->heavy_ws, p, J.plan);
   // Per-round launches only: the light lane's persistent kernel fills the
-  // device at the same time, so the workgroups of a cooperative tail launch
-  // need not all be resident, and its grid barriers could wait on workgroups
-  // that only start when an epoch ends (up to the barrier's deadline).
+  // device at the same time, so a cooperative tail launch would mostly find
+  // its workgroups not all resident and fall back after its check-in wait.
   color_params prm;
   std::memset(&prm, 0, sizeof(prm));
   prm.flags = COLOR_FLAG_NO_TAIL;
+  prm.engine = COLOR_ENGINE_INCREMENTAL;
   int rc = d.kind == COLOR_KIND_D2
-               ? color_d2(d.n, rp, ci, d.seed, nullptr, nullptr, colors, &J.stats, &prm, s->heavy_stream)
-               : color_pd2(J.n_csr_rows, d.n, rp, ci, cp, ri, d.seed, nullptr, nullptr, colors, &J.stats, &prm,
-                           s->heavy_stream);
+               ? color_d2_fixed(&s->heavy_ws, d.n, rp, ci, d.seed, colors, &J.stats, &prm, s->heavy_stream)
+               : color_pd2_fixed(&s->heavy_ws, J.n_csr_rows, d.n, rp, ci, cp, ri, d.seed, colors, &J.stats, &prm,
+                                 s->heavy_stream);
   if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
   J.rc = rc;
   J.colors.resize(static_cast<size_t>(d.n));
@@ -438,7 +448,7 @@ void heavy_lane(color_server* s) {
       (void)hipHostFree(J.h_in);
       J.h_in = nullptr;
     }
-    if (e) s->error = e;
+    if (e) J.rc = e;  // this job's failure, reported by its poll; other jobs go on
     J.state = JobState::Done;
     s->done_cv.notify_all();
   }
@@ -496,7 +506,9 @@ color_server* color_server_create(size_t hbm_budget_bytes, int32_t max_slots, in
       hipStreamCreateWithFlags(&s->heavy_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&s->epoch_done, hipEventDisableTiming) != hipSuccess)
     return fail(COLOR_EHIP);
-  if (hipMalloc(reinterpret_cast<void**>(&s->arena_base), hbm_budget_bytes) != hipSuccess ||
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->heavy_ws.host), sizeof(Scalars), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&s->arena_base), hbm_budget_bytes) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&s->d_jobs), sizeof(BatchJob) * ns) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&s->d_words), sizeof(uint64_t) * ns) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&s->d_ctr), kAlign) != hipSuccess ||
@@ -553,7 +565,14 @@ int color_server_submit(color_server* s, const color_host_job* job, uint64_t* jo
   ServedJob J;
   J.nnz = nnz;
   J.n_csr_rows = n_csr_rows;
-  J.footprint = job_footprint(d, nnz, n_csr_rows);
+  J.heavy = job_walk(d, nnz) >= kLongWalk;
+  if (J.heavy) {
+    J.plan_bytes = d.kind == COLOR_KIND_D2
+                       ? plan_incremental(d.kind, d.n, job->row_ptr, job->col_idx, job->row_ptr, &J.plan)
+                       : plan_incremental(d.kind, d.n, job->col_ptr, job->row_idx, job->row_ptr, &J.plan);
+    if (J.plan_bytes == 0) return COLOR_EHIP;
+  }
+  J.footprint = job_footprint(d, nnz, n_csr_rows, J.heavy, J.plan_bytes);
   if (J.footprint > s->arena.total()) return COLOR_E2BIG;
   J.h_in_entries = static_cast<size_t>(n_csr_rows) + 1 + static_cast<size_t>(nnz);
   if (d.kind == COLOR_KIND_PD2) J.h_in_entries += static_cast<size_t>(d.n) + 1 + static_cast<size_t>(nnz);
@@ -580,7 +599,6 @@ int color_server_submit(color_server* s, const color_host_job* job, uint64_t* jo
     return COLOR_EHIP;
   }
   J.desc = d;
-  J.heavy = job_walk(d, nnz) >= kLongWalk;
   const uint64_t id = s->next_id++;
   s->jobs.emplace(id, J);
   if (job_id) *job_id = id;

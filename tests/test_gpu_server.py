@@ -71,11 +71,19 @@ def walk(s):
 
 
 def footprint(s):
+    """An upper bound of the server's arena bytes for the job: CSR (+CSC),
+    colors, and the batched engine's 16 bytes per vertex, or for a heavy-lane
+    job the single-graph incremental engine's buffers (two list arrays of
+    the two-hop walk, bitsets, worklists and per-vertex arrays)."""
     g = s.graph
     nnz = g.nnz
     b = 4 * (g.n + 1) + 4 * nnz + 4 * g.n + 16 * g.n
     if s.kind == 3:
         b += 4 * (g.n + 1) + 4 * nnz
+    if s.kind != 1 and walk(s) >= 128:
+        deg = np.diff(g.row_ptr).astype(np.int64)
+        walk_entries = int((deg * deg).sum()) + nnz
+        b += 9 * walk_entries + 200 * g.n + (1 << 20)
     return b
 
 
@@ -145,9 +153,8 @@ def test_server_errors(gc):
         with pytest.raises(gc.ColorError) as ei:
             srv.submit(1, big.row_ptr, big.col)
         assert ei.value.code == gc.COLOR_E2BIG
+        srv._keep[12345] = 1  # an id the server never issued
         with pytest.raises(gc.ColorError) as ei:
-            gc._binding.lib().color_server_poll  # exists
-            srv._keep[12345] = 1
             srv.poll(12345)
         assert ei.value.code == gc.COLOR_EINVAL
         # a job of 0 vertices completes with an empty coloring
@@ -155,5 +162,33 @@ def test_server_errors(gc):
         srv.drain()
         colors, st = srv.poll(jid)
         assert colors.size == 0 and st.rounds == 0
+    finally:
+        srv.close()
+
+
+def test_server_heavy_job_within_budget(gc):
+    """A heavy-lane job (dense D2: long two-hop walks) keeps the single-graph
+    engine's lists inside the server's arena: a budget that fits its CSR but
+    not its lists refuses it at submit (COLOR_E2BIG); a budget that fits both
+    serves it, with the coloring of the plain call."""
+    g = gg.erdos_renyi(3000, 48, 7)
+    spec = gg.JobSpec(kind=2, family="er", graph=g, pattern=None, seed=3)
+    assert walk(spec) >= 128
+    small = 4 * (g.n + 1) + 4 * g.nnz + 4 * g.n + 16 * g.n + (1 << 16)
+    srv = gc.ColorServer(small, max_slots=4)
+    try:
+        with pytest.raises(gc.ColorError) as ei:
+            srv.submit(2, g.row_ptr, g.col, seed=3)
+        assert ei.value.code == gc.COLOR_E2BIG
+    finally:
+        srv.close()
+    srv = gc.ColorServer(footprint(spec) + (1 << 20), max_slots=4)
+    try:
+        jid, _ = srv.submit(2, g.row_ptr, g.col, seed=3)
+        srv.drain()
+        colors, st = srv.poll(jid)
+        assert st.engine == gc.ENGINE_INCREMENTAL
+        ref = oracle.color_d2(g, seed=3)
+        assert np.array_equal(colors, ref.colors) and st.rounds == ref.rounds
     finally:
         srv.close()
