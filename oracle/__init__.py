@@ -193,3 +193,94 @@ def serial_greedy(g, order) -> np.ndarray:
     out = np.zeros(g.n, dtype=np.int32)
     lib().orc_serial_greedy(g.n, _ptr(rp), _ptr(col), _ptr(o), _ptr(out))
     return out
+
+
+@dataclass
+class DistResult:
+    colors: list              # per rank: its owned vertices' colors (local order)
+    detects: int              # conflict detections run (the last one found none)
+    iterations: int           # Algorithm 2's while-loop iterations (recolorings)
+    conflicts: list           # per detection: conflicts summed over the ranks (the Allreduce)
+    exchanged: list           # per exchange: ghost copies whose color was sent
+    rounds: int               # on-node rounds summed over ranks and steps
+
+
+def _exchange_map(locals_):
+    """For every rank's ghosts: the rank owning each ghost and its index among
+    that rank's owned vertices (found by global id)."""
+    gids = np.concatenate([np.asarray(lg.gid[:lg.n_owned], dtype=np.int64) for lg in locals_])
+    part = np.concatenate([np.full(lg.n_owned, p, dtype=np.int64) for p, lg in enumerate(locals_)])
+    index = np.concatenate([np.arange(lg.n_owned, dtype=np.int64) for lg in locals_])
+    order = np.argsort(gids, kind="stable")
+    sg = gids[order]
+    maps = []
+    for lg in locals_:
+        g = np.asarray(lg.gid[lg.n_owned:], dtype=np.int64)
+        pos = np.searchsorted(sg, g)
+        if g.size and (np.any(pos >= sg.size) or np.any(sg[np.minimum(pos, sg.size - 1)] != g)):
+            raise ValueError("a ghost is owned by no rank")
+        maps.append((part[order[pos]], index[order[pos]]))
+    return maps
+
+
+def color_d1_distributed(locals_, seed: int = 1, recolor_degrees: bool = False, ghost_degrees=None,
+                         max_iterations: int = 100000) -> DistResult:
+    """Algorithm 2 (Section 3), its ranks emulated one after another.
+
+    Every rank first colors its owned vertices without ghost information (its
+    ghosts' colors are not known yet: 0).  Then, until the conflicts summed
+    over all ranks are zero: the ranks send their owned boundary colors to the
+    ranks holding ghost copies (every ghost copy the first time, later only
+    the copies whose color changed), and every rank runs one step of
+    color_d1_ghost from its committed colors: it detects the conflicts of its
+    owned-ghost edges against the received colors (the lower key loses,
+    Algorithm 4) and recolors its losers with the ghosts' colors as fixed
+    constraints.  Every rank reads only the colors sent in the last exchange,
+    so the order in which the ranks run does not matter.
+    locals_: one graphgen.LocalGraph per rank; ghost_degrees: per rank, its
+    ghosts' global degrees (recolor_degrees only)."""
+    P = len(locals_)
+    maps = _exchange_map(locals_)
+    gdeg = ghost_degrees if ghost_degrees is not None else [None] * P
+
+    def step(p, gcolors, init):
+        lg = locals_[p]
+        view = type(lg)(**{**lg.__dict__, "ghost_colors": np.asarray(gcolors, dtype=np.int32)})
+        return color_d1_ghost(view, seed=seed, init_owned=init, recolor_degrees=recolor_degrees,
+                              ghost_degree=gdeg[p])
+
+    rounds = 0
+    colors = []
+    for p in range(P):          # initial coloring: no ghost colors known yet
+        r = step(p, np.zeros(locals_[p].n_ghost, np.int32), None)
+        colors.append(r.colors)
+        rounds += r.rounds
+    gc = [colors_of(colors, m) for m in maps]
+    exchanged = [int(sum(lg.n_ghost for lg in locals_))]
+    conflicts = []
+    while True:
+        total = 0
+        new = []
+        for p in range(P):
+            r = step(p, gc[p], colors[p])
+            total += r.boundary_conflicts
+            rounds += r.rounds
+            new.append(r.colors)
+        colors = new
+        conflicts.append(int(total))
+        if total == 0 or len(conflicts) > max_iterations:
+            break
+        nxt = [colors_of(colors, m) for m in maps]
+        exchanged.append(int(sum(int(np.count_nonzero(a != b)) for a, b in zip(nxt, gc))))
+        gc = nxt
+    return DistResult(colors, len(conflicts), len(conflicts) - 1, conflicts, exchanged, rounds)
+
+
+def colors_of(colors, m):
+    """The colors a rank receives for its ghosts: owner rank's owned color."""
+    part, index = m
+    out = np.zeros(part.size, dtype=np.int32)
+    for q in np.unique(part):
+        sel = part == q
+        out[sel] = colors[int(q)][index[sel]]
+    return out
