@@ -442,6 +442,23 @@ def ghost_local_graph(g: Graph, owner: np.ndarray, part: int, layers: int,
                       gid.astype(np.int32), global_colors[gid[n_o:]].astype(np.int32))
 
 
+def ghost_homes(locals_):
+    """Where every rank's ghosts are owned: per rank (owner rank, index among
+    that rank's owned vertices) as int32 arrays, found by global id."""
+    gid = np.concatenate([lg.gid[:lg.n_owned].astype(np.int64) for lg in locals_])
+    rank = np.concatenate([np.full(lg.n_owned, r, np.int64) for r, lg in enumerate(locals_)])
+    idx = np.concatenate([np.arange(lg.n_owned, dtype=np.int64) for lg in locals_])
+    order = np.argsort(gid)
+    sorted_gid = gid[order]
+    out = []
+    for lg in locals_:
+        g = lg.gid[lg.n_owned:].astype(np.int64)
+        at = order[np.searchsorted(sorted_gid, g)]
+        assert np.array_equal(gid[at], g), "a ghost is owned by no rank"
+        out.append((rank[at].astype(np.int32), idx[at].astype(np.int32)))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Stream of jobs for the batched and served forms
 # ---------------------------------------------------------------------------

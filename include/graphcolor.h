@@ -273,6 +273,63 @@ int color_d1_noalloc(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
                      const uint32_t* prio, const int32_t* init_colors, int32_t* colors,
                      color_stats* stats, const color_params* params, void* stream);
 
+/* ----------------------------------------------------------------------- */
+/* Algorithm 2 over several ranks, emulated on one GPU.                      */
+/* ----------------------------------------------------------------------- */
+
+/* One rank's local graph (DEVICE arrays, as color_d1_ghost_step takes them)
+ * and where each of its ghosts is owned. */
+typedef struct color_part {
+    int32_t n_owned, n_ghost, layers, n_g1;
+    const int32_t* row_ptr;       /* rows of the owned (and, layers == 2, layer-1) vertices */
+    const int32_t* col_idx;       /* local ids */
+    const int32_t* gid;           /* int32[n_owned + n_ghost]: global ids */
+    const int32_t* ghost_owner;   /* int32[n_ghost]: the rank owning ghost j, in [0, num_parts) */
+    const int32_t* ghost_index;   /* int32[n_ghost]: ghost j's index among that rank's owned vertices */
+    const int32_t* ghost_degree;  /* nullable int32[n_ghost]: global degrees (COLOR_FLAG_RECOLOR_DEGREES) */
+    int32_t* owned_colors;        /* out: int32[n_owned] */
+} color_part;
+
+typedef struct color_dist_stats {
+    int32_t detects;              /* conflict detections run (the last one found none) */
+    int32_t iterations;           /* recolorings: Algorithm 2's while-loop iterations (detects - 1) */
+    int32_t num_colors;           /* largest color over all ranks */
+    int32_t trace_cap;            /* in: capacity of the two trace arrays */
+    int64_t* conflicts_trace;     /* in: HOST array or NULL; out: per detection, conflicts summed over
+                                     the ranks (each owned-ghost pair counted by the rank that owns its
+                                     owned end) */
+    int64_t* exchanged_trace;     /* in: HOST array or NULL; out: per exchange, ghost copies sent */
+    int64_t exchanged_total;      /* ghost copies sent over all exchanges: the messages of an MPI run
+                                     would carry this many (index, color) pairs */
+    int64_t rounds_total;         /* on-node rounds summed over ranks and steps */
+} color_dist_stats;
+
+/* Algorithm 2 (Section 3; Sections 3.2 and 3.3) on num_parts ranks whose
+ * local graphs are all on this GPU.  Every rank first colors its owned
+ * vertices without ghost information.  Then, until the conflicts summed
+ * over the ranks (the Allreduce) are zero: each rank receives its ghosts'
+ * current colors from their owners (the first time every ghost copy, later
+ * only the copies whose owner recolored them; here a gather kernel stands in
+ * for the messages), and each rank runs color_d1_ghost_step from its
+ * committed colors: detect against the received colors (the lower key
+ * loses, Algorithm 4), recolor its losers with the ghosts' colors as fixed
+ * constraints.  Ranks read only the colors of the last exchange, so the
+ * result does not depend on the order the ranks run in.
+ *   parts        HOST array of num_parts descriptors (device arrays inside;
+ *                ghost_owner / ghost_index are trusted unless
+ *                COLOR_FLAG_VALIDATE is set)
+ *   max_detects  stop after this many detections (0: no limit):
+ *                COLOR_ENOCONVERGE, owned_colors hold the last step's colors
+ *   stats        nullable HOST struct
+ * params as for color_d1_ghost_step (COLOR_FLAG_RECOLOR_DEGREES needs every
+ * part's ghost_degree).  The call allocates and frees its own exchange
+ * buffers (8 bytes per ghost copy); the steps use the single-graph
+ * workspace.  Returns COLOR_OK, COLOR_EINVAL (also for a ghost_owner /
+ * ghost_index out of range with COLOR_FLAG_VALIDATE), COLOR_EOVERFLOW,
+ * COLOR_ENOMEM, COLOR_EHIP, COLOR_EGRAPH or COLOR_ENOCONVERGE. */
+int color_d1_distributed(int32_t num_parts, const color_part* parts, uint32_t seed, int32_t max_detects,
+                         color_dist_stats* stats, const color_params* params, void* stream);
+
 /* The priority p of Algorithm 4's rand(GID) as the kernels compute it:
  * out[i] = p(gid ? gid[i] : i) for i < n.  gid nullable (identity).
  * Returns COLOR_OK, COLOR_EINVAL or COLOR_EHIP. */

@@ -15,12 +15,13 @@ from ._binding import (COLOR_E2BIG, COLOR_EGRAPH, COLOR_EINVAL, COLOR_EMISMATCH,
                        NOALLOC_MAX_N,
                        COLOR_EPENDING, COLOR_EQUEUED, COLOR_FLAG_KERNEL_TIMING, COLOR_FLAG_NO_TAIL,
                        COLOR_FLAG_RECOLOR_DEGREES, COLOR_FLAG_VALIDATE, COLOR_OK, ENGINE_AUTO, ENGINE_BATCH, ENGINE_INCREMENTAL, ENGINE_PULL,
-                       EXPORTED, KIND_D1, KIND_D2, KIND_PD2, CHostJob, CJob, ColorError, CParams, CStats, Params,
+                       EXPORTED, KIND_D1, KIND_D2, KIND_PD2, CDistStats, CHostJob, CJob, ColorError, CParams, CPart,
+                       CStats, Params,
                        Stats, lib, strerror)
 
 __all__ = [
     "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_d1_ghost_step", "color_priority", "color_batch",
-    "color_d1_noalloc", "NOALLOC_MAX_N", "COLOR_ESCRATCH",
+    "color_d1_noalloc", "NOALLOC_MAX_N", "COLOR_ESCRATCH", "color_d1_distributed", "DistStats",
     "color_autotune", "color_autotune_reset", "ColorServer", "Params", "Stats", "ColorError", "lib",
     "strerror", "EXPORTED", "COLOR_FLAG_VALIDATE", "COLOR_FLAG_NO_TAIL", "COLOR_FLAG_KERNEL_TIMING",
     "COLOR_FLAG_RECOLOR_DEGREES",
@@ -219,6 +220,56 @@ def color_d1_ghost_step(n_owned, n_ghost, layers, n_g1, row_ptr, col_idx, gid, g
                                    ctypes.byref(st), _params(params), _stream(stream))
     _check(rc, "color_d1_ghost_step")
     return out, (rl[:n_ghost] if rl is not None else None), _to_stats(st, buf)
+
+
+class DistStats:
+    """Statistics of color_d1_distributed (see color_dist_stats)."""
+
+    def __init__(self, c, conflicts, exchanged):
+        self.detects = c.detects
+        self.iterations = c.iterations
+        self.num_colors = c.num_colors
+        self.exchanged_total = c.exchanged_total
+        self.rounds_total = c.rounds_total
+        self.conflicts = conflicts
+        self.exchanged = exchanged
+
+
+def color_d1_distributed(parts, seed=1, max_detects=0, params=None, stream=None, trace_cap=4096):
+    """Algorithm 2 over the ranks in `parts` (list of dicts: n_owned, n_ghost,
+    layers, n_g1 and device tensors row_ptr, col_idx, gid, ghost_owner,
+    ghost_index, optional ghost_degree and out).  Returns (list of owned color
+    tensors, DistStats)."""
+    torch = _torch()
+    i32 = torch.int32
+    arr = (CPart * max(len(parts), 1))()
+    outs = []
+    for i, q in enumerate(parts):
+        o = q.get("out")
+        if o is None:
+            o = torch.empty(max(q["n_owned"], 1), dtype=i32, device=q["row_ptr"].device)
+        outs.append(o[:q["n_owned"]])
+        ng = q["n_ghost"]
+        arr[i].n_owned, arr[i].n_ghost, arr[i].layers, arr[i].n_g1 = q["n_owned"], ng, q["layers"], q["n_g1"]
+        arr[i].row_ptr = _dev_ptr(q["row_ptr"], "row_ptr", i32)
+        arr[i].col_idx = _dev_ptr(q["col_idx"], "col_idx", i32)
+        arr[i].gid = _dev_ptr(q["gid"], "gid", i32)
+        arr[i].ghost_owner = _dev_ptr(q["ghost_owner"], "ghost_owner", i32, ng) if ng > 0 else None
+        arr[i].ghost_index = _dev_ptr(q["ghost_index"], "ghost_index", i32, ng) if ng > 0 else None
+        gd = q.get("ghost_degree")
+        arr[i].ghost_degree = _dev_ptr(gd, "ghost_degree", i32, ng) if (gd is not None and ng > 0) else None
+        arr[i].owned_colors = _dev_ptr(o, "out", i32)
+    st = CDistStats()
+    ct = (ctypes.c_int64 * trace_cap)()
+    et = (ctypes.c_int64 * trace_cap)()
+    st.trace_cap = trace_cap
+    st.conflicts_trace = ctypes.cast(ct, ctypes.POINTER(ctypes.c_int64))
+    st.exchanged_trace = ctypes.cast(et, ctypes.POINTER(ctypes.c_int64))
+    rc = lib().color_d1_distributed(len(parts), arr, seed & 0xFFFFFFFF, max_detects, ctypes.byref(st),
+                                    _params(params), _stream(stream))
+    _check(rc, "color_d1_distributed", allow_noconverge=True)
+    nd = min(st.detects, trace_cap)
+    return outs, DistStats(st, list(ct[:nd]), list(et[:min(nd, trace_cap)]))
 
 
 def color_priority(n, seed=1, gid=None, device="cuda", stream=None):

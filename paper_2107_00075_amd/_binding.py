@@ -40,7 +40,7 @@ EXPORTED = [
     "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_d1_ghost_step", "color_priority",
     "color_batch", "color_server_create", "color_server_submit", "color_server_poll",
     "color_server_drain", "color_server_destroy", "color_release_workspace", "color_strerror",
-    "color_autotune", "color_autotune_reset", "color_d1_noalloc",
+    "color_autotune", "color_autotune_reset", "color_d1_noalloc", "color_d1_distributed",
 ]
 
 
@@ -70,6 +70,20 @@ class CParams(ctypes.Structure):
                 ("rounds_per_poll", ctypes.c_int32), ("tail_threshold", ctypes.c_int32),
                 ("max_workgroups", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("engine", ctypes.c_int32), ("tail_checkin_us", ctypes.c_int32)]
+
+
+class CPart(ctypes.Structure):
+    _fields_ = [("n_owned", ctypes.c_int32), ("n_ghost", ctypes.c_int32), ("layers", ctypes.c_int32),
+                ("n_g1", ctypes.c_int32), ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("gid", ctypes.c_void_p), ("ghost_owner", ctypes.c_void_p), ("ghost_index", ctypes.c_void_p),
+                ("ghost_degree", ctypes.c_void_p), ("owned_colors", ctypes.c_void_p)]
+
+
+class CDistStats(ctypes.Structure):
+    _fields_ = [("detects", ctypes.c_int32), ("iterations", ctypes.c_int32), ("num_colors", ctypes.c_int32),
+                ("trace_cap", ctypes.c_int32), ("conflicts_trace", ctypes.POINTER(ctypes.c_int64)),
+                ("exchanged_trace", ctypes.POINTER(ctypes.c_int64)), ("exchanged_total", ctypes.c_int64),
+                ("rounds_total", ctypes.c_int64)]
 
 
 class CJob(ctypes.Structure):
@@ -167,6 +181,8 @@ def lib():
         l.color_d1_ghost.argtypes = [I32, I32, I32, I32, P, P, P, P, U32, P, P, SP, PP, P]
         l.color_d1_ghost_step.restype = ctypes.c_int
         l.color_d1_ghost_step.argtypes = [I32, I32, I32, I32, P, P, P, P, P, U32, P, P, P, SP, PP, P]
+        l.color_d1_distributed.restype = ctypes.c_int
+        l.color_d1_distributed.argtypes = [I32, ctypes.POINTER(CPart), U32, I32, ctypes.POINTER(CDistStats), PP, P]
         l.color_priority.restype = ctypes.c_int
         l.color_priority.argtypes = [I32, P, U32, P, P]
         l.color_batch.restype = ctypes.c_int

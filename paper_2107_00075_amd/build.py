@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgraphcolor.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["rounds.hip", "inc.hip", "setup.hip", "keys.hip", "api.hip", "noalloc.hip", "batch.hip", "server.cpp"]
+SOURCES = ["rounds.hip", "inc.hip", "setup.hip", "keys.hip", "api.hip", "noalloc.hip", "dist.hip", "batch.hip", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

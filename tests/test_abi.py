@@ -72,6 +72,10 @@ def test_bad_arguments_rejected_on_host(lib):
     assert lib.color_d1_ghost(4, 2, 1, 0, fake, fake, fake, fake, 1, fake, None, None, ctypes.byref(pr),
                               None) == b.COLOR_EINVAL
     assert lib.color_batch(1, None, None, ctypes.byref(pr), None) == b.COLOR_EINVAL
+    assert lib.color_d1_distributed(0, None, 1, 0, None, None, None) == b.COLOR_EINVAL
+    parts = (b.CPart * 1)()
+    parts[0].n_owned, parts[0].n_ghost = 4, 2   # ghosts without owner / index arrays
+    assert lib.color_d1_distributed(1, parts, 1, 0, None, None, None) == b.COLOR_EINVAL
     # the no-allocation entry point: sizes beyond its scratch, flags it cannot honour
     assert lib.color_d1_noalloc(b.NOALLOC_MAX_N + 1, fake, fake, 1, None, None, fake, None, None,
                                 None) == b.COLOR_ESCRATCH
