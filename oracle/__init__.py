@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 TRACE_ROUNDS = 4096
 RECOLOR_DEGREES = 1   # key(v) = (deg(v), p(v), gid(v)): recolorDegrees (Section 3.3, Algorithm 4)
+GHOST_RECOLOR = 2     # ghost step: losing ghosts recolored tentatively, then restored (Section 3.2)
 
 
 _SO_OMP = os.path.join(_HERE, "liboracle_omp.so")
@@ -170,10 +171,11 @@ def color_pd2(b, seed: int = 1, prio=None, init=None, max_rounds: int = 0,
 
 
 def color_d1_ghost(lg, seed: int = 1, init_owned=None, recolor_degrees: bool = False,
-                   ghost_degree=None) -> Result:
+                   ghost_degree=None, ghost_recolor: bool = False) -> Result:
     """One rank's step.  init_owned: committed owned colors to start from (a
     later iteration of Algorithm 2); ghost_degree: the ghosts' degrees, needed
-    with recolor_degrees."""
+    with recolor_degrees; ghost_recolor: losing ghosts are recolored
+    tentatively with the owned losers, then restored (Section 3.2)."""
     rp, col, gid, gc = (_i32(x) for x in (lg.row_ptr, lg.col, lg.gid, lg.ghost_colors))
     init = None if init_owned is None else _i32(init_owned)
     gdeg = None if ghost_degree is None else _i32(ghost_degree)
@@ -184,7 +186,8 @@ def color_d1_ghost(lg, seed: int = 1, init_owned=None, recolor_degrees: bool = F
     st = _Stats()
     ret = lib().orc_color_d1_ghost(lg.n_owned, lg.n_ghost, lg.layers, lg.n_g1, _ptr(rp), _ptr(col),
                                    _ptr(gid), _ptr(gc), seed & 0xFFFFFFFF, _ptr(init), _ptr(gdeg),
-                                   _ptr(out), _ptr(remote), ctypes.byref(st), _flags(recolor_degrees))
+                                   _ptr(out), _ptr(remote), ctypes.byref(st),
+                                   _flags(recolor_degrees) | (GHOST_RECOLOR if ghost_recolor else 0))
     return _result(out, st, ret, remote[:lg.n_ghost].copy())
 
 
@@ -224,7 +227,7 @@ def _exchange_map(locals_):
 
 
 def color_d1_distributed(locals_, seed: int = 1, recolor_degrees: bool = False, ghost_degrees=None,
-                         max_iterations: int = 100000) -> DistResult:
+                         max_iterations: int = 100000, ghost_recolor: bool = False) -> DistResult:
     """Algorithm 2 (Section 3), its ranks emulated one after another.
 
     Every rank first colors its owned vertices without ghost information (its
@@ -247,7 +250,7 @@ def color_d1_distributed(locals_, seed: int = 1, recolor_degrees: bool = False, 
         lg = locals_[p]
         view = type(lg)(**{**lg.__dict__, "ghost_colors": np.asarray(gcolors, dtype=np.int32)})
         return color_d1_ghost(view, seed=seed, init_owned=init, recolor_degrees=recolor_degrees,
-                              ghost_degree=gdeg[p])
+                              ghost_degree=gdeg[p], ghost_recolor=ghost_recolor)
 
     rounds = 0
     colors = []

@@ -46,6 +46,14 @@
  *       against the ghosts' fixed colors with the key rule (Algorithm 3/4);
  *       phase 3 recolors the owned losers with the ghost colors as
  *       constraints; ghost colors are never written (save/restore of gc);
+ *   R8  tentative ghost recoloring (Section 3.2, save/restore of the ghosts'
+ *       colors gc in Algorithm 2; Section 3.4 for two layers), when asked
+ *       for: phase 2 uncolors the losing end of every conflicting owned-ghost
+ *       pair, ghost or owned; phase 3 recolors every uncolored owned vertex
+ *       and losing ghost together, in the same synchronous rounds, on the
+ *       local graph (a ghost's neighbourhood is its row with two layers, and
+ *       with one layer the owned vertices adjacent to it); then the ghosts'
+ *       colors are restored: only the owned colors are kept;
  *   R7  recolorDegrees (Section 3.3; Algorithm 4 with recolorDegrees true):
  *       when asked for, key(v) = (deg(v), p(v), gid(v)), so that of two
  *       conflicting vertices the one of lower degree is uncolored and the
@@ -217,6 +225,7 @@ typedef struct {
     int32_t ignore_from;      /* neighbours with id >= ignore_from are ignored */
     keys_t keys;              /* keys of every id the rules may read */
     int32_t max_rounds;
+    const unsigned char *eligible;  /* nullable: only these uncolored ids form the worklist */
 } rounds_t;
 
 /* Runs rounds until the worklist is empty or max_rounds is reached.
@@ -233,7 +242,7 @@ static int32_t run_rounds(const rounds_t *rc, int32_t *colors, orc_stats *st,
     int32_t r = 0;
 
     for (int32_t v = 0; v < n; v++)
-        if (colors[v] == 0) { list_push(&W, v); in_w[v] = 1; }
+        if (colors[v] == 0 && (!rc->eligible || rc->eligible[v])) { list_push(&W, v); in_w[v] = 1; }
 
     while (W.len > 0 && r < rc->max_rounds) {
         r++;
@@ -365,6 +374,7 @@ static int color_common(const graph_t *g, uint32_t seed, const uint32_t *prio,
     rc.ghost_col = NULL;
     rc.ignore_from = n;
     rc.max_rounds = max_rounds > 0 ? max_rounds : INT32_MAX;
+    rc.eligible = NULL;
     rounds = run_rounds(&rc, colors, st, 0);
     finish_stats(st, colors, n, rounds);
     free_keys(&rc.keys);
@@ -411,11 +421,12 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
 {
     int32_t m = n_owned + n_ghost;
     unsigned char *loser = (unsigned char *)calloc((size_t)(n_owned > 0 ? n_owned : 1), 1);
+    unsigned char *glose = (unsigned char *)calloc((size_t)(n_ghost > 0 ? n_ghost : 1), 1);
     graph_t g = {1, n_owned, row_ptr, col, NULL, NULL};
     rounds_t rc;
     int32_t r1, r3;
-    (void)layers;
-    (void)n_g1;   /* second-layer rows are carried but never read (ghosts are fixed) */
+    /* second-layer rows are read only with tentative ghost recoloring
+     * (reading R8); with fixed ghost colors they cannot change the result */
     if (st) memset(st, 0, sizeof(*st));
     /* an owned vertex's row holds all its edges; a ghost's degree comes from
      * its owner */
@@ -431,6 +442,7 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
     rc.ghost_col = ghost_colors;
     rc.ignore_from = n_owned;
     rc.max_rounds = INT32_MAX;
+    rc.eligible = NULL;
     r1 = run_rounds(&rc, owned_colors, st, 0);
 
     /* phase 2: every owned-ghost edge against the fixed ghost colors, all
@@ -443,16 +455,82 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
             if (st) st->boundary_conflicts++;
             if (key_greater(&rc.keys, u, v))
                 loser[v] = 1;
-            else if (remote_loser)
-                remote_loser[u - n_owned] = 1;
+            else
+                glose[u - n_owned] = 1;
         }
     }
     for (int32_t v = 0; v < n_owned; v++)
         if (loser[v]) owned_colors[v] = 0;
+    if (remote_loser)
+        for (int32_t j = 0; j < n_ghost; j++) remote_loser[j] = glose[j];
 
-    /* phase 3: recolor the losers; ghosts are constraints with fixed colors */
-    rc.ignore_from = m;
-    r3 = run_rounds(&rc, owned_colors, st, r1);
+    if (!(flags & ORC_GHOST_RECOLOR)) {
+        /* phase 3: recolor the losers; ghosts are constraints with fixed colors */
+        rc.ignore_from = m;
+        r3 = run_rounds(&rc, owned_colors, st, r1);
+    } else {
+        /* phase 3 with tentative ghost recoloring (reading R8): the local
+         * graph over all m ids; rows of owned vertices (and with two layers
+         * of layer-1 ghosts) as given, with one layer a ghost's row lists the
+         * owned vertices adjacent to it */
+        int32_t rows = layers == 2 ? n_owned + n_g1 : n_owned;
+        int32_t *rp3 = (int32_t *)calloc((size_t)m + 1, sizeof(int32_t));
+        int32_t *col3;
+        int32_t *local = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+        unsigned char *elig = (unsigned char *)calloc((size_t)(m > 0 ? m : 1), 1);
+        graph_t g3;
+        rounds_t rc3;
+        int64_t nnz3 = row_ptr[rows];
+        for (int32_t v = 0; v < rows; v++) rp3[v + 1] = row_ptr[v + 1] - row_ptr[v];
+        if (layers == 1) {
+            for (int32_t v = 0; v < n_owned; v++)
+                for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+                    if (col[e] >= n_owned) { rp3[col[e] + 1]++; nnz3++; }
+        }
+        for (int32_t v = 0; v < m; v++) rp3[v + 1] += rp3[v];
+        col3 = (int32_t *)malloc((size_t)(nnz3 > 0 ? nnz3 : 1) * sizeof(int32_t));
+        {
+            int32_t *fill = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+            for (int32_t v = 0; v < m; v++) fill[v] = rp3[v];
+            for (int32_t v = 0; v < rows; v++)
+                for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) col3[fill[v]++] = col[e];
+            if (layers == 1)
+                for (int32_t v = 0; v < n_owned; v++)
+                    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+                        if (col[e] >= n_owned) col3[fill[col[e]]++] = v;
+            free(fill);
+        }
+        /* colors of the local graph: owned as committed (losers 0), ghosts
+         * as received, except the ghosts that lost phase 2 (0); the worklist
+         * is the owned losers and the losing ghosts */
+        for (int32_t v = 0; v < n_owned; v++) {
+            local[v] = owned_colors[v];
+            elig[v] = loser[v];
+        }
+        for (int32_t j = 0; j < n_ghost; j++) {
+            local[n_owned + j] = glose[j] ? 0 : ghost_colors[j];
+            elig[n_owned + j] = glose[j];
+        }
+        g3.kind = 1;
+        g3.n = m;
+        g3.row_ptr = rp3;
+        g3.col = col3;
+        g3.col_ptr = NULL;
+        g3.row_idx = NULL;
+        rc3 = rc;
+        rc3.g = &g3;
+        rc3.n = m;
+        rc3.n_base = m;
+        rc3.ghost_col = NULL;
+        rc3.ignore_from = m;
+        rc3.eligible = elig;
+        r3 = run_rounds(&rc3, local, st, r1);
+        for (int32_t v = 0; v < n_owned; v++) owned_colors[v] = local[v];   /* ghosts restored: dropped */
+        free(rp3);
+        free(col3);
+        free(local);
+        free(elig);
+    }
 
     finish_stats(st, owned_colors, n_owned, r1 + r3);
     if (st && remote_loser) {
@@ -460,6 +538,7 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
     }
     free_keys(&rc.keys);
     free(loser);
+    free(glose);
     return 0;
 }
 

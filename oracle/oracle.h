@@ -7,6 +7,7 @@
 
 #define ORC_TRACE_ROUNDS 4096
 #define ORC_RECOLOR_DEGREES 1   /* key(v) = (deg(v), p(v), gid(v)): recolorDegrees */
+#define ORC_GHOST_RECOLOR   2   /* ghost step: losing ghosts are recolored tentatively, then restored */
 
 typedef struct {
     int32_t num_colors;          /* largest color used */
