@@ -86,6 +86,20 @@ extern "C" {
  * COLOR_EINVAL.  The library sorts the vertices by this key once per call
  * (about 36 bytes of workspace per vertex). */
 #define COLOR_FLAG_RECOLOR_DEGREES 0x8u
+/* Tentative ghost recoloring (Section 3.2: a rank may temporarily recolor
+ * ghosts in its recoloring step and restores their colors afterwards;
+ * Section 3.4: with two ghost layers that recoloring sees the ghosts' whole
+ * neighbourhoods).  Also changes the coloring.  Honoured by color_d1_ghost,
+ * color_d1_ghost_step and color_d1_distributed (ignored elsewhere): phase 2
+ * uncolors the losing end of every conflicting owned-ghost pair, ghost or
+ * owned; phase 3 recolors the owned losers and the losing ghosts together,
+ * in the same synchronous rounds, on the local graph: a ghost's neighbours
+ * are its row with two layers (layer-1 rows), and with one layer the owned
+ * vertices adjacent to it; ghosts whose colors are not known (0) stay out of
+ * it.  Only the owned colors are returned: the ghosts' tentative colors are
+ * dropped (restored).  With one layer the call builds the ghosts' rows (about
+ * 4 bytes per owned-ghost entry plus 12 per ghost of workspace). */
+#define COLOR_FLAG_GHOST_RECOLOR 0x10u
 
 /* Per-call statistics (HOST struct, every pointer argument of this type is
  * nullable). */
@@ -219,7 +233,9 @@ int color_pd2(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr, const int3
  * owned-ghost edge with the key rule on the ghosts' colors; phase 3 recolors
  * the owned losers with the ghost colors as constraints.  Ghost colors are
  * never written (the save/restore of gc in Algorithm 2).  The second layer's
- * rows are accepted; with fixed ghost colors they do not change the result.
+ * rows are accepted; with fixed ghost colors they do not change the result
+ * (with COLOR_FLAG_GHOST_RECOLOR the ghosts are recolored tentatively on
+ * them, which does).
  * Same errors as color_d1 (COLOR_EINVAL also for layers not 1 or 2). */
 int color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1,
                    const int32_t* row_ptr, const int32_t* col_idx, const int32_t* gid,

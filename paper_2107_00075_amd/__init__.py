@@ -14,7 +14,7 @@ import ctypes
 from ._binding import (COLOR_E2BIG, COLOR_EGRAPH, COLOR_EINVAL, COLOR_EMISMATCH, COLOR_ENOCONVERGE, COLOR_ESCRATCH,
                        NOALLOC_MAX_N,
                        COLOR_EPENDING, COLOR_EQUEUED, COLOR_FLAG_KERNEL_TIMING, COLOR_FLAG_NO_TAIL,
-                       COLOR_FLAG_RECOLOR_DEGREES, COLOR_FLAG_VALIDATE, COLOR_OK, ENGINE_AUTO, ENGINE_BATCH, ENGINE_INCREMENTAL, ENGINE_PULL,
+                       COLOR_FLAG_GHOST_RECOLOR, COLOR_FLAG_RECOLOR_DEGREES, COLOR_FLAG_VALIDATE, COLOR_OK, ENGINE_AUTO, ENGINE_BATCH, ENGINE_INCREMENTAL, ENGINE_PULL,
                        EXPORTED, KIND_D1, KIND_D2, KIND_PD2, CDistStats, CHostJob, CJob, ColorError, CParams, CPart,
                        CStats, Params,
                        Stats, lib, strerror)
@@ -24,7 +24,7 @@ __all__ = [
     "color_d1_noalloc", "NOALLOC_MAX_N", "COLOR_ESCRATCH", "color_d1_distributed", "DistStats",
     "color_autotune", "color_autotune_reset", "ColorServer", "Params", "Stats", "ColorError", "lib",
     "strerror", "EXPORTED", "COLOR_FLAG_VALIDATE", "COLOR_FLAG_NO_TAIL", "COLOR_FLAG_KERNEL_TIMING",
-    "COLOR_FLAG_RECOLOR_DEGREES",
+    "COLOR_FLAG_RECOLOR_DEGREES", "COLOR_FLAG_GHOST_RECOLOR",
     "ENGINE_AUTO", "ENGINE_PULL", "ENGINE_INCREMENTAL", "ENGINE_BATCH", "KIND_D1", "KIND_D2", "KIND_PD2",
 ]
 

@@ -32,6 +32,7 @@ COLOR_FLAG_VALIDATE = 0x1
 COLOR_FLAG_NO_TAIL = 0x2
 COLOR_FLAG_KERNEL_TIMING = 0x4
 COLOR_FLAG_RECOLOR_DEGREES = 0x8
+COLOR_FLAG_GHOST_RECOLOR = 0x10
 
 KIND_D1, KIND_D2, KIND_PD2 = 1, 2, 3
 ENGINE_AUTO, ENGINE_PULL, ENGINE_INCREMENTAL, ENGINE_BATCH = 0, 1, 2, 3

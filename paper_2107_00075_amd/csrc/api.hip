@@ -74,7 +74,7 @@ std::array<DevBuf*, Workspace::kNumBuffers> Workspace::buffers() {
           &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
           &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &inc_wl0, &inc_wl1, &scan_tmp,
           &deferred_work, &deferred_done, &rank, &rk_key0, &rk_key1, &rk_val0, &rk_val1, &rk_deg0,
-          &rk_deg1, &rk_tmp};
+          &rk_deg1, &rk_tmp, &gr_rp, &gr_ci, &gr_cnt, &gr_init};
 }
 
 void Workspace::release() {
@@ -1036,9 +1036,13 @@ int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_
   if (n_ghost > 0 && (!ghost_colors || !gid)) return COLOR_EINVAL;
   const bool degrees = params && (params->flags & COLOR_FLAG_RECOLOR_DEGREES);
   if (degrees && n_ghost > 0 && !ghost_degree) return COLOR_EINVAL;
+  const bool grec = params && (params->flags & COLOR_FLAG_GHOST_RECOLOR);
   const int32_t m = n_owned + n_ghost;
+  // with tentative ghost recoloring, phase 3 runs over every id that has a
+  // row: owned and (two layers) layer-1 ghosts, or (one layer) every ghost
+  const int32_t n3 = grec ? (layers == 2 ? n_owned + n_g1 : m) : n_owned;
   Call c;
-  int e = begin_call(c, kD1, params, stats, stream, n_owned, m);
+  int e = begin_call(c, kD1, params, stats, stream, n3, m);
   if (e) return e;
   std::unique_lock<std::mutex> lk(c.ws->mu);
   if (n_owned == 0) return finish_call(c, stats, 0, COLOR_OK);
@@ -1088,15 +1092,65 @@ int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_
   // phase 3: ghosts become fixed committed colors; losers are recolored
   launch_ghost_fill(n_owned, n_ghost, ghost_colors, Cint, rb.T, &c.S->maxc, c.st);
   c.launches += 3;
-  if (hipMemsetAsync(c.S->cnt[0], 0, sizeof(int32_t) * 8, c.st) != hipSuccess) return COLOR_EHIP;
-  launch_scatter(n_owned, Cint, w->bin.as<int8_t>(), L, c.wl[0], c.S->cnt[0], w->split_vertex.as<int32_t>(), c.st);
-  c.launches += 1;
-  if (hipMemcpyAsync(c.H->cnt[0], c.S->cnt[0], sizeof(int32_t) * 8, hipMemcpyDeviceToHost, c.st) != hipSuccess)
-    return COLOR_EHIP;
-  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
-  for (int i = 0; i < kBins; ++i) known[i] = c.H->cnt[0][i];
-  g.limit = m;
-  rc = run_phase<kD1>(c, g, k, L, rb, known, r1, c.P.max_rounds);
+  if (!grec) {
+    if (hipMemsetAsync(c.S->cnt[0], 0, sizeof(int32_t) * 8, c.st) != hipSuccess) return COLOR_EHIP;
+    launch_scatter(n_owned, Cint, w->bin.as<int8_t>(), L, c.wl[0], c.S->cnt[0], w->split_vertex.as<int32_t>(),
+                   c.st);
+    c.launches += 1;
+    if (hipMemcpyAsync(c.H->cnt[0], c.S->cnt[0], sizeof(int32_t) * 8, hipMemcpyDeviceToHost, c.st) != hipSuccess)
+      return COLOR_EHIP;
+    if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+    for (int i = 0; i < kBins; ++i) known[i] = c.H->cnt[0][i];
+    g.limit = m;
+    rc = run_phase<kD1>(c, g, k, L, rb, known, r1, c.P.max_rounds);
+  } else {
+    // tentative ghost recoloring (Section 3.2 save/restore; Section 3.4):
+    // owned losers and losing ghosts are recolored together on the local
+    // graph; the ghosts' tentative colors are dropped afterwards
+    const int32_t* rp3 = row_ptr;
+    const int32_t* ci3 = col_idx;
+    if (layers == 1 && n_ghost > 0) {
+      int32_t owned_nnz = 0;
+      if ((e = read_nnz(c, row_ptr, n_owned, &owned_nnz))) return e;
+      const size_t ng1 = static_cast<size_t>(n_ghost) + 1;
+      size_t scan_bytes = 0;
+      if (exclusive_scan_i32(nullptr, nullptr, n_ghost + 1, nullptr, &scan_bytes, c.st)) return COLOR_EHIP;
+      if ((e = w->gr_cnt.ensure(sizeof(int32_t) * 3 * ng1, false, c.st)) ||
+          (e = w->gr_rp.ensure(sizeof(int32_t) * (static_cast<size_t>(m) + 1), false, c.st)) ||
+          (e = w->scan_tmp.ensure(scan_bytes, false, c.st)))
+        return e;
+      int32_t* cnt = w->gr_cnt.as<int32_t>();
+      launch_zero_words(cnt, 3 * ng1, c.st);
+      // the owned rows' entries, then the ghosts' rows: one entry per
+      // owned-ghost entry of the owned rows, so at most owned_nnz more
+      if ((e = w->gr_ci.ensure(sizeof(int32_t) * (2 * static_cast<size_t>(owned_nnz) + 1), false, c.st))) return e;
+      int err = 0;
+      launch_ghost_rows(n_owned, n_ghost, row_ptr, col_idx, cnt, cnt + ng1, cnt + 2 * ng1, w->gr_rp.as<int32_t>(),
+                        w->gr_ci.as<int32_t>(), w->scan_tmp.p, w->scan_tmp.bytes, c.st, &err);
+      c.launches += 4;
+      if (err || hipGetLastError() != hipSuccess) return COLOR_EHIP;
+      rp3 = w->gr_rp.as<int32_t>();
+      ci3 = w->gr_ci.as<int32_t>();
+    }
+    if ((e = w->gr_init.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n3, 1)), false, c.st))) return e;
+    launch_ghost_recolor_init(n_owned, n3, Cint, ghost_colors, gflag, w->gr_init.as<int32_t>(), c.st);
+    c.launches += 1;
+    GraphView g3{n3, n3, rp3, ci3, rp3, ci3};
+    g3.limit = m;
+    // the second bin setup of the call counts afresh
+    static_assert(offsetof(Scalars, count_unc) == offsetof(Scalars, count_all) + sizeof(Scalars::count_all),
+                  "per-bin counts are cleared together");
+    launch_zero_words(c.S->count_all, 16, c.st);
+    launch_zero_words(&c.S->max_split_work, 1, c.st);
+    launch_zero_words(&c.S->max_work, 1, c.st);
+    launch_zero_words(&c.S->total_work, 2, c.st);
+    c.launches += 4;
+    BinLayout L3;
+    RoundBufs rb3;
+    int32_t known3[kBins];
+    if ((e = setup_bins<kD1>(c, g3, w->gr_init.as<int32_t>(), Cint, m, L3, rb3, known3))) return e;
+    rc = run_phase<kD1>(c, g3, k, L3, rb3, known3, r1, c.P.max_rounds);
+  }
   if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
   launch_flags_out(n_ghost, gflag, remote_loser, &c.S->remote, c.st);
   launch_copy_i32(n_owned, Cint, owned_colors, c.st);

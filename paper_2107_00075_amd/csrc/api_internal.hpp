@@ -63,11 +63,12 @@ struct Workspace {
   DevBuf inc_wl0, inc_wl1;  // incremental engine: worklists binned by active-list length
   DevBuf deferred_work, deferred_done;  // setup: per heavy D2/PD2 vertex, its work and slices done
   DevBuf rank, rk_key0, rk_key1, rk_val0, rk_val1, rk_deg0, rk_deg1, rk_tmp;  // recolorDegrees ranks
+  DevBuf gr_rp, gr_ci, gr_cnt, gr_init;  // tentative ghost recoloring: local CSR with ghost rows, start colors
   Scalars* host = nullptr;  // pinned staging for read-backs
   std::vector<hipEvent_t> events;  // pool for COLOR_FLAG_KERNEL_TIMING
   ~Workspace();
   void release();
-  static constexpr int kNumBuffers = 38;
+  static constexpr int kNumBuffers = 42;
   std::array<DevBuf*, kNumBuffers> buffers();   // every DevBuf above
 };
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <climits>
 
+#include "inc.hpp"
 #include "setup.hpp"
 
 namespace gcol {
@@ -495,6 +496,81 @@ void launch_boundary_uncolor(int32_t n_owned, const int32_t* loser, int32_t* C, 
   if (n_owned > 0)
     hipLaunchKernelGGL(boundary_uncolor_kernel, dim3(blocks_for(n_owned)), dim3(kBlock), 0, st, n_owned,
                        loser, C);
+}
+
+// Tentative ghost recoloring, one layer: a ghost's row in the local graph is
+// the owned vertices adjacent to it (the local graph's undirected
+// owned-ghost edges).  Counts them per ghost ...
+__global__ __launch_bounds__(kBlock) void ghost_row_count_kernel(int32_t n_owned, const int32_t* rp,
+                                                                 const int32_t* ci, int32_t* cnt) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n_owned) return;
+  for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+    const int32_t u = ci[e];
+    if (u >= n_owned) atomicAdd(&cnt[u - n_owned], 1);
+  }
+}
+
+// ... and, with the per-ghost offsets goff (exclusive scan of the counts,
+// n_ghost + 1 entries), writes the local CSR over all owned + ghost ids:
+// owned rows as given, then the ghosts' rows.
+__global__ __launch_bounds__(kBlock) void ghost_rows_kernel(int32_t n_owned, int32_t n_ghost, const int32_t* rp,
+                                                            const int32_t* ci, const int32_t* goff, int32_t* fill,
+                                                            int32_t* rp3, int32_t* ci3) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const int32_t owned_nnz = rp[n_owned];
+  if (i <= n_owned) st_dev(&rp3[i], rp[i]);
+  if (i > 0 && i <= n_ghost) st_dev(&rp3[n_owned + i], owned_nnz + goff[i]);
+  if (i >= n_owned) return;
+  for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+    const int32_t u = ci[e];
+    st_dev(&ci3[e], u);
+    if (u >= n_owned) {
+      const int32_t j = u - n_owned;
+      st_dev(&ci3[owned_nnz + goff[j] + atomicAdd(&fill[j], 1)], i);
+    }
+  }
+}
+
+// Colors the recoloring phase starts from, for the rows-carrying ids
+// [0, n3): owned vertices as committed (losers already 0), ghosts as
+// received except the losing ones (0: recolored tentatively); a ghost whose
+// color is not known yet (0 received) gets kGhostUnknown, which keeps it out
+// of the worklist and out of every first fit.
+__global__ __launch_bounds__(kBlock) void ghost_recolor_init_kernel(int32_t n_owned, int32_t n3, const int32_t* C,
+                                                                    const int32_t* gc, const int32_t* gflag,
+                                                                    int32_t* init) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n3) return;
+  int32_t c;
+  if (v < n_owned) {
+    c = ld_dev(&C[v]);
+  } else {
+    const int32_t j = v - n_owned;
+    c = ld_dev(&gflag[j]) ? 0 : (gc[j] == 0 ? kGhostUnknown : gc[j]);
+  }
+  st_dev(&init[v], c);
+}
+
+void launch_ghost_rows(int32_t n_owned, int32_t n_ghost, const int32_t* rp, const int32_t* ci, int32_t* cnt,
+                       int32_t* goff, int32_t* fill, int32_t* rp3, int32_t* ci3, void* scan_tmp, size_t scan_bytes,
+                       hipStream_t st, int* err) {
+  *err = 0;
+  if (n_ghost > 0) {
+    hipLaunchKernelGGL(ghost_row_count_kernel, dim3(blocks_for(std::max(n_owned, 1))), dim3(kBlock), 0, st, n_owned,
+                       rp, ci, cnt);
+    if (exclusive_scan_i32(cnt, goff, n_ghost + 1, scan_tmp, &scan_bytes, st)) *err = 1;
+  }
+  const int32_t items = std::max(n_owned + 1, n_ghost + 1);
+  hipLaunchKernelGGL(ghost_rows_kernel, dim3(blocks_for(items)), dim3(kBlock), 0, st, n_owned, n_ghost, rp, ci,
+                     goff, fill, rp3, ci3);
+}
+
+void launch_ghost_recolor_init(int32_t n_owned, int32_t n3, const int32_t* C, const int32_t* gc, const int32_t* gflag,
+                               int32_t* init, hipStream_t st) {
+  if (n3 > 0)
+    hipLaunchKernelGGL(ghost_recolor_init_kernel, dim3(blocks_for(n3)), dim3(kBlock), 0, st, n_owned, n3, C, gc,
+                       gflag, init);
 }
 
 void launch_ghost_fill(int32_t n_owned, int32_t n_ghost, const int32_t* gc, int32_t* C, int32_t* T,

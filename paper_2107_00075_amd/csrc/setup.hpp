@@ -43,6 +43,17 @@ void launch_boundary(int32_t n_owned, const int32_t* rp, const int32_t* ci, cons
 void launch_boundary_uncolor(int32_t n_owned, const int32_t* loser, int32_t* C, hipStream_t st);
 void launch_ghost_fill(int32_t n_owned, int32_t n_ghost, const int32_t* gc, int32_t* C, int32_t* T,
                        int32_t* maxc, hipStream_t st);
+// Tentative ghost recoloring: a ghost whose color is not known yet.
+constexpr int32_t kGhostUnknown = 0x7fffffff;
+// One ghost layer: the local CSR over owned + ghost ids, a ghost's row being
+// its owned neighbours.  cnt and fill: n_ghost + 1 zeroed words; goff:
+// n_ghost + 1; rp3: n_owned + n_ghost + 1; ci3: rp[n_owned] + cut entries.
+// *err = 1 if the scan failed.
+void launch_ghost_rows(int32_t n_owned, int32_t n_ghost, const int32_t* rp, const int32_t* ci, int32_t* cnt,
+                       int32_t* goff, int32_t* fill, int32_t* rp3, int32_t* ci3, void* scan_tmp, size_t scan_bytes,
+                       hipStream_t st, int* err);
+void launch_ghost_recolor_init(int32_t n_owned, int32_t n3, const int32_t* C, const int32_t* gc, const int32_t* gflag,
+                               int32_t* init, hipStream_t st);
 void launch_max_i32(int32_t n, const int32_t* a, int32_t* out, hipStream_t st);
 void launch_flags_out(int32_t n, const int32_t* gflag, uint8_t* out, unsigned long long* count,
                       hipStream_t st);
