@@ -442,6 +442,60 @@ def ghost_local_graph(g: Graph, owner: np.ndarray, part: int, layers: int,
                       gid.astype(np.int32), global_colors[gid[n_o:]].astype(np.int32))
 
 
+def slab_partition(dims, parts: int) -> np.ndarray:
+    """Block partition of a stencil mesh (id = x + X (y + Y z)) along its last
+    axis into `parts` slabs of consecutive planes."""
+    dims = tuple(int(d) for d in dims)
+    n = int(np.prod(dims))
+    z = np.arange(n, dtype=np.int64) // (n // dims[-1])
+    return (z * parts // dims[-1]).astype(np.int32)
+
+
+@dataclass
+class LocalPattern:
+    """One rank's share of a partial distance-2 problem: owned columns
+    [0, n_owned) in increasing GID order, then ghost columns (columns that
+    share a row with an owned column); the local rows are the rows touching
+    an owned column.  col_ptr/row_idx: the owned columns' rows (local row
+    ids); row_ptr/col_idx: the local rows' columns (local column ids)."""
+    n_owned: int
+    n_ghost: int
+    n_rows: int
+    col_ptr: np.ndarray
+    row_idx: np.ndarray
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    gid: np.ndarray
+    ghost_colors: np.ndarray
+
+
+def pd2_local_pattern(b: Bipartite, owner_cols: np.ndarray, part: int, global_colors: np.ndarray) -> LocalPattern:
+    cp = b.col_ptr.astype(np.int64)
+    owned = np.nonzero(owner_cols == part)[0].astype(np.int64)
+    d = cp[owned + 1] - cp[owned]
+    idx = np.repeat(cp[owned], d) + (np.arange(d.sum()) - np.repeat(np.cumsum(d) - d, d))
+    rows_of_owned = b.row_idx[idx].astype(np.int64)
+    lrows = np.unique(rows_of_owned)
+    rp = b.row_ptr.astype(np.int64)
+    rd = rp[lrows + 1] - rp[lrows]
+    ridx = np.repeat(rp[lrows], rd) + (np.arange(rd.sum()) - np.repeat(np.cumsum(rd) - rd, rd))
+    cols_of_rows = b.col_idx[ridx].astype(np.int64)
+    ghosts = np.unique(cols_of_rows[owner_cols[cols_of_rows] != part])
+    gid = np.concatenate([owned, ghosts])
+    lcol = np.full(b.n_cols, -1, dtype=np.int64)
+    lcol[gid] = np.arange(gid.size)
+    lrow = np.full(b.n_rows, -1, dtype=np.int64)
+    lrow[lrows] = np.arange(lrows.size)
+    col_ptr = np.zeros(owned.size + 1, dtype=np.int64)
+    np.cumsum(d, out=col_ptr[1:])
+    row_ptr = np.zeros(lrows.size + 1, dtype=np.int64)
+    np.cumsum(rd, out=row_ptr[1:])
+    return LocalPattern(int(owned.size), int(ghosts.size), int(lrows.size), col_ptr.astype(np.int32),
+                        lrow[rows_of_owned].astype(np.int32), row_ptr.astype(np.int32),
+                        lcol[cols_of_rows].astype(np.int32), gid.astype(np.int32),
+                        global_colors[ghosts].astype(np.int32))
+
+
 def ghost_homes(locals_):
     """Where every rank's ghosts are owned: per rank (owner rank, index among
     that rank's owned vertices) as int32 arrays, found by global id."""

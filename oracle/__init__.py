@@ -85,6 +85,9 @@ def lib(omp: bool = False):
         l.orc_color_d1_ghost.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int32, P, P, P, P, ctypes.c_uint32, P, P, P, P, P,
                                          ctypes.c_int]
+        l.orc_color_d2_ghost.restype = ctypes.c_int
+        l.orc_color_d2_ghost.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P,
+                                         ctypes.c_uint32, P, P, P, ctypes.c_int]
         l.orc_serial_greedy.restype = None
         l.orc_serial_greedy.argtypes = [ctypes.c_int32, P, P, P, P]
         _libs[omp] = l
@@ -189,6 +192,30 @@ def color_d1_ghost(lg, seed: int = 1, init_owned=None, recolor_degrees: bool = F
                                    _ptr(out), _ptr(remote), ctypes.byref(st),
                                    _flags(recolor_degrees) | (GHOST_RECOLOR if ghost_recolor else 0))
     return _result(out, st, ret, remote[:lg.n_ghost].copy())
+
+
+def color_d2_ghost(lg, seed: int = 1) -> Result:
+    """One rank's distance-2 step on a two-layer local graph (graphgen
+    LocalGraph with layers = 2): reading R9 of oracle.c."""
+    rp, col, gid, gc = (_i32(x) for x in (lg.row_ptr, lg.col, lg.gid, lg.ghost_colors))
+    out = np.zeros(lg.n_owned, dtype=np.int32)
+    remote = np.zeros(max(lg.n_ghost, 1), dtype=np.uint8)
+    st = _Stats()
+    ret = lib().orc_color_d2_ghost(2, lg.n_owned, lg.n_ghost, _ptr(rp), _ptr(col), _ptr(rp), _ptr(col), _ptr(gid),
+                                   _ptr(gc), seed & 0xFFFFFFFF, _ptr(out), _ptr(remote), ctypes.byref(st), 0)
+    return _result(out, st, ret, remote[:lg.n_ghost].copy())
+
+
+def color_pd2_ghost(lp, seed: int = 1) -> Result:
+    """One rank's partial distance-2 step on its local pattern (graphgen
+    LocalPattern: owned columns' rows, the local rows' columns)."""
+    arrs = [_i32(x) for x in (lp.col_ptr, lp.row_idx, lp.row_ptr, lp.col_idx, lp.gid, lp.ghost_colors)]
+    out = np.zeros(lp.n_owned, dtype=np.int32)
+    remote = np.zeros(max(lp.n_ghost, 1), dtype=np.uint8)
+    st = _Stats()
+    ret = lib().orc_color_d2_ghost(3, lp.n_owned, lp.n_ghost, *[_ptr(a) for a in arrs], seed & 0xFFFFFFFF,
+                                   _ptr(out), _ptr(remote), ctypes.byref(st), 0)
+    return _result(out, st, ret, remote[:lp.n_ghost].copy())
 
 
 def serial_greedy(g, order) -> np.ndarray:

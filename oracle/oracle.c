@@ -54,6 +54,17 @@
  *       local graph (a ghost's neighbourhood is its row with two layers, and
  *       with one layer the owned vertices adjacent to it); then the ghosts'
  *       colors are restored: only the owned colors are kept;
+ *   R9  distance-2 and partial distance-2 ghost step (Section 3.5,
+ *       Algorithm 5 over the rank's owned vertices; Section 3.6): the local
+ *       graph carries the full two-hop neighbourhood of every owned vertex
+ *       (D2: rows of the owned vertices and of the first ghost layer; PD2:
+ *       the owned columns' rows and those rows' columns).  Phase 1 colors the
+ *       owned vertices with every ghost uncolored (ghost colors are not
+ *       used, the adjacency through ghosts is); phase 2 compares every owned
+ *       vertex with every distinct ghost of its two-hop neighbourhood
+ *       against the ghosts' fixed colors (key rule; each pair counted once);
+ *       phase 3 recolors the owned losers with the ghosts' colors as
+ *       constraints;
  *   R7  recolorDegrees (Section 3.3; Algorithm 4 with recolorDegrees true):
  *       when asked for, key(v) = (deg(v), p(v), gid(v)), so that of two
  *       conflicting vertices the one of lower degree is uncolored and the
@@ -539,6 +550,96 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
     free_keys(&rc.keys);
     free(loser);
     free(glose);
+    return 0;
+}
+
+/* One rank's step for distance-2 (kind 2) or partial distance-2 (kind 3)
+ * coloring (reading R9).  D2: hop-1 and hop-2 arrays are one local CSR whose
+ * rows are the owned vertices then the first ghost layer; PD2: hop 1 is the
+ * owned columns' rows (col_ptr, row_idx: local row ids), hop 2 the local
+ * rows' columns (row_ptr, col_idx: local column ids, owned first, then
+ * ghosts).  The first n_owned local ids are owned, the next n_ghost ghosts. */
+int orc_color_d2_ghost(int kind, int32_t n_owned, int32_t n_ghost, const int32_t *hop1_ptr,
+                       const int32_t *hop1_idx, const int32_t *hop2_ptr, const int32_t *hop2_idx,
+                       const int32_t *gid, const int32_t *ghost_colors, uint32_t seed,
+                       int32_t *owned_colors, unsigned char *remote_loser, orc_stats *st, int flags)
+{
+    int32_t m = n_owned + n_ghost;
+    unsigned char *loser = (unsigned char *)calloc((size_t)(n_owned > 0 ? n_owned : 1), 1);
+    unsigned char *glose = (unsigned char *)calloc((size_t)(n_ghost > 0 ? n_ghost : 1), 1);
+    int32_t *none = (int32_t *)calloc((size_t)(n_ghost > 0 ? n_ghost : 1), sizeof(int32_t));
+    int32_t *seen = (int32_t *)malloc((size_t)(n_ghost > 0 ? n_ghost : 1) * sizeof(int32_t));
+    graph_t g;
+    rounds_t rc;
+    list_t nb = {0};
+    int32_t r1, r3;
+    if (kind == 2) {
+        g.kind = 2;
+        g.row_ptr = hop1_ptr;
+        g.col = hop1_idx;
+        g.col_ptr = NULL;
+        g.row_idx = NULL;
+    } else {
+        g.kind = 3;
+        g.row_ptr = hop2_ptr;
+        g.col = hop2_idx;
+        g.col_ptr = hop1_ptr;
+        g.row_idx = hop1_idx;
+    }
+    g.n = n_owned;
+    if (st) memset(st, 0, sizeof(*st));
+    /* an owned vertex's degree: its hop-1 row; degrees of ghosts are not
+     * used by this step */
+    rc.keys = make_keys(m, gid, seed, NULL, 0, hop1_ptr, n_owned, NULL);
+    for (int32_t v = 0; v < n_owned; v++) owned_colors[v] = 0;
+    (void)flags;
+
+    /* phase 1: owned vertices only; ghosts are walked through but
+     * uncolored (color 0 constrains nothing; ghosts never join a worklist) */
+    rc.g = &g;
+    rc.n = n_owned;
+    rc.n_base = n_owned;
+    rc.ghost_col = none;
+    rc.ignore_from = m;
+    rc.max_rounds = INT32_MAX;
+    rc.eligible = NULL;
+    r1 = run_rounds(&rc, owned_colors, st, 0);
+
+    /* phase 2: every distinct ghost of every owned vertex's two-hop
+     * neighbourhood against the ghosts' fixed colors, judged all at once */
+    for (int32_t j = 0; j < n_ghost; j++) seen[j] = -1;
+    for (int32_t v = 0; v < n_owned; v++) {
+        neighbourhood(&g, v, &nb);
+        for (int64_t i = 0; i < nb.len; i++) {
+            int32_t x = nb.ids[i];
+            if (x < n_owned || seen[x - n_owned] == v) continue;
+            seen[x - n_owned] = v;
+            if (owned_colors[v] != ghost_colors[x - n_owned]) continue;
+            if (st) st->boundary_conflicts++;
+            if (key_greater(&rc.keys, x, v))
+                loser[v] = 1;
+            else
+                glose[x - n_owned] = 1;
+        }
+    }
+    for (int32_t v = 0; v < n_owned; v++)
+        if (loser[v]) owned_colors[v] = 0;
+    if (remote_loser)
+        for (int32_t j = 0; j < n_ghost; j++) remote_loser[j] = glose[j];
+
+    /* phase 3: recolor the losers; ghosts are constraints with fixed colors */
+    rc.ghost_col = ghost_colors;
+    r3 = run_rounds(&rc, owned_colors, st, r1);
+
+    finish_stats(st, owned_colors, n_owned, r1 + r3);
+    if (st && remote_loser)
+        for (int32_t j = 0; j < n_ghost; j++) st->remote_losers += remote_loser[j];
+    free_keys(&rc.keys);
+    free(loser);
+    free(glose);
+    free(none);
+    free(seen);
+    free(nb.ids);
     return 0;
 }
 

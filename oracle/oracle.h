@@ -41,6 +41,10 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
                        const int32_t *ghost_colors, uint32_t seed, const int32_t *init_owned,
                        const int32_t *ghost_degree, int32_t *owned_colors,
                        unsigned char *remote_loser, orc_stats *st, int flags);
+int orc_color_d2_ghost(int kind, int32_t n_owned, int32_t n_ghost, const int32_t *hop1_ptr,
+                       const int32_t *hop1_idx, const int32_t *hop2_ptr, const int32_t *hop2_idx,
+                       const int32_t *gid, const int32_t *ghost_colors, uint32_t seed,
+                       int32_t *owned_colors, unsigned char *remote_loser, orc_stats *st, int flags);
 void orc_serial_greedy(int32_t n, const int32_t *row_ptr, const int32_t *col,
                        const int32_t *order, int32_t *colors);
 #endif
