@@ -289,6 +289,42 @@ int color_d1_noalloc(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
                      const uint32_t* prio, const int32_t* init_colors, int32_t* colors,
                      color_stats* stats, const color_params* params, void* stream);
 
+/* One rank's step of the distributed distance-2 method (Section 3,
+ * Algorithm 2, with the distance-2 conflict detection of Section 3.5,
+ * Algorithm 5, over the rank's owned vertices) on a local graph with two
+ * ghost layers, which carries the full two-hop neighbourhood of every owned
+ * vertex:
+ *   local ids: owned [0, n_owned), then ghosts [n_owned, n_owned + n_ghost),
+ *   the first n_g1 of them the first layer;
+ *   row_ptr int32[n_owned + n_g1 + 1], col_idx local ids: the rows of the
+ *   owned vertices, then of the first-layer ghosts (complete rows)
+ *   gid int32[n_owned + n_ghost]; ghost_colors int32[n_ghost] (>= 0; 0 = not
+ *   known yet); owned_colors out int32[n_owned]; remote_loser out
+ *   uint8[n_ghost], nullable.
+ * Phase 1 colors the owned vertices at distance 2 with every ghost
+ * uncolored (walks pass through ghosts, the ghosts' colors are not used);
+ * phase 2 compares every owned vertex with every distinct ghost within two
+ * hops against the ghosts' colors (the lower key loses; boundary_conflicts
+ * counts each such pair once); phase 3 recolors the owned losers with the
+ * ghosts' colors as constraints.  Pull engine (engine =
+ * COLOR_ENGINE_INCREMENTAL returns COLOR_EINVAL).  Errors as color_d2. */
+int color_d2_ghost(int32_t n_owned, int32_t n_ghost, int32_t n_g1, const int32_t* row_ptr,
+                   const int32_t* col_idx, const int32_t* gid, const int32_t* ghost_colors, uint32_t seed,
+                   int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats,
+                   const color_params* params, void* stream);
+
+/* The same step for partial distance-2 coloring of columns (Section 3.6): a
+ * rank owns columns; its local pattern holds the rows that touch an owned
+ * column and all of those rows' columns:
+ *   col_ptr int32[n_owned + 1], row_idx: the owned columns' rows (local row
+ *   ids in [0, n_rows)); row_ptr int32[n_rows + 1], col_idx: the local rows'
+ *   columns (local column ids: owned [0, n_owned), then ghost columns).
+ * Other arguments, phases and errors as color_d2_ghost. */
+int color_pd2_ghost(int32_t n_owned, int32_t n_ghost, int32_t n_rows, const int32_t* col_ptr,
+                    const int32_t* row_idx, const int32_t* row_ptr, const int32_t* col_idx,
+                    const int32_t* gid, const int32_t* ghost_colors, uint32_t seed, int32_t* owned_colors,
+                    uint8_t* remote_loser, color_stats* stats, const color_params* params, void* stream);
+
 /* ----------------------------------------------------------------------- */
 /* Algorithm 2 over several ranks, emulated on one GPU.                      */
 /* ----------------------------------------------------------------------- */

@@ -22,6 +22,7 @@ from ._binding import (COLOR_E2BIG, COLOR_EGRAPH, COLOR_EINVAL, COLOR_EMISMATCH,
 __all__ = [
     "color_d1", "color_d2", "color_pd2", "color_d1_ghost", "color_d1_ghost_step", "color_priority", "color_batch",
     "color_d1_noalloc", "NOALLOC_MAX_N", "COLOR_ESCRATCH", "color_d1_distributed", "DistStats",
+    "color_d2_ghost", "color_pd2_ghost",
     "color_autotune", "color_autotune_reset", "ColorServer", "Params", "Stats", "ColorError", "lib",
     "strerror", "EXPORTED", "COLOR_FLAG_VALIDATE", "COLOR_FLAG_NO_TAIL", "COLOR_FLAG_KERNEL_TIMING",
     "COLOR_FLAG_RECOLOR_DEGREES", "COLOR_FLAG_GHOST_RECOLOR",
@@ -219,6 +220,49 @@ def color_d1_ghost_step(n_owned, n_ghost, layers, n_g1, row_ptr, col_idx, gid, g
                                    _dev_ptr(rl, "remote_loser") if rl is not None else None,
                                    ctypes.byref(st), _params(params), _stream(stream))
     _check(rc, "color_d1_ghost_step")
+    return out, (rl[:n_ghost] if rl is not None else None), _to_stats(st, buf)
+
+
+def color_d2_ghost(n_owned, n_ghost, n_g1, row_ptr, col_idx, gid, ghost_colors, seed=1, out=None,
+                   remote_loser=True, params=None, stream=None, trace_cap=0):
+    """One rank's distance-2 step on its two-layer local graph.  Returns
+    (owned colors, remote-loser flags or None, Stats)."""
+    torch = _torch()
+    i32 = torch.int32
+    dev = row_ptr.device
+    if out is None:
+        out = torch.empty(max(n_owned, 0), dtype=i32, device=dev)
+    rl = torch.empty(max(n_ghost, 1), dtype=torch.uint8, device=dev) if remote_loser else None
+    st, buf = _stats(trace_cap)
+    rc = lib().color_d2_ghost(n_owned, n_ghost, n_g1, _dev_ptr(row_ptr, "row_ptr", i32),
+                              _dev_ptr(col_idx, "col_idx", i32), _dev_ptr(gid, "gid", i32),
+                              _dev_ptr(ghost_colors, "ghost_colors", i32, n_ghost) if n_ghost > 0 else None,
+                              seed & 0xFFFFFFFF, _dev_ptr(out, "owned_colors", i32, n_owned),
+                              _dev_ptr(rl, "remote_loser") if rl is not None else None,
+                              ctypes.byref(st), _params(params), _stream(stream))
+    _check(rc, "color_d2_ghost")
+    return out, (rl[:n_ghost] if rl is not None else None), _to_stats(st, buf)
+
+
+def color_pd2_ghost(n_owned, n_ghost, n_rows, col_ptr, row_idx, row_ptr, col_idx, gid, ghost_colors, seed=1,
+                    out=None, remote_loser=True, params=None, stream=None, trace_cap=0):
+    """One rank's partial distance-2 step on its local pattern.  Returns
+    (owned column colors, remote-loser flags or None, Stats)."""
+    torch = _torch()
+    i32 = torch.int32
+    dev = col_ptr.device
+    if out is None:
+        out = torch.empty(max(n_owned, 0), dtype=i32, device=dev)
+    rl = torch.empty(max(n_ghost, 1), dtype=torch.uint8, device=dev) if remote_loser else None
+    st, buf = _stats(trace_cap)
+    rc = lib().color_pd2_ghost(n_owned, n_ghost, n_rows, _dev_ptr(col_ptr, "col_ptr", i32),
+                               _dev_ptr(row_idx, "row_idx", i32), _dev_ptr(row_ptr, "row_ptr", i32),
+                               _dev_ptr(col_idx, "col_idx", i32), _dev_ptr(gid, "gid", i32),
+                               _dev_ptr(ghost_colors, "ghost_colors", i32, n_ghost) if n_ghost > 0 else None,
+                               seed & 0xFFFFFFFF, _dev_ptr(out, "owned_colors", i32, n_owned),
+                               _dev_ptr(rl, "remote_loser") if rl is not None else None,
+                               ctypes.byref(st), _params(params), _stream(stream))
+    _check(rc, "color_pd2_ghost")
     return out, (rl[:n_ghost] if rl is not None else None), _to_stats(st, buf)
 
 

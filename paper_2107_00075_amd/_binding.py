@@ -42,6 +42,7 @@ EXPORTED = [
     "color_batch", "color_server_create", "color_server_submit", "color_server_poll",
     "color_server_drain", "color_server_destroy", "color_release_workspace", "color_strerror",
     "color_autotune", "color_autotune_reset", "color_d1_noalloc", "color_d1_distributed",
+    "color_d2_ghost", "color_pd2_ghost",
 ]
 
 
@@ -184,6 +185,10 @@ def lib():
         l.color_d1_ghost_step.argtypes = [I32, I32, I32, I32, P, P, P, P, P, U32, P, P, P, SP, PP, P]
         l.color_d1_distributed.restype = ctypes.c_int
         l.color_d1_distributed.argtypes = [I32, ctypes.POINTER(CPart), U32, I32, ctypes.POINTER(CDistStats), PP, P]
+        l.color_d2_ghost.restype = ctypes.c_int
+        l.color_d2_ghost.argtypes = [I32, I32, I32, P, P, P, P, U32, P, P, SP, PP, P]
+        l.color_pd2_ghost.restype = ctypes.c_int
+        l.color_pd2_ghost.argtypes = [I32, I32, I32, P, P, P, P, P, P, U32, P, P, SP, PP, P]
         l.color_priority.restype = ctypes.c_int
         l.color_priority.argtypes = [I32, P, U32, P, P]
         l.color_batch.restype = ctypes.c_int

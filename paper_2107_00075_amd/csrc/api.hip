@@ -1163,6 +1163,106 @@ int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_
   return finish_call(c, stats, c.H->aux_max, rc);
 }
 
+}  // extern "C"
+
+namespace gcol {
+
+// One rank's distance-2 (MODE kD2) or partial distance-2 (kPD2) step:
+// ghost-uncolored phase 1 on the owned vertices (the two-hop walks pass
+// through ghosts, whose colors and tentative colors are 0), the two-hop
+// boundary detect against the ghosts' fixed colors, and the recoloring of the
+// owned losers with the ghosts' colors as constraints.  Pull engine.
+template <int MODE>
+static int ghost2_step(int32_t n_owned, int32_t n_ghost, const int32_t* rp1, const int32_t* ci1, const int32_t* rp2,
+                       const int32_t* ci2, const int32_t* gid, const int32_t* ghost_colors, uint32_t seed,
+                       int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats, const color_params* params,
+                       void* stream) {
+  if (n_owned < 0 || n_ghost < 0) return COLOR_EINVAL;
+  if (static_cast<int64_t>(n_owned) + n_ghost >= INT_MAX) return COLOR_EOVERFLOW;
+  if (n_owned > 0 && (!rp1 || !ci1 || !rp2 || !ci2 || !gid || !owned_colors)) return COLOR_EINVAL;
+  if (n_ghost > 0 && (!ghost_colors || !gid)) return COLOR_EINVAL;
+  if (params && params->engine == COLOR_ENGINE_INCREMENTAL) return COLOR_EINVAL;
+  const int32_t m = n_owned + n_ghost;
+  Call c;
+  int e = begin_call(c, MODE, params, stats, stream, n_owned, m);
+  if (e) return e;
+  std::unique_lock<std::mutex> lk(c.ws->mu);
+  if (n_owned == 0) return finish_call(c, stats, 0, COLOR_OK);
+  Workspace* w = c.ws;
+  if ((e = w->C.ensure(sizeof(int32_t) * static_cast<size_t>(m), false, c.st))) return e;
+  if ((e = w->aux0.ensure(sizeof(int32_t) * static_cast<size_t>(n_owned), false, c.st))) return e;
+  if ((e = w->aux1.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n_ghost, 1)), false, c.st))) return e;
+  int32_t* Cint = w->C.as<int32_t>();
+  KeySource k{nullptr, gid, hash_seed(seed), nullptr};
+  // phase 1: ghosts uncolored (0 constrains nothing and never ties)
+  launch_zero_words(Cint + n_owned, static_cast<size_t>(n_ghost), c.st);
+  launch_zero_words(w->T.as<int32_t>() + n_owned, static_cast<size_t>(n_ghost), c.st);
+  c.launches += 2;
+  GraphView g{n_owned, n_owned, rp1, ci1, rp2, ci2};
+  g.limit = m;
+  BinLayout L;
+  RoundBufs rb;
+  int32_t known[kBins];
+  if ((e = setup_bins<MODE>(c, g, nullptr, Cint, m, L, rb, known))) return e;
+  int rc = run_phase<MODE>(c, g, k, L, rb, known, 0, c.P.max_rounds);
+  if (rc != COLOR_OK) return rc == COLOR_ENOCONVERGE ? finish_call(c, stats, -1, rc) : rc;
+  if (hipMemcpyAsync(&c.H->rounds_done, &c.S->rounds_done, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) !=
+      hipSuccess)
+    return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  const int r1 = c.H->rounds_done;
+  // phase 2: owned vertices against the distinct ghosts of their two-hop
+  // neighbourhoods (Algorithm 5 over the owned vertices)
+  int32_t* loser = w->aux0.as<int32_t>();
+  int32_t* gflag = w->aux1.as<int32_t>();
+  launch_zero_words(gflag, static_cast<size_t>(std::max(n_ghost, 1)), c.st);
+  launch_boundary2<MODE>(g, n_owned, Cint, ghost_colors, k, loser, gflag, &c.S->conflicts, c.st);
+  launch_boundary_uncolor(n_owned, loser, Cint, c.st);
+  // phase 3: ghosts carry their fixed colors; the losers are recolored
+  launch_ghost_fill(n_owned, n_ghost, ghost_colors, Cint, rb.T, &c.S->maxc, c.st);
+  c.launches += 4;
+  launch_zero_words(c.S->cnt[0], 8, c.st);
+  launch_scatter(n_owned, Cint, w->bin.as<int8_t>(), L, c.wl[0], c.S->cnt[0], w->split_vertex.as<int32_t>(), c.st);
+  c.launches += 2;
+  if (hipMemcpyAsync(c.H->cnt[0], c.S->cnt[0], sizeof(int32_t) * 8, hipMemcpyDeviceToHost, c.st) != hipSuccess)
+    return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  for (int i = 0; i < kBins; ++i) known[i] = c.H->cnt[0][i];
+  rc = run_phase<MODE>(c, g, k, L, rb, known, r1, c.P.max_rounds);
+  if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
+  launch_flags_out(n_ghost, gflag, remote_loser, &c.S->remote, c.st);
+  launch_copy_i32(n_owned, Cint, owned_colors, c.st);
+  launch_max_i32(n_owned, Cint, &c.S->aux_max, c.st);
+  c.launches += 3;
+  if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
+  if (hipMemcpyAsync(&c.H->aux_max, &c.S->aux_max, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) != hipSuccess)
+    return COLOR_EHIP;
+  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
+  return finish_call(c, stats, c.H->aux_max, rc);
+}
+
+}  // namespace gcol
+
+extern "C" {
+
+int color_d2_ghost(int32_t n_owned, int32_t n_ghost, int32_t n_g1, const int32_t* row_ptr, const int32_t* col_idx,
+                   const int32_t* gid, const int32_t* ghost_colors, uint32_t seed, int32_t* owned_colors,
+                   uint8_t* remote_loser, color_stats* stats, const color_params* params, void* stream) {
+  if (n_g1 < 0 || n_g1 > n_ghost) return COLOR_EINVAL;
+  return ghost2_step<kD2>(n_owned, n_ghost, row_ptr, col_idx, row_ptr, col_idx, gid, ghost_colors, seed,
+                          owned_colors, remote_loser, stats, params, stream);
+}
+
+int color_pd2_ghost(int32_t n_owned, int32_t n_ghost, int32_t n_rows, const int32_t* col_ptr, const int32_t* row_idx,
+                    const int32_t* row_ptr, const int32_t* col_idx, const int32_t* gid, const int32_t* ghost_colors,
+                    uint32_t seed, int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats,
+                    const color_params* params, void* stream) {
+  if (n_rows < 0) return COLOR_EINVAL;
+  if (n_owned > 0 && n_rows == 0 && (!col_ptr || !row_idx)) return COLOR_EINVAL;
+  return ghost2_step<kPD2>(n_owned, n_ghost, col_ptr, row_idx, row_ptr, col_idx, gid, ghost_colors, seed,
+                           owned_colors, remote_loser, stats, params, stream);
+}
+
 int color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1, const int32_t* row_ptr,
                    const int32_t* col_idx, const int32_t* gid, const int32_t* ghost_colors, uint32_t seed,
                    int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats, const color_params* params,

@@ -396,6 +396,60 @@ __global__ __launch_bounds__(kBlock) void boundary_kernel(int32_t n_owned, const
   if (lane_id() == 0 && tot) atomicAdd(conflicts, static_cast<unsigned long long>(tot));
 }
 
+// Distance-2 / partial distance-2 ghost phase 2 (Algorithm 5 over the owned
+// vertices): every owned vertex walks its two-hop neighbourhood (MODE's
+// walk, the walk of scan_nbhd); each distinct ghost x with the vertex's color
+// is a conflict judged by the key rule on the ghosts' fixed colors.  A walk
+// can reach x along several paths: an entry counts only if x does not occur
+// earlier in the walk (checked by re-walking, which only conflicting
+// entries pay for).
+template <int MODE, typename F>
+__device__ __forceinline__ void walk2(const GraphView& g, int32_t v, F&& f) {
+  int64_t pos = 0;
+  for (int32_t e = g.rp[v]; e < g.rp[v + 1]; ++e) {
+    const int32_t u = g.ci[e];
+    if (MODE == kD2) {
+      if (f(u, pos++)) return;
+    }
+    for (int32_t q = g.rp2[u]; q < g.rp2[u + 1]; ++q) {
+      const int32_t x = g.ci2[q];
+      if (x != v && f(x, pos++)) return;
+    }
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void boundary2_kernel(GraphView g, int32_t n_owned, const int32_t* C,
+                                                           const int32_t* ghost_colors, KeySource k, int32_t* loser,
+                                                           int32_t* gflag, unsigned long long* conflicts) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  uint32_t found = 0;
+  if (v < n_owned) {
+    const int32_t cv = ld_dev(&C[v]);
+    const uint64_t kv = key_of(k, v);
+    bool lose = false;
+    walk2<MODE>(g, v, [&](int32_t x, int64_t at) {
+      if (x < n_owned || ghost_colors[x - n_owned] != cv) return false;
+      bool earlier = false;
+      walk2<MODE>(g, v, [&](int32_t y, int64_t p) {
+        if (p >= at) return true;
+        earlier = y == x;
+        return earlier;
+      });
+      if (earlier) return false;
+      ++found;
+      if (key_of(k, x) > kv) lose = true;
+      else st_dev(&gflag[x - n_owned], 1);
+      return false;
+    });
+    st_dev(&loser[v], lose ? 1 : 0);
+  }
+  uint64_t tot = found;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) tot += __shfl_xor(tot, off, kWave);
+  if (lane_id() == 0 && tot) atomicAdd(conflicts, static_cast<unsigned long long>(tot));
+}
+
 __global__ __launch_bounds__(kBlock) void boundary_uncolor_kernel(int32_t n_owned, const int32_t* loser,
                                                                   int32_t* C) {
   const int32_t v = blockIdx.x * kBlock + threadIdx.x;
@@ -572,6 +626,19 @@ void launch_ghost_recolor_init(int32_t n_owned, int32_t n3, const int32_t* C, co
     hipLaunchKernelGGL(ghost_recolor_init_kernel, dim3(blocks_for(n3)), dim3(kBlock), 0, st, n_owned, n3, C, gc,
                        gflag, init);
 }
+
+template <int MODE>
+void launch_boundary2(const GraphView& g, int32_t n_owned, const int32_t* C, const int32_t* ghost_colors,
+                      const KeySource& k, int32_t* loser, int32_t* gflag, unsigned long long* conflicts,
+                      hipStream_t st) {
+  if (n_owned > 0)
+    hipLaunchKernelGGL(boundary2_kernel<MODE>, dim3(blocks_for(n_owned)), dim3(kBlock), 0, st, g, n_owned, C,
+                       ghost_colors, k, loser, gflag, conflicts);
+}
+template void launch_boundary2<kD2>(const GraphView&, int32_t, const int32_t*, const int32_t*, const KeySource&,
+                                    int32_t*, int32_t*, unsigned long long*, hipStream_t);
+template void launch_boundary2<kPD2>(const GraphView&, int32_t, const int32_t*, const int32_t*, const KeySource&,
+                                     int32_t*, int32_t*, unsigned long long*, hipStream_t);
 
 void launch_ghost_fill(int32_t n_owned, int32_t n_ghost, const int32_t* gc, int32_t* C, int32_t* T,
                        int32_t* maxc, hipStream_t st) {

@@ -40,6 +40,10 @@ void launch_priority(int32_t n, const int32_t* gid, uint32_t hs, uint32_t* out, 
 void launch_boundary(int32_t n_owned, const int32_t* rp, const int32_t* ci, const int32_t* C,
                      const int32_t* ghost_colors, const KeySource& k, int32_t* loser, int32_t* gflag,
                      unsigned long long* conflicts, hipStream_t st);
+template <int MODE>
+void launch_boundary2(const GraphView& g, int32_t n_owned, const int32_t* C, const int32_t* ghost_colors,
+                      const KeySource& k, int32_t* loser, int32_t* gflag, unsigned long long* conflicts,
+                      hipStream_t st);
 void launch_boundary_uncolor(int32_t n_owned, const int32_t* loser, int32_t* C, hipStream_t st);
 void launch_ghost_fill(int32_t n_owned, int32_t n_ghost, const int32_t* gc, int32_t* C, int32_t* T,
                        int32_t* maxc, hipStream_t st);
