@@ -33,7 +33,13 @@ Other workloads (one JSON line each, same keys):
                        4,000,000 x 1,000,000 power-law pattern
     --workload ghost   one rank's ghost-layer step (color_d1_ghost) on part 0
                        of a 16-way hash partition of R-MAT scale 24, with 1
-                       and 2 ghost layers, plus property checks
+                       and 2 ghost layers, fixed ghosts and tentative ghost
+                       recoloring, plus property checks
+    --workload dist    Algorithm 2 over all 16 ranks of that partition on one
+                       GPU (color_d1_distributed)
+    --workload ghost2  the distance-2 step on a slab of the 7-point mesh 96^3
+                       and the partial distance-2 step on part 0 of the PD2
+                       pattern (color_d2_ghost, color_pd2_ghost)
 
 Profiling helpers (no GPU):
     --summarize-pmc FETCH_DIR WRITE_DIR   turns two rocprofv3 --pmc runs
@@ -605,13 +611,25 @@ def bench_serve(args, torch, gc, dev):
 # ghost-layer step on one part of a partitioned graph
 # ---------------------------------------------------------------------------
 
+def _timed(torch, args, fn):
+    for _ in range(args.warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = fn()
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t0) / args.steps
+
+
 def bench_ghost(args, torch, gc, dev):
     """One rank's step (color_d1_ghost) on part 0 of a 16-way hash partition
-    of R-MAT scale `--ghost-scale`, with 1 and 2 ghost layers.  Checks
-    properties that hold at any size: owned colors proper among owned
+    of R-MAT scale `--ghost-scale`, with 1 and 2 ghost layers, with the ghosts'
+    colors fixed and with tentative ghost recoloring (Section 3.2 / 3.4).
+    Checks properties that hold at any size: owned colors proper among owned
     vertices, every owned-ghost pair still equal after the step has its ghost
-    flagged as a remote loser, and the 2-layer result equal to the 1-layer
-    one."""
+    flagged as a remote loser, and (fixed ghosts) the 2-layer result equal to
+    the 1-layer one."""
     import numpy as np
 
     import graphgen as gg
@@ -621,7 +639,8 @@ def bench_ghost(args, torch, gc, dev):
     log(f"[bench] rmat s{args.ghost_scale}: n={g.n} nnz={g.nnz} maxdeg={delta} ({time.time() - t:.1f}s)")
     owner = gg.hash_partition(g.n, 16, seed=7)
     gcol = gg.ghost_colors_uniform(g.n, delta, seed=11)
-    res = {}
+    res, rec = {}, {}
+    kern = {}
     for layers in (1, 2):
         t = time.time()
         log(f"[bench] building part 0 with {layers} ghost layer(s)")
@@ -631,24 +650,28 @@ def bench_ghost(args, torch, gc, dev):
         rp, ci, gid, gco = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
                             for a in (lg.row_ptr, lg.col, lg.gid, lg.ghost_colors))
         out = torch.empty(lg.n_owned, dtype=torch.int32, device=dev)
-
-        def step():
-            return gc.color_d1_ghost(lg.n_owned, lg.n_ghost, layers, lg.n_g1, rp, ci, gid, gco, seed=1, out=out)
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            colors, rl, st = step()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        colors = colors.cpu().numpy()
-        rl = rl.cpu().numpy()
+        timing = gc.Params(flags=gc.COLOR_FLAG_KERNEL_TIMING)
+        (colors, rl, st), dt = _timed(torch, args, lambda: gc.color_d1_ghost(
+            lg.n_owned, lg.n_ghost, layers, lg.n_g1, rp, ci, gid, gco, seed=1, out=out, params=timing))
+        colors, rl = colors.cpu().numpy(), rl.cpu().numpy()
         owned_nnz = int(lg.row_ptr[lg.n_owned])
         res[layers] = {"colors": colors, "rl": rl, "st": st, "ms": dt * 1e3, "lg": lg, "owned_nnz": owned_nnz}
         log(f"[bench] {layers} layer(s): {dt * 1e3:.2f} ms, colors {st.num_colors}, rounds {st.rounds}, "
-            f"conflicts {st.boundary_conflicts}, remote losers {st.remote_losers}")
+            f"conflicts {st.boundary_conflicts}, remote losers {st.remote_losers}, engine {st.engine}")
+        if layers == 1:
+            names = ("inc_color_kernel", "inc_detect_kernel") if st.engine == gc.ENGINE_INCREMENTAL else \
+                ("color_round_kernel<D1>", "detect_round_kernel<D1>")
+            cb, db = (st.color_bytes, st.detect_bytes) if st.engine == gc.ENGINE_INCREMENTAL else d1_kernel_bytes(st)
+            for kname, byts, ns, nl in kernel_rows(gc, st, names, cb, db):
+                kern[kname] = (byts, ns, nl)
+        grp = gc.Params(flags=gc.COLOR_FLAG_GHOST_RECOLOR)
+        (c2, rl2, st2), dt2 = _timed(torch, args, lambda: gc.color_d1_ghost(
+            lg.n_owned, lg.n_ghost, layers, lg.n_g1, rp, ci, gid, gco, seed=1, out=out, params=grp))
+        rec[layers] = {"ms": round(dt2 * 1e3, 3), "colors": st2.num_colors, "rounds": st2.rounds,
+                       "boundary_conflicts": st2.boundary_conflicts, "remote_losers": st2.remote_losers,
+                       "differs_from_fixed_ghosts": int(np.count_nonzero(c2.cpu().numpy() != colors))}
+        log(f"[bench] {layers} layer(s), tentative ghost recoloring: {dt2 * 1e3:.2f} ms, {st2.num_colors} colors")
+        del rp, ci, gid, gco
     # properties on the 1-layer local graph
     lg = res[1]["lg"]
     colors, rl = res[1]["colors"], res[1]["rl"]
@@ -663,6 +686,24 @@ def bench_ghost(args, torch, gc, dev):
     same_layers = bool(np.array_equal(res[1]["colors"], res[2]["colors"]) and
                        np.array_equal(res[1]["rl"], res[2]["rl"][:res[1]["rl"].size]))
     st1 = res[1]["st"]
+    roofline = None
+    if kern:
+        dom = max(kern, key=lambda k: kern[k][1])
+        b_, ns, nl = kern[dom]
+        ach = b_ / ns if ns else 0.0
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "avg_launch_us": round(ns / max(nl, 1) / 1e3, 3), "alg_bytes_per_launch": int(b_ / max(nl, 1))}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        t0 = time.perf_counter()
+        r = oracle.color_d1_ghost(lg, seed=1)
+        secs = time.perf_counter() - t0
+        assert np.array_equal(r.colors, colors), "oracle and GPU differ on part 0"
+        cpu = {"value": round(res[1]["owned_nnz"] / secs, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": f"the same step (part 0, 1 layer), single-threaded C oracle, {secs:.1f}s"}
     return {
         "metric": "edges colored/s (D1 ghost-layer step, part 0 of 16)",
         "value": round(res[1]["owned_nnz"] / (res[1]["ms"] / 1e3), 1),
@@ -684,11 +725,158 @@ def bench_ghost(args, torch, gc, dev):
                                        "rounds": v["st"].rounds,
                                        "boundary_conflicts": v["st"].boundary_conflicts,
                                        "remote_losers": v["st"].remote_losers} for k, v in res.items()},
+                   "tentative_ghost_recoloring": {str(k): v for k, v in rec.items()},
                    "checks": {"owned_proper": proper, "equal_pairs_flagged": flagged,
                               "two_layers_equal_one": same_layers}},
-        "roofline": None,
-        "cpu_baseline": None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
         "boundary_conflicts": st1.boundary_conflicts,
+    }
+
+
+def bench_dist(args, torch, gc, dev):
+    """Algorithm 2 over 16 ranks on one GPU (color_d1_distributed): R-MAT
+    scale `--ghost-scale` split 16 ways by hash, every rank's local graph
+    with one ghost layer resident; one step = the whole distributed coloring
+    (initial colorings, exchanges, detections, recolorings until no
+    conflict), with the hash key, recolorDegrees and tentative ghost
+    recoloring."""
+    import numpy as np
+
+    import graphgen as gg
+    t = time.time()
+    g = gg.rmat(args.ghost_scale, 16, seed=1, progress=lambda m: log(f"[bench] {m} ({time.time() - t:.0f}s)"))
+    log(f"[bench] rmat s{args.ghost_scale}: n={g.n} nnz={g.nnz} ({time.time() - t:.1f}s)")
+    owner = gg.hash_partition(g.n, 16, seed=7)
+    zeros = np.zeros(g.n, np.int32)
+    deg = g.degrees()
+    parts, locs = [], []
+    for p in range(16):
+        lg = gg.ghost_local_graph(g, owner, p, 1, zeros, sort_rows=False)
+        locs.append(lg)
+    homes = gg.ghost_homes(locs)
+    for lg, (o, i) in zip(locs, homes):
+        d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)  # noqa: E731
+        parts.append(dict(n_owned=lg.n_owned, n_ghost=lg.n_ghost, layers=1, n_g1=lg.n_g1, row_ptr=d(lg.row_ptr),
+                          col_idx=d(lg.col), gid=d(lg.gid), ghost_owner=d(o), ghost_index=d(i),
+                          ghost_degree=d(deg[lg.gid[lg.n_owned:]])))
+    log(f"[bench] 16 local graphs resident ({time.time() - t:.1f}s)")
+    out = {}
+    for name, flags in (("hash_key", 0), ("recolor_degrees", gc.COLOR_FLAG_RECOLOR_DEGREES),
+                        ("ghost_recoloring", gc.COLOR_FLAG_GHOST_RECOLOR)):
+        few = argparse.Namespace(steps=min(args.steps, 2), warmup=min(args.warmup, 1))
+        (cols, st), dt = _timed(torch, few, lambda: gc.color_d1_distributed(parts, seed=1,
+                                                                          params=gc.Params(flags=flags)))
+        out[name] = {"ms": round(dt * 1e3, 3), "colors": st.num_colors, "detects": st.detects,
+                     "iterations": st.iterations, "conflicts": st.conflicts, "exchanged": st.exchanged,
+                     "exchanged_bytes": 8 * st.exchanged_total, "rounds_total": st.rounds_total}
+        log(f"[bench] Algorithm 2, {name}: {dt * 1e3:.1f} ms, {st.num_colors} colors, {st.detects} detections, "
+            f"{8 * st.exchanged_total} bytes exchanged")
+        if name == "hash_key":
+            C = np.zeros(g.n, np.int32)
+            for lg, c in zip(locs, cols):
+                C[lg.gid[:lg.n_owned]] = c.cpu().numpy()
+            src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+            out[name]["proper"] = bool(np.all(C[src] != C[g.col]))
+    rp, ci = torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev)
+    (_, st1), dt1 = _timed(torch, args, lambda: gc.color_d1(rp, ci, seed=1))
+    one = {"ms": round(dt1 * 1e3, 3), "colors": st1.num_colors, "rounds": st1.rounds}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        small = gg.rmat(19, 16, seed=1)
+        ow = gg.hash_partition(small.n, 16, seed=7)
+        sl = [gg.ghost_local_graph(small, ow, p, 1, np.zeros(small.n, np.int32)) for p in range(16)]
+        t0 = time.perf_counter()
+        oracle.color_d1_distributed(sl, seed=1)
+        secs = time.perf_counter() - t0
+        cpu = {"value": round(small.nnz / secs, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": f"Algorithm 2 over 16 ranks of R-MAT scale 19 ef16 (1/32 of the graph), single-threaded "
+                         f"C oracle per rank step, {secs:.1f}s"}
+    base = out["hash_key"]
+    return {
+        "metric": "edges colored/s (Algorithm 2 over 16 ranks on one GPU)",
+        "value": round(g.nnz / (base["ms"] / 1e3), 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": base["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"R-MAT s{args.ghost_scale} ef16 seed 1 split 16 ways by hash (seed 7), one ghost "
+                               f"layer, every rank resident; exchanges by gather kernel",
+                   "variants": out, "single_gpu_color_d1": one},
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+
+
+def bench_ghost2(args, torch, gc, dev):
+    """One rank's distance-2 step (color_d2_ghost) on a middle slab of the
+    7-point mesh 96^3 split into 16 slabs along z, and one rank's partial
+    distance-2 step (color_pd2_ghost) on part 0 of the 4,000,000 x 1,000,000
+    power-law pattern split 16 ways by column hash; ghost colors uniform in
+    [1, 25] (mesh: the distance-2 neighbourhood has 24 members) and [1, 64]."""
+    import numpy as np
+
+    import graphgen as gg
+    t = time.time()
+    dims = (96, 96, 96)
+    mesh = gg.stencil(dims, 7)
+    lg = gg.ghost_local_graph(mesh, gg.slab_partition(dims, 16), 1, 2,
+                              np.random.default_rng(11).integers(1, 26, mesh.n).astype(np.int32))
+    b = gg.bipartite_powerlaw(4_000_000, 1_000_000, 8, 2.1, seed=1)
+    lp = gg.pd2_local_pattern(b, gg.hash_partition(b.n_cols, 16, seed=7), 0,
+                              np.random.default_rng(12).integers(1, 65, b.n_cols).astype(np.int32))
+    log(f"[bench] D2 slab: owned {lg.n_owned}, ghosts {lg.n_ghost}; PD2 part 0: owned {lp.n_owned} columns, "
+        f"ghosts {lp.n_ghost}, rows {lp.n_rows} ({time.time() - t:.1f}s)")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)  # noqa: E731
+    m_args = (lg.n_owned, lg.n_ghost, lg.n_g1, d(lg.row_ptr), d(lg.col), d(lg.gid), d(lg.ghost_colors))
+    p_args = (lp.n_owned, lp.n_ghost, lp.n_rows, d(lp.col_ptr), d(lp.row_idx), d(lp.row_ptr), d(lp.col_idx),
+              d(lp.gid), d(lp.ghost_colors))
+    (c1, r1, s1), dt1 = _timed(torch, args, lambda: gc.color_d2_ghost(*m_args, seed=1))
+    (c2, r2, s2), dt2 = _timed(torch, args, lambda: gc.color_pd2_ghost(*p_args, seed=1))
+    m_nnz = int(lg.row_ptr[lg.n_owned])
+    p_nnz = int(lp.col_ptr[lp.n_owned])
+    res = {"d2_mesh_slab": {"ms": round(dt1 * 1e3, 3), "owned": lg.n_owned, "ghosts": lg.n_ghost,
+                            "owned_row_nnz": m_nnz, "colors": s1.num_colors, "rounds": s1.rounds,
+                            "boundary_conflicts": s1.boundary_conflicts, "remote_losers": s1.remote_losers},
+           "pd2_part0": {"ms": round(dt2 * 1e3, 3), "owned": lp.n_owned, "ghosts": lp.n_ghost, "rows": lp.n_rows,
+                         "owned_col_nnz": p_nnz, "colors": s2.num_colors, "rounds": s2.rounds,
+                         "boundary_conflicts": s2.boundary_conflicts, "remote_losers": s2.remote_losers}}
+    log(f"[bench] D2 ghost: {dt1 * 1e3:.2f} ms; PD2 ghost: {dt2 * 1e3:.2f} ms")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        t0 = time.perf_counter()
+        ref = oracle.color_d2_ghost(lg, seed=1)
+        secs = time.perf_counter() - t0
+        assert np.array_equal(ref.colors, c1.cpu().numpy()), "oracle and GPU differ on the mesh slab"
+        cpu = {"value": round(m_nnz / secs, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": f"the D2 mesh-slab step, single-threaded C oracle, {secs:.1f}s"}
+    return {
+        "metric": "edges colored/s (D2 + PD2 ghost-layer steps)",
+        "value": round((m_nnz + p_nnz) / (dt1 + dt2), 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round((dt1 + dt2) * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "D2: 7-pt mesh 96^3 in 16 z-slabs, slab 1, 2 ghost layers; PD2: 4,000,000 x "
+                               "1,000,000 power-law pattern, 16-way column hash, part 0", "steps": res},
+        "roofline": None,
+        "cpu_baseline": cpu,
     }
 
 
@@ -767,7 +955,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-d2pd2", action="store_true", help="d1: skip the D2 + PD2 block of the line")
-    ap.add_argument("--workload", default="d1", choices=["d1", "d2pd2", "batch", "serve", "ghost"])
+    ap.add_argument("--workload", default="d1", choices=["d1", "d2pd2", "batch", "serve", "ghost", "dist", "ghost2"])
     ap.add_argument("--ghost-scale", type=int, default=24, help="ghost: R-MAT scale of the partitioned graph")
     ap.add_argument("--jobs", type=int, default=300, help="batch/serve: jobs in the stream")
     ap.add_argument("--n-max", type=float, default=3e4, help="batch/serve: largest job size (vertices)")
@@ -802,6 +990,10 @@ def main():
         out = bench_serve(args, torch, gc, dev)
     elif args.workload == "ghost":
         out = bench_ghost(args, torch, gc, dev)
+    elif args.workload == "dist":
+        out = bench_dist(args, torch, gc, dev)
+    elif args.workload == "ghost2":
+        out = bench_ghost2(args, torch, gc, dev)
     elif args.workload == "d2pd2":
         out = bench_d2pd2(args, torch, gc, dev)
     else:

@@ -446,15 +446,40 @@ int orc_color_d1_ghost(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t
     if (remote_loser)
         for (int32_t j = 0; j < n_ghost; j++) remote_loser[j] = 0;
 
-    /* phase 1: ghost-blind rounds on the owned-induced subgraph */
+    /* phase 1: ghost-blind rounds on the owned-induced subgraph: the owned
+     * rows without their ghost entries (a vertex's visit reads only its
+     * owned neighbours) */
+    {
+        int32_t *rp1 = (int32_t *)calloc((size_t)n_owned + 1, sizeof(int32_t));
+        int32_t *col1;
+        int32_t k1 = 0;
+        graph_t g1;
+        for (int32_t v = 0; v < n_owned; v++)
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+                if (col[e] < n_owned) rp1[v + 1]++;
+        for (int32_t v = 0; v < n_owned; v++) rp1[v + 1] += rp1[v];
+        col1 = (int32_t *)malloc((size_t)(rp1[n_owned] > 0 ? rp1[n_owned] : 1) * sizeof(int32_t));
+        for (int32_t v = 0; v < n_owned; v++)
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; e++)
+                if (col[e] < n_owned) col1[k1++] = col[e];
+        g1.kind = 1;
+        g1.n = n_owned;
+        g1.row_ptr = rp1;
+        g1.col = col1;
+        g1.col_ptr = NULL;
+        g1.row_idx = NULL;
+        rc.g = &g1;
+        rc.n = n_owned;
+        rc.n_base = n_owned;
+        rc.ghost_col = ghost_colors;
+        rc.ignore_from = n_owned;
+        rc.max_rounds = INT32_MAX;
+        rc.eligible = NULL;
+        r1 = run_rounds(&rc, owned_colors, st, 0);
+        free(rp1);
+        free(col1);
+    }
     rc.g = &g;
-    rc.n = n_owned;
-    rc.n_base = n_owned;
-    rc.ghost_col = ghost_colors;
-    rc.ignore_from = n_owned;
-    rc.max_rounds = INT32_MAX;
-    rc.eligible = NULL;
-    r1 = run_rounds(&rc, owned_colors, st, 0);
 
     /* phase 2: every owned-ghost edge against the fixed ghost colors, all
      * pairs judged on the phase-1 colors (Algorithm 3 with Algorithm 4) */

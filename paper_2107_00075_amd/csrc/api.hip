@@ -74,7 +74,7 @@ std::array<DevBuf*, Workspace::kNumBuffers> Workspace::buffers() {
           &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
           &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &inc_wl0, &inc_wl1, &scan_tmp,
           &deferred_work, &deferred_done, &rank, &rk_key0, &rk_key1, &rk_val0, &rk_val1, &rk_deg0,
-          &rk_deg1, &rk_tmp, &gr_rp, &gr_ci, &gr_cnt, &gr_init};
+          &rk_deg1, &rk_tmp, &gr_rp, &gr_ci, &gr_cnt, &gr_init, &own_rp, &own_ci, &pair_set};
 }
 
 void Workspace::release() {
@@ -796,6 +796,54 @@ int validate_job(const color_job& j, void* stream) {
   return validate_graph<kPD2>(c, j.n, j.n_rows, j.col_ptr, j.row_idx, j.row_ptr, j.col_idx);
 }
 
+// Colors the uncolored vertices of g (colors[] is set up from init) on the
+// engine the parameters name, or the library's choice.  n_total: the ids
+// colors[] and the tentative colors cover.
+template <int MODE>
+static int run_engine(Call& c, const GraphView& g, const KeySource& k, const int32_t* init, int32_t* colors,
+                      int32_t n_total) {
+  const int32_t n = g.n;
+  BinLayout L;
+  RoundBufs rb;
+  int32_t known[kBins];
+  int e;
+  if (c.P.engine != COLOR_ENGINE_PULL) {
+    // bins without split units (the incremental engine has none; the pull
+    // engine only runs on them here for graphs without heavy vertices), and
+    // unless the caller set them, the incremental engine's own bounds: its
+    // active lists shrink round by round, and a vertex whose list is longer
+    // than one pass of a wavefront is faster on a whole workgroup
+    color_params saved = c.P;
+    c.P.bin_hi[3] = INT_MAX;
+    if (!c.user_bins) incremental_bins(MODE, c.P.bin_hi);
+    e = setup_bins<MODE>(c, g, init, colors, n_total, L, rb, known);
+    c.P = saved;
+    if (e) return e;
+    int64_t left = 0;
+    for (int i = 0; i < kBins; ++i) left += known[i];
+    // library choice: the incremental engine pays off when the work is
+    // concentrated in a few vertices that would be rescanned every round, or
+    // when two-hop walks are long (dense D2/PD2: every revisit of a vertex
+    // would re-walk thousands of entries; measured 2-12x faster)
+    const double avg = static_cast<double>(c.H->total_work) / std::max<int64_t>(1, n);
+    const bool skewed = c.H->max_work > 64 && c.H->max_work > 16.0 * std::max(1.0, avg);
+    const bool long_walks = MODE != kD1 && avg >= 128.0;
+    if (left > 0 && (c.P.engine == COLOR_ENGINE_INCREMENTAL || skewed || long_walks)) {
+      int fell_back = 0;
+      const int rc = run_incremental<MODE>(c, g, k, init, colors, L, known, &fell_back);
+      if (!fell_back) {
+        c.engine = COLOR_ENGINE_INCREMENTAL;
+        return rc;
+      }
+      // lists too large for int32 offsets: pull on the same worklists
+    }
+  } else {
+    if ((e = setup_bins<MODE>(c, g, init, colors, n_total, L, rb, known))) return e;
+  }
+  c.engine = COLOR_ENGINE_PULL;
+  return run_phase<MODE>(c, g, k, L, rb, known, 0, c.P.max_rounds);
+}
+
 // fixed_ws: a workspace of fixed buffers (the no-allocation entry point's
 // static scratch array, the server's heavy-lane regions of its arena): the
 // call allocates nothing, and a buffer asked for more than it holds fails
@@ -828,43 +876,7 @@ static int color_graph_once(int32_t n, int32_t n_rows, const int32_t* rp, const 
   if (c.P.flags & COLOR_FLAG_RECOLOR_DEGREES) {
     if ((e = degree_rank(c, n, g.rp, n, nullptr, k))) return e;
   }
-  BinLayout L;
-  RoundBufs rb;
-  int32_t known[kBins];
-  if (c.P.engine != COLOR_ENGINE_PULL) {
-    // bins without split units (the incremental engine has none; the pull
-    // engine only runs on them here for graphs without heavy vertices), and
-    // unless the caller set them, the incremental engine's own bounds: its
-    // active lists shrink round by round, and a vertex whose list is longer
-    // than one pass of a wavefront is faster on a whole workgroup
-    color_params saved = c.P;
-    c.P.bin_hi[3] = INT_MAX;
-    if (!c.user_bins) incremental_bins(MODE, c.P.bin_hi);
-    e = setup_bins<MODE>(c, g, init, colors, n, L, rb, known);
-    c.P = saved;
-    if (e) return e;
-    // library choice: the incremental engine pays off when the work is
-    // concentrated in a few vertices that would be rescanned every round, or
-    // when two-hop walks are long (dense D2/PD2: every revisit of a vertex
-    // would re-walk thousands of entries; measured 2-12x faster)
-    const double avg = static_cast<double>(c.H->total_work) / std::max<int64_t>(1, n);
-    const bool skewed = c.H->max_work > 64 && c.H->max_work > 16.0 * std::max(1.0, avg);
-    const bool long_walks = MODE != kD1 && avg >= 128.0;
-    if (c.P.engine == COLOR_ENGINE_INCREMENTAL || skewed || long_walks) {
-      int fell_back = 0;
-      const int rc = run_incremental<MODE>(c, g, k, init, colors, L, known, &fell_back);
-      if (!fell_back) {
-        if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
-        c.engine = COLOR_ENGINE_INCREMENTAL;
-        return finish_call(c, stats, -1, rc);
-      }
-      // lists too large for int32 offsets: pull on the same worklists
-    }
-  } else {
-    if ((e = setup_bins<MODE>(c, g, init, colors, n, L, rb, known))) return e;
-  }
-  c.engine = COLOR_ENGINE_PULL;
-  const int rc = run_phase<MODE>(c, g, k, L, rb, known, 0, c.P.max_rounds);
+  const int rc = run_engine<MODE>(c, g, k, init, colors, n);
   if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
   return finish_call(c, stats, -1, rc);
 }
@@ -1024,7 +1036,7 @@ int color_pd2(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr, const int3
                            col_colors, stats, params, stream);
 }
 
-int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1, const int32_t* row_ptr,
+static int ghost_step_once(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1, const int32_t* row_ptr,
                         const int32_t* col_idx, const int32_t* gid, const int32_t* ghost_colors,
                         const int32_t* ghost_degree, uint32_t seed, const int32_t* init_owned,
                         int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats,
@@ -1069,14 +1081,38 @@ int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_
     if ((e = degree_rank(c, m, row_ptr, n_owned, ghost_degree, k))) return e;
   }
   // phase 1: ghost-blind rounds on the owned-induced subgraph (with
-  // init_owned: only over the owned vertices it leaves uncolored)
-  GraphView g{n_owned, n_owned, row_ptr, col_idx, row_ptr, col_idx};
-  BinLayout L;
-  RoundBufs rb;
-  int32_t known[kBins];
-  if ((e = setup_bins<kD1>(c, g, init_owned, Cint, m, L, rb, known))) return e;
-  int rc = run_phase<kD1>(c, g, k, L, rb, known, 0, c.P.max_rounds);
+  // init_owned: only over the owned vertices it leaves uncolored), built
+  // once: the owned rows without their ghost entries, on either engine
+  int32_t owned_nnz = 0;
+  if ((e = read_nnz(c, row_ptr, n_owned, &owned_nnz))) return e;
+  {
+    const size_t n1 = static_cast<size_t>(n_owned) + 1;
+    const size_t e1 = static_cast<size_t>(owned_nnz) + 1;
+    size_t scan_bytes = 0;
+    if (exclusive_scan_i32(nullptr, nullptr, owned_nnz + 1, nullptr, &scan_bytes, c.st)) return COLOR_EHIP;
+    // own_rp: the subgraph's offsets, then the flags and their scan
+    if ((e = w->own_rp.ensure(sizeof(int32_t) * (n1 + 2 * e1), false, c.st)) ||
+        (e = w->scan_tmp.ensure(scan_bytes, false, c.st)))
+      return e;
+    int32_t* rp1 = w->own_rp.as<int32_t>();
+    int32_t* flag = rp1 + n1;
+    int32_t* pos = flag + e1;
+    if (launch_owned_subgraph(n_owned, owned_nnz, row_ptr, col_idx, flag, pos, rp1, nullptr, w->scan_tmp.p,
+                              w->scan_tmp.bytes, c.st))
+      return COLOR_EHIP;
+    int32_t nnz1 = 0;
+    if ((e = read_nnz(c, pos, owned_nnz, &nnz1))) return e;
+    if ((e = w->own_ci.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(nnz1, 1)), false, c.st))) return e;
+    launch_owned_subgraph(n_owned, owned_nnz, row_ptr, col_idx, flag, pos, rp1, w->own_ci.as<int32_t>(), nullptr, 0,
+                          c.st);
+    c.launches += 3;
+  }
+  GraphView g1{n_owned, n_owned, w->own_rp.as<int32_t>(), w->own_ci.as<int32_t>(), w->own_rp.as<int32_t>(),
+               w->own_ci.as<int32_t>()};
+  int rc = run_engine<kD1>(c, g1, k, init_owned, Cint, m);
   if (rc != COLOR_OK) return rc == COLOR_ENOCONVERGE ? finish_call(c, stats, -1, rc) : rc;
+  // phases 2 and 3 read the full local rows
+  GraphView g{n_owned, n_owned, row_ptr, col_idx, row_ptr, col_idx};
   if (hipMemcpyAsync(&c.H->rounds_done, &c.S->rounds_done, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) !=
       hipSuccess)
     return COLOR_EHIP;
@@ -1087,21 +1123,29 @@ int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_
   int32_t* gflag = w->aux1.as<int32_t>();
   if (hipMemsetAsync(gflag, 0, sizeof(int32_t) * static_cast<size_t>(std::max(n_ghost, 1)), c.st) != hipSuccess)
     return COLOR_EHIP;
-  launch_boundary(n_owned, row_ptr, col_idx, Cint, ghost_colors, k, loser, gflag, &c.S->conflicts, c.st);
+  launch_zero_words(loser, static_cast<size_t>(n_owned), c.st);
+  launch_boundary(n_owned, owned_nnz, row_ptr, col_idx, Cint, ghost_colors, k, loser, gflag, &c.S->conflicts, c.st);
   launch_boundary_uncolor(n_owned, loser, Cint, c.st);
   // phase 3: ghosts become fixed committed colors; losers are recolored
-  launch_ghost_fill(n_owned, n_ghost, ghost_colors, Cint, rb.T, &c.S->maxc, c.st);
+  launch_ghost_fill(n_owned, n_ghost, ghost_colors, Cint, w->T.as<int32_t>(), &c.S->maxc, c.st);
   c.launches += 3;
+  // the phase-3 bin setup counts afresh: per-bin totals, maxima and the
+  // worklist counts, whose ping-pong halves still hold phase 1's last rounds
+  static_assert(offsetof(Scalars, count_unc) == offsetof(Scalars, count_all) + sizeof(Scalars::count_all),
+                "per-bin counts are cleared together");
+  launch_zero_words(c.S->count_all, 16, c.st);
+  launch_zero_words(c.S->cnt, sizeof(c.S->cnt) / 4, c.st);
+  launch_zero_words(&c.S->max_split_work, 1, c.st);
+  launch_zero_words(&c.S->max_work, 1, c.st);
+  launch_zero_words(&c.S->total_work, 2, c.st);
+  c.launches += 5;
   if (!grec) {
-    if (hipMemsetAsync(c.S->cnt[0], 0, sizeof(int32_t) * 8, c.st) != hipSuccess) return COLOR_EHIP;
-    launch_scatter(n_owned, Cint, w->bin.as<int8_t>(), L, c.wl[0], c.S->cnt[0], w->split_vertex.as<int32_t>(),
-                   c.st);
-    c.launches += 1;
-    if (hipMemcpyAsync(c.H->cnt[0], c.S->cnt[0], sizeof(int32_t) * 8, hipMemcpyDeviceToHost, c.st) != hipSuccess)
-      return COLOR_EHIP;
-    if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
-    for (int i = 0; i < kBins; ++i) known[i] = c.H->cnt[0][i];
+    // the owned losers on the full rows, ghosts as fixed constraints
     g.limit = m;
+    BinLayout L;
+    RoundBufs rb;
+    int32_t known[kBins];
+    if ((e = setup_bins<kD1>(c, g, Cint, Cint, m, L, rb, known))) return e;
     rc = run_phase<kD1>(c, g, k, L, rb, known, r1, c.P.max_rounds);
   } else {
     // tentative ghost recoloring (Section 3.2 save/restore; Section 3.4):
@@ -1110,8 +1154,6 @@ int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_
     const int32_t* rp3 = row_ptr;
     const int32_t* ci3 = col_idx;
     if (layers == 1 && n_ghost > 0) {
-      int32_t owned_nnz = 0;
-      if ((e = read_nnz(c, row_ptr, n_owned, &owned_nnz))) return e;
       const size_t ng1 = static_cast<size_t>(n_ghost) + 1;
       size_t scan_bytes = 0;
       if (exclusive_scan_i32(nullptr, nullptr, n_ghost + 1, nullptr, &scan_bytes, c.st)) return COLOR_EHIP;
@@ -1125,8 +1167,8 @@ int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_
       // owned-ghost entry of the owned rows, so at most owned_nnz more
       if ((e = w->gr_ci.ensure(sizeof(int32_t) * (2 * static_cast<size_t>(owned_nnz) + 1), false, c.st))) return e;
       int err = 0;
-      launch_ghost_rows(n_owned, n_ghost, row_ptr, col_idx, cnt, cnt + ng1, cnt + 2 * ng1, w->gr_rp.as<int32_t>(),
-                        w->gr_ci.as<int32_t>(), w->scan_tmp.p, w->scan_tmp.bytes, c.st, &err);
+      launch_ghost_rows(n_owned, n_ghost, owned_nnz, row_ptr, col_idx, cnt, cnt + ng1, cnt + 2 * ng1,
+                        w->gr_rp.as<int32_t>(), w->gr_ci.as<int32_t>(), w->scan_tmp.p, w->scan_tmp.bytes, c.st, &err);
       c.launches += 4;
       if (err || hipGetLastError() != hipSuccess) return COLOR_EHIP;
       rp3 = w->gr_rp.as<int32_t>();
@@ -1137,14 +1179,6 @@ int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_
     c.launches += 1;
     GraphView g3{n3, n3, rp3, ci3, rp3, ci3};
     g3.limit = m;
-    // the second bin setup of the call counts afresh
-    static_assert(offsetof(Scalars, count_unc) == offsetof(Scalars, count_all) + sizeof(Scalars::count_all),
-                  "per-bin counts are cleared together");
-    launch_zero_words(c.S->count_all, 16, c.st);
-    launch_zero_words(&c.S->max_split_work, 1, c.st);
-    launch_zero_words(&c.S->max_work, 1, c.st);
-    launch_zero_words(&c.S->total_work, 2, c.st);
-    c.launches += 4;
     BinLayout L3;
     RoundBufs rb3;
     int32_t known3[kBins];
@@ -1161,6 +1195,24 @@ int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_
     return COLOR_EHIP;
   if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
   return finish_call(c, stats, c.H->aux_max, rc);
+}
+
+// A step whose tail kernel's grid barrier gave up starts over with
+// per-round launches only (the same coloring).
+int color_d1_ghost_step(int32_t n_owned, int32_t n_ghost, int32_t layers, int32_t n_g1, const int32_t* row_ptr,
+                        const int32_t* col_idx, const int32_t* gid, const int32_t* ghost_colors,
+                        const int32_t* ghost_degree, uint32_t seed, const int32_t* init_owned,
+                        int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats,
+                        const color_params* params, void* stream) {
+  const int rc = ghost_step_once(n_owned, n_ghost, layers, n_g1, row_ptr, col_idx, gid, ghost_colors, ghost_degree,
+                                 seed, init_owned, owned_colors, remote_loser, stats, params, stream);
+  if (rc != kRcRetryNoTail) return rc;
+  color_params p;
+  if (params) p = *params;
+  else std::memset(&p, 0, sizeof(p));
+  p.flags |= COLOR_FLAG_NO_TAIL;
+  return ghost_step_once(n_owned, n_ghost, layers, n_g1, row_ptr, col_idx, gid, ghost_colors, ghost_degree, seed,
+                         init_owned, owned_colors, remote_loser, stats, &p, stream);
 }
 
 }  // extern "C"
@@ -1216,7 +1268,25 @@ static int ghost2_step(int32_t n_owned, int32_t n_ghost, const int32_t* rp1, con
   int32_t* loser = w->aux0.as<int32_t>();
   int32_t* gflag = w->aux1.as<int32_t>();
   launch_zero_words(gflag, static_cast<size_t>(std::max(n_ghost, 1)), c.st);
-  launch_boundary2<MODE>(g, n_owned, Cint, ghost_colors, k, loser, gflag, &c.S->conflicts, c.st);
+  launch_zero_words(loser, static_cast<size_t>(n_owned), c.st);
+  int32_t nnz1 = 0;
+  if ((e = read_nnz(c, rp1, n_owned, &nnz1))) return e;
+  launch_boundary2<MODE>(g, n_owned, nnz1, Cint, ghost_colors, k, loser, gflag, &c.S->hits, nullptr, 0,
+                         &c.S->conflicts, c.st);
+  if (hipMemcpyAsync(&c.H->hits, &c.S->hits, sizeof(unsigned long long), hipMemcpyDeviceToHost, c.st) !=
+          hipSuccess ||
+      hipStreamSynchronize(c.st) != hipSuccess)
+    return COLOR_EHIP;
+  if (c.H->hits > 0) {
+    // distinct pairs: a set with at least twice as many slots as entries
+    uint64_t slots = 1024;
+    while (slots < 2 * static_cast<uint64_t>(c.H->hits)) slots <<= 1;
+    if ((e = w->pair_set.ensure(sizeof(unsigned long long) * slots, false, c.st))) return e;
+    launch_fill_u64(w->pair_set.as<unsigned long long>(), slots, ~0ull, c.st);
+    launch_boundary2<MODE>(g, n_owned, nnz1, Cint, ghost_colors, k, loser, gflag, &c.S->hits,
+                           w->pair_set.as<unsigned long long>(), slots - 1, &c.S->conflicts, c.st);
+    c.launches += 2;
+  }
   launch_boundary_uncolor(n_owned, loser, Cint, c.st);
   // phase 3: ghosts carry their fixed colors; the losers are recolored
   launch_ghost_fill(n_owned, n_ghost, ghost_colors, Cint, rb.T, &c.S->maxc, c.st);

@@ -52,6 +52,7 @@ struct Scalars {
   unsigned long long total_work;
   unsigned long long conflicts; // ghost phase-2 conflicts
   unsigned long long remote;    // ghost remote losers
+  unsigned long long hits;      // D2/PD2 ghost step: conflicting two-hop walk entries
 };
 
 // Per-device workspace of the single-graph entry points.
@@ -64,11 +65,13 @@ struct Workspace {
   DevBuf deferred_work, deferred_done;  // setup: per heavy D2/PD2 vertex, its work and slices done
   DevBuf rank, rk_key0, rk_key1, rk_val0, rk_val1, rk_deg0, rk_deg1, rk_tmp;  // recolorDegrees ranks
   DevBuf gr_rp, gr_ci, gr_cnt, gr_init;  // tentative ghost recoloring: local CSR with ghost rows, start colors
+  DevBuf own_rp, own_ci;                 // ghost step: the owned-induced subgraph of phase 1
+  DevBuf pair_set;                       // D2/PD2 ghost step: distinct conflicting (owned, ghost) pairs
   Scalars* host = nullptr;  // pinned staging for read-backs
   std::vector<hipEvent_t> events;  // pool for COLOR_FLAG_KERNEL_TIMING
   ~Workspace();
   void release();
-  static constexpr int kNumBuffers = 42;
+  static constexpr int kNumBuffers = 45;
   std::array<DevBuf*, kNumBuffers> buffers();   // every DevBuf above
 };
 

@@ -367,87 +367,105 @@ __global__ __launch_bounds__(kBlock) void priority_kernel(int32_t n, const int32
 // Ghost phase 2 (Algorithm 3 with Algorithm 4 on the ghosts' fixed colors):
 // every owned-ghost edge with equal colors is a conflict; the owned endpoint
 // loses when the ghost's key is greater, otherwise the ghost is flagged.  All
-// pairs are judged on the phase-1 colors; losers are uncolored afterwards by
-// boundary_uncolor_kernel.
+// pairs are judged on the phase-1 colors (a thread per owned-row entry, so a
+// hub's row spreads over many threads); losers are uncolored afterwards by
+// boundary_uncolor_kernel.  loser must be zeroed first.
+__device__ __forceinline__ int32_t row_of(const int32_t* rp, int32_t n, int32_t e);
+
 __global__ __launch_bounds__(kBlock) void boundary_kernel(int32_t n_owned, const int32_t* rp,
                                                           const int32_t* ci, const int32_t* C,
                                                           const int32_t* ghost_colors, KeySource k,
                                                           int32_t* loser, int32_t* gflag,
                                                           unsigned long long* conflicts) {
-  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  const int32_t e = blockIdx.x * kBlock + threadIdx.x;
   uint32_t found = 0;
-  if (v < n_owned) {
-    const int32_t cv = ld_dev(&C[v]);
-    const uint64_t kv = key_of(k, v);
-    bool lose = false;
-    for (int32_t q = rp[v]; q < rp[v + 1]; ++q) {
-      const int32_t u = ci[q];
-      if (u < n_owned) continue;
-      if (ghost_colors[u - n_owned] != cv) continue;
-      ++found;
-      if (key_of(k, u) > kv) lose = true;
-      else st_dev(&gflag[u - n_owned], 1);
+  if (e < rp[n_owned]) {
+    const int32_t u = ci[e];
+    if (u >= n_owned) {
+      const int32_t v = row_of(rp, n_owned, e);
+      if (ghost_colors[u - n_owned] == ld_dev(&C[v])) {
+        found = 1;
+        if (key_of(k, u) > key_of(k, v)) st_dev(&loser[v], 1);
+        else st_dev(&gflag[u - n_owned], 1);
+      }
     }
-    st_dev(&loser[v], lose ? 1 : 0);
   }
-  uint64_t tot = found;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) tot += __shfl_xor(tot, off, kWave);
+  const uint64_t tot = __popcll(__ballot(found != 0));
   if (lane_id() == 0 && tot) atomicAdd(conflicts, static_cast<unsigned long long>(tot));
 }
 
 // Distance-2 / partial distance-2 ghost phase 2 (Algorithm 5 over the owned
-// vertices): every owned vertex walks its two-hop neighbourhood (MODE's
-// walk, the walk of scan_nbhd); each distinct ghost x with the vertex's color
-// is a conflict judged by the key rule on the ghosts' fixed colors.  A walk
-// can reach x along several paths: an entry counts only if x does not occur
-// earlier in the walk (checked by re-walking, which only conflicting
-// entries pay for).
-template <int MODE, typename F>
-__device__ __forceinline__ void walk2(const GraphView& g, int32_t v, F&& f) {
-  int64_t pos = 0;
-  for (int32_t e = g.rp[v]; e < g.rp[v + 1]; ++e) {
-    const int32_t u = g.ci[e];
-    if (MODE == kD2) {
-      if (f(u, pos++)) return;
-    }
-    for (int32_t q = g.rp2[u]; q < g.rp2[u + 1]; ++q) {
-      const int32_t x = g.ci2[q];
-      if (x != v && f(x, pos++)) return;
-    }
+// vertices): every owned vertex's two-hop walk is compared with the ghosts'
+// fixed colors, a thread per hop-1 entry (u) walking u itself (D2) and u's
+// hop-2 row, so heavy vertices spread over many threads.  A conflicting
+// ghost x of v makes v lose (key(x) > key(v)) or flags x; both are
+// idempotent, so the walk's repeated entries do not matter to them.  The
+// count is of distinct (v, x) pairs: pass 1 counts the conflicting entries,
+// pass 2 inserts them into an open-addressing set of (v, x) keys sized for
+// them and counts the insertions that found an empty slot.
+__device__ __forceinline__ int32_t row_of(const int32_t* rp, int32_t n, int32_t e) {
+  int32_t lo = 0, hi = n - 1;  // the last row whose start is <= e
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (rp[mid] <= e) lo = mid;
+    else hi = mid - 1;
   }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
 }
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void boundary2_kernel(GraphView g, int32_t n_owned, const int32_t* C,
                                                            const int32_t* ghost_colors, KeySource k, int32_t* loser,
-                                                           int32_t* gflag, unsigned long long* conflicts) {
-  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-  uint32_t found = 0;
-  if (v < n_owned) {
+                                                           int32_t* gflag, unsigned long long* hits,
+                                                           unsigned long long* set, uint64_t set_mask,
+                                                           unsigned long long* conflicts) {
+  const int32_t e = blockIdx.x * kBlock + threadIdx.x;
+  const int32_t nnz1 = g.rp[n_owned];
+  uint64_t n_hit = 0, n_new = 0;
+  if (e < nnz1) {
+    const int32_t v = row_of(g.rp, n_owned, e);
     const int32_t cv = ld_dev(&C[v]);
-    const uint64_t kv = key_of(k, v);
-    bool lose = false;
-    walk2<MODE>(g, v, [&](int32_t x, int64_t at) {
-      if (x < n_owned || ghost_colors[x - n_owned] != cv) return false;
-      bool earlier = false;
-      walk2<MODE>(g, v, [&](int32_t y, int64_t p) {
-        if (p >= at) return true;
-        earlier = y == x;
-        return earlier;
-      });
-      if (earlier) return false;
-      ++found;
-      if (key_of(k, x) > kv) lose = true;
+    const int32_t u = g.ci[e];
+    auto visit = [&](int32_t x) {
+      if (x < n_owned || x == v || ghost_colors[x - n_owned] != cv) return;
+      ++n_hit;
+      if (key_of(k, x) > key_of(k, v)) st_dev(&loser[v], 1);
       else st_dev(&gflag[x - n_owned], 1);
-      return false;
-    });
-    st_dev(&loser[v], lose ? 1 : 0);
+      if (set) {
+        const unsigned long long pair = (static_cast<unsigned long long>(v) << 32) | static_cast<uint32_t>(x);
+        for (uint64_t h = mix64(pair) & set_mask;; h = (h + 1) & set_mask) {
+          const unsigned long long was = atomicCAS(&set[h], ~0ull, pair);
+          if (was == ~0ull) {
+            ++n_new;
+            break;
+          }
+          if (was == pair) break;
+        }
+      }
+    };
+    if (MODE == kD2) visit(u);
+    for (int32_t q = g.rp2[u]; q < g.rp2[u + 1]; ++q) visit(g.ci2[q]);
   }
-  uint64_t tot = found;
 #pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) tot += __shfl_xor(tot, off, kWave);
-  if (lane_id() == 0 && tot) atomicAdd(conflicts, static_cast<unsigned long long>(tot));
+  for (int off = 1; off < kWave; off <<= 1) {
+    n_hit += __shfl_xor(n_hit, off, kWave);
+    n_new += __shfl_xor(n_new, off, kWave);
+  }
+  if (lane_id() == 0) {
+    if (n_hit) atomicAdd(hits, static_cast<unsigned long long>(n_hit));
+    if (n_new) atomicAdd(conflicts, static_cast<unsigned long long>(n_new));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void fill_u64_kernel(unsigned long long* p, uint64_t n, unsigned long long x) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) p[i] = x;
 }
 
 __global__ __launch_bounds__(kBlock) void boundary_uncolor_kernel(int32_t n_owned, const int32_t* loser,
@@ -538,11 +556,11 @@ void launch_priority(int32_t n, const int32_t* gid, uint32_t hs, uint32_t* out, 
   if (n > 0) hipLaunchKernelGGL(priority_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, gid, hs, out);
 }
 
-void launch_boundary(int32_t n_owned, const int32_t* rp, const int32_t* ci, const int32_t* C,
+void launch_boundary(int32_t n_owned, int32_t owned_nnz, const int32_t* rp, const int32_t* ci, const int32_t* C,
                      const int32_t* ghost_colors, const KeySource& k, int32_t* loser, int32_t* gflag,
                      unsigned long long* conflicts, hipStream_t st) {
-  if (n_owned > 0)
-    hipLaunchKernelGGL(boundary_kernel, dim3(blocks_for(n_owned)), dim3(kBlock), 0, st, n_owned, rp, ci, C,
+  if (n_owned > 0 && owned_nnz > 0)
+    hipLaunchKernelGGL(boundary_kernel, dim3(blocks_for(owned_nnz)), dim3(kBlock), 0, st, n_owned, rp, ci, C,
                        ghost_colors, k, loser, gflag, conflicts);
 }
 
@@ -552,17 +570,34 @@ void launch_boundary_uncolor(int32_t n_owned, const int32_t* loser, int32_t* C, 
                        loser, C);
 }
 
+// Ghost phase 1 reads the owned-induced subgraph: the owned rows without
+// their ghost entries (ids >= n_owned).  A flag per owned-row entry (1: kept),
+// an exclusive scan of the flags, then every kept entry moves to its scanned
+// position and every row starts at the scan of its first entry.
+__global__ __launch_bounds__(kBlock) void owned_flags_kernel(int32_t n_owned, const int32_t* rp, const int32_t* ci,
+                                                             int32_t* flag) {
+  const int32_t e = blockIdx.x * kBlock + threadIdx.x;
+  const int32_t nnz = rp[n_owned];
+  if (e < nnz) st_dev(&flag[e], ci[e] < n_owned ? 1 : 0);
+  else if (e == nnz) st_dev(&flag[e], 0);
+}
+
+__global__ __launch_bounds__(kBlock) void owned_compact_kernel(int32_t n_owned, const int32_t* rp, const int32_t* ci,
+                                                               const int32_t* pos, int32_t* rp1, int32_t* ci1) {
+  const int32_t e = blockIdx.x * kBlock + threadIdx.x;
+  if (e <= n_owned) st_dev(&rp1[e], pos[rp[e]]);
+  if (e < rp[n_owned] && ci[e] < n_owned) st_dev(&ci1[pos[e]], ci[e]);
+}
+
 // Tentative ghost recoloring, one layer: a ghost's row in the local graph is
 // the owned vertices adjacent to it (the local graph's undirected
 // owned-ghost edges).  Counts them per ghost ...
 __global__ __launch_bounds__(kBlock) void ghost_row_count_kernel(int32_t n_owned, const int32_t* rp,
                                                                  const int32_t* ci, int32_t* cnt) {
-  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-  if (v >= n_owned) return;
-  for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
-    const int32_t u = ci[e];
-    if (u >= n_owned) atomicAdd(&cnt[u - n_owned], 1);
-  }
+  const int32_t e = blockIdx.x * kBlock + threadIdx.x;  // a thread per owned-row entry
+  if (e >= rp[n_owned]) return;
+  const int32_t u = ci[e];
+  if (u >= n_owned) atomicAdd(&cnt[u - n_owned], 1);
 }
 
 // ... and, with the per-ghost offsets goff (exclusive scan of the counts,
@@ -571,18 +606,16 @@ __global__ __launch_bounds__(kBlock) void ghost_row_count_kernel(int32_t n_owned
 __global__ __launch_bounds__(kBlock) void ghost_rows_kernel(int32_t n_owned, int32_t n_ghost, const int32_t* rp,
                                                             const int32_t* ci, const int32_t* goff, int32_t* fill,
                                                             int32_t* rp3, int32_t* ci3) {
-  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;  // offsets by id, entries by position
   const int32_t owned_nnz = rp[n_owned];
   if (i <= n_owned) st_dev(&rp3[i], rp[i]);
   if (i > 0 && i <= n_ghost) st_dev(&rp3[n_owned + i], owned_nnz + goff[i]);
-  if (i >= n_owned) return;
-  for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
-    const int32_t u = ci[e];
-    st_dev(&ci3[e], u);
-    if (u >= n_owned) {
-      const int32_t j = u - n_owned;
-      st_dev(&ci3[owned_nnz + goff[j] + atomicAdd(&fill[j], 1)], i);
-    }
+  if (i >= owned_nnz) return;
+  const int32_t u = ci[i];
+  st_dev(&ci3[i], u);
+  if (u >= n_owned) {
+    const int32_t j = u - n_owned;
+    st_dev(&ci3[owned_nnz + goff[j] + atomicAdd(&fill[j], 1)], row_of(rp, n_owned, i));
   }
 }
 
@@ -606,18 +639,31 @@ __global__ __launch_bounds__(kBlock) void ghost_recolor_init_kernel(int32_t n_ow
   st_dev(&init[v], c);
 }
 
-void launch_ghost_rows(int32_t n_owned, int32_t n_ghost, const int32_t* rp, const int32_t* ci, int32_t* cnt,
-                       int32_t* goff, int32_t* fill, int32_t* rp3, int32_t* ci3, void* scan_tmp, size_t scan_bytes,
-                       hipStream_t st, int* err) {
+void launch_ghost_rows(int32_t n_owned, int32_t n_ghost, int32_t owned_nnz, const int32_t* rp, const int32_t* ci,
+                       int32_t* cnt, int32_t* goff, int32_t* fill, int32_t* rp3, int32_t* ci3, void* scan_tmp,
+                       size_t scan_bytes, hipStream_t st, int* err) {
   *err = 0;
   if (n_ghost > 0) {
-    hipLaunchKernelGGL(ghost_row_count_kernel, dim3(blocks_for(std::max(n_owned, 1))), dim3(kBlock), 0, st, n_owned,
-                       rp, ci, cnt);
+    hipLaunchKernelGGL(ghost_row_count_kernel, dim3(blocks_for(std::max(owned_nnz, 1))), dim3(kBlock), 0, st,
+                       n_owned, rp, ci, cnt);
     if (exclusive_scan_i32(cnt, goff, n_ghost + 1, scan_tmp, &scan_bytes, st)) *err = 1;
   }
-  const int32_t items = std::max(n_owned + 1, n_ghost + 1);
+  const int32_t items = std::max(std::max(n_owned + 1, n_ghost + 1), owned_nnz);
   hipLaunchKernelGGL(ghost_rows_kernel, dim3(blocks_for(items)), dim3(kBlock), 0, st, n_owned, n_ghost, rp, ci,
                      goff, fill, rp3, ci3);
+}
+
+int launch_owned_subgraph(int32_t n_owned, int32_t owned_nnz, const int32_t* rp, const int32_t* ci, int32_t* flag,
+                          int32_t* pos, int32_t* rp1, int32_t* ci1_or_null, void* scan_tmp, size_t scan_bytes,
+                          hipStream_t st) {
+  const int32_t items = std::max(owned_nnz + 1, n_owned + 1);
+  if (ci1_or_null == nullptr) {
+    hipLaunchKernelGGL(owned_flags_kernel, dim3(blocks_for(owned_nnz + 1)), dim3(kBlock), 0, st, n_owned, rp, ci, flag);
+    return exclusive_scan_i32(flag, pos, owned_nnz + 1, scan_tmp, &scan_bytes, st);
+  }
+  hipLaunchKernelGGL(owned_compact_kernel, dim3(blocks_for(items)), dim3(kBlock), 0, st, n_owned, rp, ci, pos, rp1,
+                     ci1_or_null);
+  return 0;
 }
 
 void launch_ghost_recolor_init(int32_t n_owned, int32_t n3, const int32_t* C, const int32_t* gc, const int32_t* gflag,
@@ -627,18 +673,26 @@ void launch_ghost_recolor_init(int32_t n_owned, int32_t n3, const int32_t* C, co
                        gflag, init);
 }
 
-template <int MODE>
-void launch_boundary2(const GraphView& g, int32_t n_owned, const int32_t* C, const int32_t* ghost_colors,
-                      const KeySource& k, int32_t* loser, int32_t* gflag, unsigned long long* conflicts,
-                      hipStream_t st) {
-  if (n_owned > 0)
-    hipLaunchKernelGGL(boundary2_kernel<MODE>, dim3(blocks_for(n_owned)), dim3(kBlock), 0, st, g, n_owned, C,
-                       ghost_colors, k, loser, gflag, conflicts);
+void launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long x, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, p,
+                       n, x);
 }
-template void launch_boundary2<kD2>(const GraphView&, int32_t, const int32_t*, const int32_t*, const KeySource&,
-                                    int32_t*, int32_t*, unsigned long long*, hipStream_t);
-template void launch_boundary2<kPD2>(const GraphView&, int32_t, const int32_t*, const int32_t*, const KeySource&,
-                                     int32_t*, int32_t*, unsigned long long*, hipStream_t);
+
+template <int MODE>
+void launch_boundary2(const GraphView& g, int32_t n_owned, int32_t nnz1, const int32_t* C, const int32_t* ghost_colors,
+                      const KeySource& k, int32_t* loser, int32_t* gflag, unsigned long long* hits,
+                      unsigned long long* set, uint64_t set_mask, unsigned long long* conflicts, hipStream_t st) {
+  if (nnz1 > 0)
+    hipLaunchKernelGGL(boundary2_kernel<MODE>, dim3(blocks_for(nnz1)), dim3(kBlock), 0, st, g, n_owned, C,
+                       ghost_colors, k, loser, gflag, hits, set, set_mask, conflicts);
+}
+template void launch_boundary2<kD2>(const GraphView&, int32_t, int32_t, const int32_t*, const int32_t*,
+                                    const KeySource&, int32_t*, int32_t*, unsigned long long*, unsigned long long*,
+                                    uint64_t, unsigned long long*, hipStream_t);
+template void launch_boundary2<kPD2>(const GraphView&, int32_t, int32_t, const int32_t*, const int32_t*,
+                                     const KeySource&, int32_t*, int32_t*, unsigned long long*, unsigned long long*,
+                                     uint64_t, unsigned long long*, hipStream_t);
 
 void launch_ghost_fill(int32_t n_owned, int32_t n_ghost, const int32_t* gc, int32_t* C, int32_t* T,
                        int32_t* maxc, hipStream_t st) {

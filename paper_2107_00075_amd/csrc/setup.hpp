@@ -37,13 +37,20 @@ void launch_validate(int32_t n_rows, int32_t n_cols, const int32_t* rp, const in
                      const int32_t* rpT, const int32_t* ciT, int32_t n_trows, int square, int32_t* err,
                      hipStream_t st);
 void launch_priority(int32_t n, const int32_t* gid, uint32_t hs, uint32_t* out, hipStream_t st);
-void launch_boundary(int32_t n_owned, const int32_t* rp, const int32_t* ci, const int32_t* C,
+// D1 ghost phase 2 (a thread per owned-row entry; loser zeroed first).
+void launch_boundary(int32_t n_owned, int32_t owned_nnz, const int32_t* rp, const int32_t* ci, const int32_t* C,
                      const int32_t* ghost_colors, const KeySource& k, int32_t* loser, int32_t* gflag,
                      unsigned long long* conflicts, hipStream_t st);
+// Two-hop boundary detect of the D2/PD2 ghost step (one thread per hop-1
+// entry of the owned vertices; nnz1 = rp[n_owned]).  Pass 1 (set == nullptr)
+// decides losers and flags and adds the conflicting walk entries to *hits;
+// pass 2 (set: set_mask + 1 slots of ~0) counts distinct (v, x) pairs into
+// *conflicts.  loser must be zeroed first.
 template <int MODE>
-void launch_boundary2(const GraphView& g, int32_t n_owned, const int32_t* C, const int32_t* ghost_colors,
-                      const KeySource& k, int32_t* loser, int32_t* gflag, unsigned long long* conflicts,
-                      hipStream_t st);
+void launch_boundary2(const GraphView& g, int32_t n_owned, int32_t nnz1, const int32_t* C, const int32_t* ghost_colors,
+                      const KeySource& k, int32_t* loser, int32_t* gflag, unsigned long long* hits,
+                      unsigned long long* set, uint64_t set_mask, unsigned long long* conflicts, hipStream_t st);
+void launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long x, hipStream_t st);
 void launch_boundary_uncolor(int32_t n_owned, const int32_t* loser, int32_t* C, hipStream_t st);
 void launch_ghost_fill(int32_t n_owned, int32_t n_ghost, const int32_t* gc, int32_t* C, int32_t* T,
                        int32_t* maxc, hipStream_t st);
@@ -53,9 +60,19 @@ constexpr int32_t kGhostUnknown = 0x7fffffff;
 // its owned neighbours.  cnt and fill: n_ghost + 1 zeroed words; goff:
 // n_ghost + 1; rp3: n_owned + n_ghost + 1; ci3: rp[n_owned] + cut entries.
 // *err = 1 if the scan failed.
-void launch_ghost_rows(int32_t n_owned, int32_t n_ghost, const int32_t* rp, const int32_t* ci, int32_t* cnt,
-                       int32_t* goff, int32_t* fill, int32_t* rp3, int32_t* ci3, void* scan_tmp, size_t scan_bytes,
-                       hipStream_t st, int* err);
+void launch_ghost_rows(int32_t n_owned, int32_t n_ghost, int32_t owned_nnz, const int32_t* rp, const int32_t* ci,
+                       int32_t* cnt, int32_t* goff, int32_t* fill, int32_t* rp3, int32_t* ci3, void* scan_tmp,
+                       size_t scan_bytes, hipStream_t st, int* err);
+// The owned-induced subgraph of a rank's local graph, in two calls: with
+// ci1_or_null == nullptr, flags every owned-row entry (flag: owned_nnz + 1
+// words) and scans the flags into pos (owned_nnz + 1); then, with ci1, writes
+// rp1 (n_owned + 1) and the kept entries.  Returns nonzero if the scan failed.
+int launch_owned_subgraph(int32_t n_owned, int32_t owned_nnz, const int32_t* rp, const int32_t* ci, int32_t* flag,
+                          int32_t* pos, int32_t* rp1, int32_t* ci1_or_null, void* scan_tmp, size_t scan_bytes,
+                          hipStream_t st);
+// then, with ci1, copies the entries.  Returns nonzero if the scan failed.
+int launch_owned_subgraph(int32_t n_owned, const int32_t* rp, const int32_t* ci, int32_t* cnt, int32_t* rp1,
+                          int32_t* ci1_or_null, void* scan_tmp, size_t scan_bytes, hipStream_t st);
 void launch_ghost_recolor_init(int32_t n_owned, int32_t n3, const int32_t* C, const int32_t* gc, const int32_t* gflag,
                                int32_t* init, hipStream_t st);
 void launch_max_i32(int32_t n, const int32_t* a, int32_t* out, hipStream_t st);
