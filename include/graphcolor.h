@@ -27,10 +27,14 @@
  * (memory from hipMalloc / a torch CUDA tensor) owned by the caller; the
  * library never frees or retains it.  `stream` is a hipStream_t (NULL = the
  * default stream).  Calls are blocking: they return after all work they
- * enqueued on `stream` has finished.  The library keeps a per-device
- * workspace that grows to the largest call seen (released by
- * color_release_workspace); calls on one device are serialized by an
- * internal lock.
+ * enqueued on `stream` has finished.  Each call runs on a workspace that no
+ * other call holds at the same time, taken from a per-device pool (up to 8
+ * workspaces per device, each growing to the largest call it served, kept
+ * until color_release_workspace; a 9th concurrent call waits for one), so
+ * calls made at the same time from different host threads on different
+ * streams are independent: they neither wait for nor share memory with each
+ * other.  Only color_d1_noalloc (one static array per device) serializes
+ * its calls.
  *
  * Graph layout.  A graph with n vertices is CSR: row_ptr int32[n+1]
  * (row_ptr[0] = 0, non-decreasing), col_idx int32[row_ptr[n]] with

@@ -85,18 +85,22 @@ void Workspace::release() {
   host = nullptr;
 }
 
-static std::mutex g_ws_mu;
-static std::map<int, Workspace*> g_ws;
+// Workspaces of the single-graph entry points: a pool per device.  A call
+// takes a workspace no other call holds (creating one, up to
+// kMaxWorkspaces per device), so calls from different host threads on
+// different streams run at the same time on separate memory; beyond the cap
+// a call waits for a busy workspace.  Each workspace grows to the largest
+// call it served and is kept until color_release_workspace.
+constexpr size_t kMaxWorkspaces = 8;
 
-Workspace* workspace_for_current_device(int* err) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) {
-    *err = COLOR_EHIP;
-    return nullptr;
-  }
-  std::lock_guard<std::mutex> lk(g_ws_mu);
-  auto it = g_ws.find(dev);
-  if (it != g_ws.end()) return it->second;
+struct DevicePool {
+  std::vector<Workspace*> all;
+};
+
+static std::mutex g_ws_mu;
+static std::map<int, DevicePool> g_ws;
+
+static Workspace* new_workspace(int dev, int* err) {
   Workspace* w = new Workspace();
   w->device = dev;
   if (hipHostMalloc(reinterpret_cast<void**>(&w->host), sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
@@ -104,8 +108,38 @@ Workspace* workspace_for_current_device(int* err) {
     *err = COLOR_ENOMEM;
     return nullptr;
   }
-  g_ws[dev] = w;
   return w;
+}
+
+int acquire_workspace(std::unique_lock<std::mutex>* held, Workspace** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return COLOR_EHIP;
+  Workspace* wait_on = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    DevicePool& pool = g_ws[dev];
+    for (Workspace* w : pool.all) {
+      std::unique_lock<std::mutex> l(w->mu, std::try_to_lock);
+      if (l.owns_lock()) {
+        *held = std::move(l);
+        *out = w;
+        return COLOR_OK;
+      }
+    }
+    if (pool.all.size() < kMaxWorkspaces) {
+      int err = COLOR_OK;
+      Workspace* w = new_workspace(dev, &err);
+      if (!w) return err;
+      pool.all.push_back(w);
+      *held = std::unique_lock<std::mutex>(w->mu);
+      *out = w;
+      return COLOR_OK;
+    }
+    wait_on = pool.all.front();
+  }
+  *held = std::unique_lock<std::mutex>(wait_on->mu);
+  *out = wait_on;
+  return COLOR_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -395,8 +429,12 @@ int begin_call(Call& c, int mode, const color_params* user, color_stats* stats, 
   // COLOR_ENOCONVERGE instead of an endless loop.
   if (c.P.max_rounds == 0) c.P.max_rounds = n_total < INT_MAX ? n_total + 1 : INT_MAX;
   c.st = static_cast<hipStream_t>(stream);
-  c.ws = fixed_ws ? fixed_ws : workspace_for_current_device(&e);
-  if (!c.ws) return e;
+  if (fixed_ws) {
+    c.lock = std::unique_lock<std::mutex>(fixed_ws->mu);
+    c.ws = fixed_ws;
+  } else if ((e = acquire_workspace(&c.lock, &c.ws))) {
+    return e;
+  }
   c.trace_cap = (stats && stats->worklist_trace && stats->trace_cap > 0) ? stats->trace_cap : 0;
   c.timing = (c.P.flags & COLOR_FLAG_KERNEL_TIMING) != 0 && stats != nullptr;
   Workspace* w = c.ws;
@@ -790,7 +828,6 @@ int validate_job(const color_job& j, void* stream) {
   Call c;
   int e = begin_call(c, j.kind, nullptr, nullptr, stream, 1, 1);
   if (e) return e;
-  std::unique_lock<std::mutex> lk(c.ws->mu);
   if (j.kind == COLOR_KIND_D1) return validate_graph<kD1>(c, j.n, j.n, j.row_ptr, j.col_idx, j.row_ptr, j.col_idx);
   if (j.kind == COLOR_KIND_D2) return validate_graph<kD2>(c, j.n, j.n, j.row_ptr, j.col_idx, j.row_ptr, j.col_idx);
   return validate_graph<kPD2>(c, j.n, j.n_rows, j.col_ptr, j.row_idx, j.row_ptr, j.col_idx);
@@ -860,7 +897,6 @@ static int color_graph_once(int32_t n, int32_t n_rows, const int32_t* rp, const 
   Call c;
   int e = begin_call(c, MODE, params, stats, stream, n, n, fixed_ws);
   if (e) return e;
-  std::unique_lock<std::mutex> lk(c.ws->mu);
   if (n == 0) return finish_call(c, stats, 0, COLOR_OK);
   if (c.P.flags & COLOR_FLAG_VALIDATE) {
     if ((e = validate_graph<MODE>(c, n, n_rows, rp, ci, rp2, ci2))) return e;
@@ -1056,7 +1092,6 @@ static int ghost_step_once(int32_t n_owned, int32_t n_ghost, int32_t layers, int
   Call c;
   int e = begin_call(c, kD1, params, stats, stream, n3, m);
   if (e) return e;
-  std::unique_lock<std::mutex> lk(c.ws->mu);
   if (n_owned == 0) return finish_call(c, stats, 0, COLOR_OK);
   Workspace* w = c.ws;
   if ((e = w->C.ensure(sizeof(int32_t) * static_cast<size_t>(m), false, c.st))) return e;
@@ -1238,7 +1273,6 @@ static int ghost2_step(int32_t n_owned, int32_t n_ghost, const int32_t* rp1, con
   Call c;
   int e = begin_call(c, MODE, params, stats, stream, n_owned, m);
   if (e) return e;
-  std::unique_lock<std::mutex> lk(c.ws->mu);
   if (n_owned == 0) return finish_call(c, stats, 0, COLOR_OK);
   Workspace* w = c.ws;
   if ((e = w->C.ensure(sizeof(int32_t) * static_cast<size_t>(m), false, c.st))) return e;
@@ -1353,11 +1387,12 @@ int color_release_workspace(void) {
   release_batch_workspaces();
   std::lock_guard<std::mutex> lk(g_ws_mu);
   for (auto& kv : g_ws) {
-    std::lock_guard<std::mutex> lk2(kv.second->mu);
-    kv.second->release();
-    if (hipHostMalloc(reinterpret_cast<void**>(&kv.second->host), sizeof(Scalars), hipHostMallocDefault) !=
-        hipSuccess)
-      kv.second->host = nullptr;
+    for (Workspace* w : kv.second.all) {
+      std::lock_guard<std::mutex> lk2(w->mu);
+      w->release();
+      if (hipHostMalloc(reinterpret_cast<void**>(&w->host), sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
+        w->host = nullptr;
+    }
   }
   return COLOR_OK;
 }

@@ -75,11 +75,14 @@ struct Workspace {
   std::array<DevBuf*, kNumBuffers> buffers();   // every DevBuf above
 };
 
-Workspace* workspace_for_current_device(int* err);
+// A workspace of the current device no other call holds, returned locked
+// (the lock moves into *held).
+int acquire_workspace(std::unique_lock<std::mutex>* held, Workspace** out);
 
 // State of one library call.
 struct Call {
   Workspace* ws = nullptr;
+  std::unique_lock<std::mutex> lock;  // holds ws for the whole call
   hipStream_t st = nullptr;
   color_params P;
   int launches = 0;

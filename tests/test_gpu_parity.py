@@ -400,3 +400,41 @@ def test_library_engine_choice(gc):
         colors, st = gc.color_d2(dev(g.row_ptr), dev(g.col), seed=5)
         assert st.engine == want
         assert np.array_equal(colors.cpu().numpy(), oracle.color_d2(g, seed=5).colors)
+
+
+def test_concurrent_calls_on_two_streams(gc):
+    """Two host threads color different graphs on two streams at the same
+    time (each call holds its own workspace from the per-device pool); both
+    results equal the oracle, repeated so that the calls overlap."""
+    import threading
+    a = gg.rmat(16, 16, 4)
+    b = gg.bipartite_powerlaw(60000, 15000, 8, 2.1, 3)
+    ra = oracle.color_d1(a, seed=2)
+    rb = oracle.color_pd2(b, seed=2)
+    da = (dev(a.row_ptr), dev(a.col))
+    db = (dev(b.row_ptr), dev(b.col_idx), dev(b.col_ptr), dev(b.row_idx))
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(which):
+        s = torch.cuda.Stream()
+        try:
+            with torch.cuda.stream(s):
+                for _ in range(6):
+                    if which == 0:
+                        c, st = gc.color_d1(*da, seed=2, stream=s, params=gc.Params(engine=ENGINE["id"]))
+                        ok = np.array_equal(c.cpu().numpy(), ra.colors) and st.rounds == ra.rounds
+                    else:
+                        c, st = gc.color_pd2(*db, seed=2, stream=s, params=gc.Params(engine=ENGINE["id"]))
+                        ok = np.array_equal(c.cpu().numpy(), rb.colors) and st.rounds == rb.rounds
+                    if not ok:
+                        errors.append(which)
+        except Exception as ex:  # noqa: BLE001 - reported below
+            errors.append(repr(ex))
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=300)
+    assert not errors, errors
