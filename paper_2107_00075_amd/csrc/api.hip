@@ -643,6 +643,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   ib.rounds_done = &S->rounds_done;
   ib.llen = w->inc_Ll.as<int32_t>();
   ib.uniform = 0;
+  ib.defer_split = 0;
 
   if (init) {
     IncBufs pb = ib;
@@ -691,9 +692,13 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
     b.wl_out = wl[pout];
     b.cnt_in = S->cnt[pin];
     b.cnt_out = S->cnt[pout];
-    b.A_in = r == 1 ? A0 : B;
+    // without initial colors round 1's losers leave the lists unsplit (the
+    // read-only adjacency or two-hop lists); round 2 reads those and writes
+    // the first compacted, key-split lists, which later rounds compact in place
+    b.A_in = (r == 1 || (r == 2 && !init)) ? A0 : B;
     b.A_out = B;
     b.uniform = (r == 1 && !init) ? 1 : 0;
+    b.defer_split = (r == 1 && !init) ? 1 : 0;
     b.alen_in = Lb;
     b.alen_out = Lb;
     return b;
@@ -716,10 +721,15 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
       g = std::min<int64_t>(g, std::min(tail_blocks_resident(), std::max(8, c.P.max_workgroups)));
       if (g >= 8) g = g / 8 * 8;
       IncRoundSet set;
-      set.b[0] = round_bufs(1);
-      set.b[1] = round_bufs(3);
-      set.b[2] = round_bufs(2);
-      for (IncBufs& b : set.b) b.bytes_slot = 6;
+      set.base = round_bufs(3);
+      set.base.bytes_slot = 6;
+      set.wl0 = wl[0];
+      set.wl1 = wl[1];
+      set.cnt0 = S->cnt[0];
+      set.cnt1 = S->cnt[1];
+      set.A0 = A0;
+      set.uniform1 = init ? 0 : 1;
+      set.defer1 = init ? 0 : 1;
       static_assert(offsetof(Scalars, tail_left) == offsetof(Scalars, bar) + sizeof(Scalars::bar) + sizeof(int32_t),
                     "barrier words and tail flags are cleared together");
       if (hipMemsetAsync(S->bar, 0, sizeof(S->bar) + 2 * sizeof(int32_t), c.st) != hipSuccess) return COLOR_EHIP;

@@ -112,6 +112,7 @@ constexpr int kCompactAlways = 2;
 constexpr int kCompactPeriod = 8;  // a power of two
 
 __device__ __forceinline__ bool compact_now(const IncBufs& b, int round, int32_t v) {
+  if (b.defer_split) return false;
   return b.A_in != b.A_out || round <= kCompactAlways || ((round + v) & (kCompactPeriod - 1)) == 0;
 }
 
@@ -262,7 +263,7 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
     if (lose && !compact_now(b, round, v)) {
       if (sub == 0) {
         s_ent[idx] = v;
-        s_tb[idx] = static_cast<int8_t>(inc_bin_of(L, len + ld_mut<MUT>(&b.llen[v])));  // not the first pass
+        s_tb[idx] = static_cast<int8_t>(inc_bin_of(L, first_pass ? len : len + ld_mut<MUT>(&b.llen[v])));
         bytes += 24;
       }
     } else if (lose) {
@@ -409,7 +410,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
   bytes += 4ull * read;  // list entries and tentative colors this thread read
   if (lose && !compact_now(b, round, v)) {
     if (tid == 0) {
-      const int nb = inc_bin_of(L, len + ld_mut<MUT>(&b.llen[v]));  // not the first pass
+      const int nb = inc_bin_of(L, first_pass ? len : len + ld_mut<MUT>(&b.llen[v]));
       const int32_t p = atomicAdd(&b.cnt_out[nb], 1);
       st_dev(&b.wl_out[L.off[nb] + p], v);
       bytes += 28;
@@ -724,8 +725,7 @@ __device__ __forceinline__ bool tail_checkin(uint32_t* bar, int32_t* err, uint64
 }
 
 // Rounds round0 .. round_cap of one call: color phase, barrier, detect phase,
-// barrier, stop when the next worklist is empty.  set.b[0] holds the buffers
-// of round 1, set.b[1] and set.b[2] those of later odd and even rounds.
+// barrier, stop when the next worklist is empty.
 // *left receives 1 if the cap was reached with vertices left.
 __global__ __launch_bounds__(kBlock) void inc_tail_kernel(KeySource k, IncRoundSet set, BinLayout L, int round0,
                                                           int round_cap, uint32_t* bar, int32_t* err,
@@ -739,7 +739,15 @@ __global__ __launch_bounds__(kBlock) void inc_tail_kernel(KeySource k, IncRoundS
   __shared__ IncPre s_pre;  // next round's map and largest color, read once per round
   if (!tail_checkin(bar, err, checkin_ticks, &s_ok)) return;
   for (int r = round0; r <= round_cap; ++r) {
-    const IncBufs& b = r == 1 ? set.b[0] : set.b[1 + ((r - 1) & 1)];
+    IncBufs b = set.base;
+    const bool odd = (r & 1) != 0;
+    b.wl_in = odd ? set.wl0 : set.wl1;
+    b.wl_out = odd ? set.wl1 : set.wl0;
+    b.cnt_in = odd ? set.cnt0 : set.cnt1;
+    b.cnt_out = odd ? set.cnt1 : set.cnt0;
+    b.A_in = (r == 1 || (r == 2 && set.defer1)) ? set.A0 : set.base.A_out;
+    b.uniform = r == 1 ? set.uniform1 : 0;
+    b.defer_split = r == 1 ? set.defer1 : 0;
     const bool first = r == round0;
     inc_color_phase<1>(b, L, r, sh.c, first ? nullptr : &s_pre);
     if (!grid_sync(bar, err, deadline, &s_ok)) return;

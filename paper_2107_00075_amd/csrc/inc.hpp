@@ -23,6 +23,8 @@ struct IncBufs {
   int32_t* llen;               // after the first pass: the lower-key part at the back of a list
   int32_t uniform;             // 1 in round 1 without initial colors: every vertex is uncolored and
                                // every tentative color is 1
+  int32_t defer_split;         // round 1 without initial colors: losers keep the read-only lists
+                               // untouched (round 2 splits and compacts them)
   const int32_t* fw_off;       // bitset word offsets, n+1 entries
   uint32_t* F;                 // forbidden-color bitsets (bit c-1 = color c)
   int32_t* maxc;               // largest committed color
@@ -54,9 +56,19 @@ inline int64_t inc_round_units(const int32_t cnt[kBins], const BinLayout& L) {
   return u + cnt[kBlockBin] + cnt[kSplitBin];
 }
 
-// Buffers of round 1 ([0]) and of later odd ([1]) and even ([2]) rounds.
+// The buffers of every round of the tail kernel: the fields all rounds share
+// (base: as for round 3 and later), the worklist ping-pong, and the unsplit
+// lists of the first rounds.  Rounds are built from it with scalar selects
+// (no dynamically indexed array of buffer sets, which would live in scratch).
 struct IncRoundSet {
-  IncBufs b[3];
+  IncBufs base;
+  int32_t* wl0;
+  int32_t* wl1;
+  int32_t* cnt0;
+  int32_t* cnt1;
+  const int32_t* A0;      // the unsplit lists (round 1; round 2 when round 1 deferred the split)
+  int32_t uniform1;       // round 1 is uniform
+  int32_t defer1;         // round 1 defers the split to round 2
 };
 
 constexpr int32_t kErrTailBarrier = 0x100;  // error bit: a tail-kernel grid barrier gave up
