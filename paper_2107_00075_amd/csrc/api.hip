@@ -74,7 +74,8 @@ std::array<DevBuf*, Workspace::kNumBuffers> Workspace::buffers() {
           &split_flag, &split_mask, &aux0, &aux1, &deferred, &inc_len, &inc_words, &inc_fwoff, &inc_aoff,
           &inc_F, &inc_L0, &inc_Ll, &inc_B0, &inc_B1, &inc_bm, &inc_wl0, &inc_wl1, &scan_tmp,
           &deferred_work, &deferred_done, &rank, &rk_key0, &rk_key1, &rk_val0, &rk_val1, &rk_deg0,
-          &rk_deg1, &rk_tmp, &gr_rp, &gr_ci, &gr_cnt, &gr_init, &own_rp, &own_ci, &pair_set};
+          &rk_deg1, &rk_tmp, &gr_rp, &gr_ci, &gr_cnt, &gr_init, &own_rp, &own_ci, &pair_set, &inc_T8,
+          &inc_done};
 }
 
 void Workspace::release() {
@@ -535,7 +536,7 @@ static int read_nnz(Call& c, const int32_t* rp, int32_t n, int32_t* nnz) {
 // ---------------------------------------------------------------------------
 template <int MODE>
 int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32_t* init, int32_t* colors,
-                    BinLayout& L, int32_t known[kBins], int* fell_back) {
+                    BinLayout& L, int32_t known[kBins], int* fell_back, int round0) {
   Workspace* w = c.ws;
   Scalars* S = c.S;
   Scalars* H = c.H;
@@ -644,12 +645,35 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   ib.llen = w->inc_Ll.as<int32_t>();
   ib.uniform = 0;
   ib.defer_split = 0;
+  ib.round_base = round0;
+  // tentative colors as bytes while they fit one: a color taken in round r
+  // is at most (largest initial color) + r (first fit over colors committed
+  // before the round, whose largest grows by at most one per round)
+  if ((e = w->inc_T8.ensure((static_cast<size_t>(n) + 3) / 4 * 4, false, c.st))) return e;
+  if ((e = w->inc_done.ensure(sizeof(uint32_t) * (static_cast<size_t>(n) / 32 + 1), false, c.st))) return e;
+  ib.T8 = w->inc_T8.as<uint8_t>();
+  ib.done = w->inc_done.as<uint32_t>();
+  ib.t8_last = std::max(0, 255 - H->maxc);
+  launch_inc_state_init(n, colors, ib.T8, ib.done, c.st);
+  c.launches += 1;
 
   if (init) {
-    IncBufs pb = ib;
-    pb.alen_in = Lb;
-    launch_inc_init_push(pb, n, A0, c.st);
-    c.launches += 1;
+    if constexpr (MODE != kD1) {
+      if (g.ids > g.limit) {
+        // walks reach members outside the lists (a rank's ghosts, fixed
+        // colors): every uncolored vertex takes all its members' colors
+        int32_t nnz1 = 0;
+        if ((e = read_nnz(c, g.rp, n, &nnz1))) return e;
+        launch_inc_init_pull<MODE>(g, nnz1, ib, c.st);
+        c.launches += 1;
+      }
+    }
+    if (g.ids <= g.limit || MODE == kD1) {
+      IncBufs pb = ib;
+      pb.alen_in = Lb;
+      launch_inc_init_push(pb, n, A0, c.st);
+      c.launches += 1;
+    }
   }
   if (hipGetLastError() != hipSuccess) return COLOR_EHIP;
   // Worklists binned by active-list length: a loser goes to the bin of its
@@ -753,7 +777,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
           continue;
         }
         if (H->tail_err) return kRcRetryNoTail;  // a grid barrier gave up: the outputs are not valid
-        c.tail_rounds = std::max(0, H->rounds_done - local);
+        c.tail_rounds = std::max(0, H->rounds_done - round0 - local);
         return H->tail_left ? COLOR_ENOCONVERGE : COLOR_OK;
       }
       // cooperative launch refused: per-round launches from here on
@@ -804,11 +828,11 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
 }
 
 template int run_incremental<kD1>(Call&, const GraphView&, const KeySource&, const int32_t*, int32_t*,
-                                  BinLayout&, int32_t*, int*);
+                                  BinLayout&, int32_t*, int*, int);
 template int run_incremental<kD2>(Call&, const GraphView&, const KeySource&, const int32_t*, int32_t*,
-                                  BinLayout&, int32_t*, int*);
+                                  BinLayout&, int32_t*, int*, int);
 template int run_incremental<kPD2>(Call&, const GraphView&, const KeySource&, const int32_t*, int32_t*,
-                                   BinLayout&, int32_t*, int*);
+                                   BinLayout&, int32_t*, int*, int);
 
 // The input contract (COLOR_FLAG_VALIDATE), checked on the device: row
 // offsets, ranges, self-loops, duplicates and symmetry (D1/D2), or that the
@@ -848,7 +872,7 @@ int validate_job(const color_job& j, void* stream) {
 // colors[] and the tentative colors cover.
 template <int MODE>
 static int run_engine(Call& c, const GraphView& g, const KeySource& k, const int32_t* init, int32_t* colors,
-                      int32_t n_total) {
+                      int32_t n_total, int round0 = 0) {
   const int32_t n = g.n;
   BinLayout L;
   RoundBufs rb;
@@ -877,7 +901,7 @@ static int run_engine(Call& c, const GraphView& g, const KeySource& k, const int
     const bool long_walks = MODE != kD1 && avg >= 128.0;
     if (left > 0 && (c.P.engine == COLOR_ENGINE_INCREMENTAL || skewed || long_walks)) {
       int fell_back = 0;
-      const int rc = run_incremental<MODE>(c, g, k, init, colors, L, known, &fell_back);
+      const int rc = run_incremental<MODE>(c, g, k, init, colors, L, known, &fell_back, round0);
       if (!fell_back) {
         c.engine = COLOR_ENGINE_INCREMENTAL;
         return rc;
@@ -888,7 +912,7 @@ static int run_engine(Call& c, const GraphView& g, const KeySource& k, const int
     if ((e = setup_bins<MODE>(c, g, init, colors, n_total, L, rb, known))) return e;
   }
   c.engine = COLOR_ENGINE_PULL;
-  return run_phase<MODE>(c, g, k, L, rb, known, 0, c.P.max_rounds);
+  return run_phase<MODE>(c, g, k, L, rb, known, round0, c.P.max_rounds);
 }
 
 // fixed_ws: a workspace of fixed buffers (the no-allocation entry point's
@@ -1005,11 +1029,14 @@ size_t plan_incremental(int kind, int32_t n, const int32_t* rp1, const int32_t* 
   p->inc_B0 = p->inc_B1 = 4 * entries;
   p->inc_bm = std::max(bm, sets);
   p->inc_wl0 = p->inc_wl1 = 4 * 4 * nn;  // bin regions: at most 4n entries
+  p->inc_T8 = (nn + 3) / 4 * 4;  // as run_incremental sizes it
+  p->inc_done = 4 * (nn / 32 + 1);
   p->scan_tmp = std::max<size_t>(scan, 1);
   size_t t = 0;
   for (size_t b : {p->small, p->T, p->work, p->bin, p->wl0, p->wl1, p->trace, p->deferred, p->deferred_work,
                    p->deferred_done, p->inc_len, p->inc_words, p->inc_fwoff, p->inc_aoff, p->inc_L0, p->inc_Ll,
-                   p->inc_F, p->inc_B0, p->inc_B1, p->inc_bm, p->inc_wl0, p->inc_wl1, p->scan_tmp})
+                   p->inc_F, p->inc_B0, p->inc_B1, p->inc_bm, p->inc_wl0, p->inc_wl1, p->inc_T8, p->inc_done,
+                   p->scan_tmp})
     t += (b + 255) / 256 * 256;
   return t;
 }
@@ -1049,6 +1076,8 @@ void carve_workspace(Workspace* w, char* base, const IncPlan& p) {
   take(w->inc_bm, p.inc_bm);
   take(w->inc_wl0, p.inc_wl0);
   take(w->inc_wl1, p.inc_wl1);
+  take(w->inc_T8, p.inc_T8);
+  take(w->inc_done, p.inc_done);
   take(w->scan_tmp, p.scan_tmp);
 }
 
@@ -1266,19 +1295,19 @@ namespace gcol {
 
 // One rank's distance-2 (MODE kD2) or partial distance-2 (kPD2) step:
 // ghost-uncolored phase 1 on the owned vertices (the two-hop walks pass
-// through ghosts, whose colors and tentative colors are 0), the two-hop
-// boundary detect against the ghosts' fixed colors, and the recoloring of the
-// owned losers with the ghosts' colors as constraints.  Pull engine.
+// through ghosts, whose colors and tentative colors are 0) on the engine the
+// parameters name or the library's choice, the two-hop boundary detect
+// against the ghosts' fixed colors, and the recoloring of the owned losers
+// with the ghosts' colors as constraints on the pull engine.
 template <int MODE>
-static int ghost2_step(int32_t n_owned, int32_t n_ghost, const int32_t* rp1, const int32_t* ci1, const int32_t* rp2,
-                       const int32_t* ci2, const int32_t* gid, const int32_t* ghost_colors, uint32_t seed,
-                       int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats, const color_params* params,
-                       void* stream) {
+static int ghost2_step_once(int32_t n_owned, int32_t n_ghost, const int32_t* rp1, const int32_t* ci1,
+                            const int32_t* rp2, const int32_t* ci2, const int32_t* gid, const int32_t* ghost_colors,
+                            uint32_t seed, int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats,
+                            const color_params* params, void* stream) {
   if (n_owned < 0 || n_ghost < 0) return COLOR_EINVAL;
   if (static_cast<int64_t>(n_owned) + n_ghost >= INT_MAX) return COLOR_EOVERFLOW;
   if (n_owned > 0 && (!rp1 || !ci1 || !rp2 || !ci2 || !gid || !owned_colors)) return COLOR_EINVAL;
   if (n_ghost > 0 && (!ghost_colors || !gid)) return COLOR_EINVAL;
-  if (params && params->engine == COLOR_ENGINE_INCREMENTAL) return COLOR_EINVAL;
   const int32_t m = n_owned + n_ghost;
   Call c;
   int e = begin_call(c, MODE, params, stats, stream, n_owned, m);
@@ -1290,18 +1319,18 @@ static int ghost2_step(int32_t n_owned, int32_t n_ghost, const int32_t* rp1, con
   if ((e = w->aux1.ensure(sizeof(int32_t) * static_cast<size_t>(std::max(n_ghost, 1)), false, c.st))) return e;
   int32_t* Cint = w->C.as<int32_t>();
   KeySource k{nullptr, gid, hash_seed(seed), nullptr};
-  // phase 1: ghosts uncolored (0 constrains nothing and never ties)
+  // phase 1: ghosts uncolored (0 constrains nothing and never ties), on
+  // either engine: the pull engine walks through the ghosts and reads their
+  // zeros; the incremental engine's lists keep the owned members only
+  // (limit), as a ghost can neither constrain nor beat an owned vertex here
   launch_zero_words(Cint + n_owned, static_cast<size_t>(n_ghost), c.st);
   launch_zero_words(w->T.as<int32_t>() + n_owned, static_cast<size_t>(n_ghost), c.st);
   c.launches += 2;
+  GraphView g1{n_owned, n_owned, rp1, ci1, rp2, ci2};
+  int rc = run_engine<MODE>(c, g1, k, nullptr, Cint, m);
+  if (rc != COLOR_OK) return rc == COLOR_ENOCONVERGE ? finish_call(c, stats, -1, rc) : rc;
   GraphView g{n_owned, n_owned, rp1, ci1, rp2, ci2};
   g.limit = m;
-  BinLayout L;
-  RoundBufs rb;
-  int32_t known[kBins];
-  if ((e = setup_bins<MODE>(c, g, nullptr, Cint, m, L, rb, known))) return e;
-  int rc = run_phase<MODE>(c, g, k, L, rb, known, 0, c.P.max_rounds);
-  if (rc != COLOR_OK) return rc == COLOR_ENOCONVERGE ? finish_call(c, stats, -1, rc) : rc;
   if (hipMemcpyAsync(&c.H->rounds_done, &c.S->rounds_done, sizeof(int32_t), hipMemcpyDeviceToHost, c.st) !=
       hipSuccess)
     return COLOR_EHIP;
@@ -1332,17 +1361,24 @@ static int ghost2_step(int32_t n_owned, int32_t n_ghost, const int32_t* rp1, con
     c.launches += 2;
   }
   launch_boundary_uncolor(n_owned, loser, Cint, c.st);
-  // phase 3: ghosts carry their fixed colors; the losers are recolored
-  launch_ghost_fill(n_owned, n_ghost, ghost_colors, Cint, rb.T, &c.S->maxc, c.st);
-  c.launches += 4;
-  launch_zero_words(c.S->cnt[0], 8, c.st);
-  launch_scatter(n_owned, Cint, w->bin.as<int8_t>(), L, c.wl[0], c.S->cnt[0], w->split_vertex.as<int32_t>(), c.st);
+  // phase 3: ghosts carry their fixed colors; the losers are recolored on
+  // either engine (the incremental engine's lists keep the owned members,
+  // the ghosts' colors enter the losers' bitsets once) after a fresh bin
+  // setup: the per-bin totals, maxima, heavy-vertex counters and worklist
+  // counts still hold phase 1's
+  launch_ghost_fill(n_owned, n_ghost, ghost_colors, Cint, w->T.as<int32_t>(), &c.S->maxc, c.st);
   c.launches += 2;
-  if (hipMemcpyAsync(c.H->cnt[0], c.S->cnt[0], sizeof(int32_t) * 8, hipMemcpyDeviceToHost, c.st) != hipSuccess)
-    return COLOR_EHIP;
-  if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
-  for (int i = 0; i < kBins; ++i) known[i] = c.H->cnt[0][i];
-  rc = run_phase<MODE>(c, g, k, L, rb, known, r1, c.P.max_rounds);
+  static_assert(offsetof(Scalars, deferred_grab) == offsetof(Scalars, max_work) + 2 * sizeof(int32_t),
+                "max_work, deferred_cnt and deferred_grab are cleared together");
+  launch_zero_words(c.S->count_all, 16, c.st);
+  launch_zero_words(c.S->cnt, sizeof(c.S->cnt) / 4, c.st);
+  launch_zero_words(&c.S->max_split_work, 1, c.st);
+  launch_zero_words(&c.S->max_work, 4, c.st);
+  launch_zero_words(&c.S->total_work, 2, c.st);
+  c.launches += 5;
+  GraphView g3{n_owned, n_owned, rp1, ci1, rp2, ci2};
+  g3.ids = m;
+  rc = run_engine<MODE>(c, g3, k, Cint, Cint, m, r1);
   if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
   launch_flags_out(n_ghost, gflag, remote_loser, &c.S->remote, c.st);
   launch_copy_i32(n_owned, Cint, owned_colors, c.st);
@@ -1353,6 +1389,25 @@ static int ghost2_step(int32_t n_owned, int32_t n_ghost, const int32_t* rp1, con
     return COLOR_EHIP;
   if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
   return finish_call(c, stats, c.H->aux_max, rc);
+}
+
+// A step whose tail kernel's grid barrier gave up (phase 1 on the
+// incremental engine) starts over with per-round launches only (the same
+// coloring).
+template <int MODE>
+static int ghost2_step(int32_t n_owned, int32_t n_ghost, const int32_t* rp1, const int32_t* ci1, const int32_t* rp2,
+                       const int32_t* ci2, const int32_t* gid, const int32_t* ghost_colors, uint32_t seed,
+                       int32_t* owned_colors, uint8_t* remote_loser, color_stats* stats, const color_params* params,
+                       void* stream) {
+  const int rc = ghost2_step_once<MODE>(n_owned, n_ghost, rp1, ci1, rp2, ci2, gid, ghost_colors, seed, owned_colors,
+                                        remote_loser, stats, params, stream);
+  if (rc != kRcRetryNoTail) return rc;
+  color_params p;
+  if (params) p = *params;
+  else std::memset(&p, 0, sizeof(p));
+  p.flags |= COLOR_FLAG_NO_TAIL;
+  return ghost2_step_once<MODE>(n_owned, n_ghost, rp1, ci1, rp2, ci2, gid, ghost_colors, seed, owned_colors,
+                                remote_loser, stats, &p, stream);
 }
 
 }  // namespace gcol

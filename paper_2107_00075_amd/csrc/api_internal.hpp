@@ -62,6 +62,7 @@ struct Workspace {
   DevBuf T, C, work, bin, wl0, wl1, small, trace, split_vertex, split_ctr, split_flag, split_mask, aux0, aux1;
   DevBuf deferred, inc_len, inc_words, inc_fwoff, inc_aoff, inc_F, inc_L0, inc_Ll, inc_B0, inc_B1, inc_bm, scan_tmp;
   DevBuf inc_wl0, inc_wl1;  // incremental engine: worklists binned by active-list length
+  DevBuf inc_T8, inc_done;  // incremental engine: tentative colors as bytes, committed bits
   DevBuf deferred_work, deferred_done;  // setup: per heavy D2/PD2 vertex, its work and slices done
   DevBuf rank, rk_key0, rk_key1, rk_val0, rk_val1, rk_deg0, rk_deg1, rk_tmp;  // recolorDegrees ranks
   DevBuf gr_rp, gr_ci, gr_cnt, gr_init;  // tentative ghost recoloring: local CSR with ghost rows, start colors
@@ -71,7 +72,7 @@ struct Workspace {
   std::vector<hipEvent_t> events;  // pool for COLOR_FLAG_KERNEL_TIMING
   ~Workspace();
   void release();
-  static constexpr int kNumBuffers = 45;
+  static constexpr int kNumBuffers = 47;
   std::array<DevBuf*, kNumBuffers> buffers();   // every DevBuf above
 };
 
@@ -134,7 +135,7 @@ int color_pd2_fixed(Workspace* ws, int32_t n_rows, int32_t n_cols, const int32_t
 struct IncPlan {
   size_t small, T, work, bin, wl0, wl1, trace, deferred, deferred_work, deferred_done;
   size_t inc_len, inc_words, inc_fwoff, inc_aoff, inc_L0, inc_Ll, inc_F, inc_B0, inc_B1, inc_bm, inc_wl0, inc_wl1,
-      scan_tmp;
+      inc_T8, inc_done, scan_tmp;
 };
 // kind COLOR_KIND_D2: (rp1, ci1) = (rp2, .) = the adjacency; COLOR_KIND_PD2:
 // (rp1, ci1) = the CSC, rp2 = the CSR row offsets.  HOST arrays.  Returns
@@ -148,7 +149,7 @@ int setup_bins(Call& c, const GraphView& g, const int32_t* init, int32_t* C, int
                RoundBufs& rb, int32_t known[kBins]);
 template <int MODE>
 int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32_t* init, int32_t* colors,
-                    BinLayout& L, int32_t known[kBins], int* fell_back);
+                    BinLayout& L, int32_t known[kBins], int* fell_back, int round0 = 0);
 template <int MODE>
 int run_phase(Call& c, const GraphView& g, const KeySource& k, const BinLayout& L, const RoundBufs& base,
               int32_t known[kBins], int round0, int max_rounds);

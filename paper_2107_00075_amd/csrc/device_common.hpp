@@ -69,6 +69,23 @@ __device__ __forceinline__ X ld_mut(const X* p) {
   if constexpr (MUT != 0) return ld_dev(p);
   else return *p;
 }
+template <int MUT, typename X>
+__device__ __forceinline__ void st_mut(X* p, X v) {
+  if constexpr (MUT != 0) st_dev(p, v);
+  else *p = v;
+}
+
+// The row of CSR entry e (0 <= e < rp[n]): the last row whose start is <= e,
+// by binary search over the n row offsets (empty rows are skipped).
+__device__ __forceinline__ int32_t row_of(const int32_t* rp, int32_t n, int32_t e) {
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (rp[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // Where a vertex's key comes from.  key(v) = (p(v), gid(v)) packed into 64
 // bits so that one unsigned compare is the lexicographic compare; the lower

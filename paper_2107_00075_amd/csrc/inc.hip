@@ -116,6 +116,28 @@ __device__ __forceinline__ bool compact_now(const IncBufs& b, int round, int32_t
   return b.A_in != b.A_out || round <= kCompactAlways || ((round + v) & (kCompactPeriod - 1)) == 0;
 }
 
+// The conflict test's gather: a neighbour's tentative color from the byte
+// array while every tentative color fits a byte (4 MB for 2^22 vertices, so
+// the gathers mostly hit L2), else from the 32-bit array.  Committed
+// neighbours hold their own color in both, or 0 in the byte array where
+// they were committed before the call: neither equals a tentative color
+// the vertex could have taken.
+template <int MUT>
+__device__ __forceinline__ int32_t tentative_of(const IncBufs& b, bool t8, int32_t u) {
+  return t8 ? static_cast<int32_t>(ld_mut<MUT>(&b.T8[u])) : ld_mut<MUT>(&b.T[u]);
+}
+
+// The compaction test: u committed, from one bit per vertex (512 KB for
+// 2^22 vertices) instead of its 32-bit color.
+template <int MUT>
+__device__ __forceinline__ bool committed(const IncBufs& b, int32_t u) {
+  return (ld_mut<MUT>(&b.done[u >> 5]) >> (u & 31)) & 1u;
+}
+
+__device__ __forceinline__ void mark_committed(const IncBufs& b, int32_t v) {
+  atomicOr(&b.done[v >> 5], 1u << (v & 31));
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -146,8 +168,9 @@ __device__ __forceinline__ void inc_color_phase(const IncBufs& b, const BinLayou
       for (int i = 0; i < kBins; ++i) atomic_reset_i32(&b.cnt_out[i]);
       atomic_reset_i32(&b.tile_ctr[1]);
       if (M.total > 0) {
-        atomicMax(b.rounds_done, round);
-        if (b.trace && round <= b.trace_cap) st_dev(&b.trace[round - 1], M.total);
+        const int gr = round + b.round_base;
+        atomicMax(b.rounds_done, gr);
+        if (b.trace && gr <= b.trace_cap) st_dev(&b.trace[gr - 1], M.total);
         atomicAdd(&b.acc[0], static_cast<unsigned long long>(M.total));
       }
     }
@@ -177,10 +200,11 @@ __device__ __forceinline__ void inc_color_phase(const IncBufs& b, const BinLayou
       }
     }
     st_dev(&b.T[v], t);
+    if (round <= b.t8_last) st_mut<MUT>(&b.T8[v], static_cast<uint8_t>(t));
     work += static_cast<uint64_t>(ld_mut<MUT>(&b.work[v]));
     lists += static_cast<uint64_t>(ld_mut<MUT>(&b.alen_in[v]));
-    // worklist id, two bitset offsets, the words scanned, static work, T write
-    bytes += 4 + 8 + 4 * static_cast<uint64_t>(min(w + 1, max(nw, 1))) + 4 + 4;
+    // worklist id, two bitset offsets, the words scanned, static work, T write (and its byte)
+    bytes += 4 + 8 + 4 * static_cast<uint64_t>(min(w + 1, max(nw, 1))) + 4 + 4 + (round <= b.t8_last ? 1 : 0);
   }
   work = wsum(work);
   lists = wsum(lists);
@@ -223,6 +247,7 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
   const int first = lane_id() & ~(G - 1);
   const uint64_t gm = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
   const bool first_pass = b.A_in != b.A_out;
+  const bool t8 = round <= b.t8_last;
   for (int32_t idx = gi; idx < count; idx += per_pass) {
     const int32_t v = ld_mut<MUT>(&wl[idx]);
     const int32_t tv = ld_mut<MUT>(&b.T[v]);
@@ -248,7 +273,7 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const bool higher = u[j] >= 0 && (!first_pass || key_of(k, u[j]) > kv);
-        t[j] = higher ? (b.uniform ? tv : ld_mut<MUT>(&b.T[u[j]])) : -1;
+        t[j] = higher ? (b.uniform ? tv : tentative_of<MUT>(b, t8, u[j])) : -1;
         gath += (higher && !b.uniform) ? 1 : 0;
       }
       bool hit = false;
@@ -259,7 +284,8 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
         break;
       }
     }
-    bytes += 4ull * static_cast<uint64_t>(read + gath);  // list entries and tentative colors this lane read
+    // list entries and tentative colors this lane read
+    bytes += 4ull * static_cast<uint64_t>(read) + (t8 ? 1ull : 4ull) * static_cast<uint64_t>(gath);
     if (lose && !compact_now(b, round, v)) {
       if (sub == 0) {
         s_ent[idx] = v;
@@ -277,7 +303,7 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
         bool keep = false, hi = true;
         if (e < len) {
           u = ld_mut<MUT>(&A[e]);
-          keep = b.uniform || ld_mut<MUT>(&b.C[u]) == 0;  // round 1: nobody was committed before it
+          keep = b.uniform || !committed<MUT>(b, u);  // round 1: nobody was committed before it
           if (first_pass) hi = key_of(k, u) > kv;
         }
         const uint64_t bal_h = (__ballot(keep && hi) >> first) & gm;
@@ -321,6 +347,7 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
       }
       if (sub == 0) {
         st_dev(&b.C[v], tv);
+        mark_committed(b, v);
         maxc_acc = max(maxc_acc, tv);
         s_ent[idx] = -1;
         bytes += 20 + 4ull * static_cast<uint64_t>(len + lo_len);  // own fields, C write, the push pass
@@ -375,6 +402,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const bool first_pass = b.A_in != b.A_out;
+  const bool t8 = round <= b.t8_last;
   const int32_t tv = ld_mut<MUT>(&b.T[v]);
   const uint64_t kv = key_of(k, v);
   const int32_t base = ld_mut<MUT>(&b.aoff[v]);
@@ -382,7 +410,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
   const int32_t* A = b.A_in + base;
   constexpr int32_t step = kBlock * kIncBatch;
   bool lose = false;
-  uint32_t read = 0;
+  uint32_t read = 0, gath = 0;
   for (int32_t e0 = 0; e0 < len; e0 += step) {
     int32_t u[kIncBatch], t[kIncBatch];
 #pragma unroll
@@ -396,8 +424,8 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j) {
       const bool higher = u[j] >= 0 && (!first_pass || key_of(k, u[j]) > kv);
-      t[j] = higher ? (b.uniform ? tv : ld_mut<MUT>(&b.T[u[j]])) : -1;
-      read += (higher && !b.uniform) ? 1u : 0u;
+      t[j] = higher ? (b.uniform ? tv : tentative_of<MUT>(b, t8, u[j])) : -1;
+      gath += (higher && !b.uniform) ? 1u : 0u;
     }
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j)
@@ -407,7 +435,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
       break;
     }
   }
-  bytes += 4ull * read;  // list entries and tentative colors this thread read
+  bytes += 4ull * read + (t8 ? 1ull : 4ull) * gath;  // list entries and tentative colors this thread read
   if (lose && !compact_now(b, round, v)) {
     if (tid == 0) {
       const int nb = inc_bin_of(L, first_pass ? len : len + ld_mut<MUT>(&b.llen[v]));
@@ -434,7 +462,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
       }
 #pragma unroll
       for (int j = 0; j < kIncBatch; ++j) {
-        const bool keep = u[j] >= 0 && (b.uniform || ld_mut<MUT>(&b.C[u[j]]) == 0);
+        const bool keep = u[j] >= 0 && (b.uniform || !committed<MUT>(b, u[j]));
         const bool hi = !first_pass || (u[j] >= 0 && key_of(k, u[j]) > kv);
         keep_hi |= (keep && hi) ? (1u << j) : 0u;
         keep_lo |= (keep && !hi) ? (1u << j) : 0u;
@@ -489,7 +517,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
         u[j] = q < lo_len ? ld_mut<MUT>(&A[cap - 1 - q]) : -1;
       }
 #pragma unroll
-      for (int j = 0; j < kIncBatch; ++j) keep |= (u[j] >= 0 && ld_mut<MUT>(&b.C[u[j]]) == 0) ? (1u << j) : 0u;
+      for (int j = 0; j < kIncBatch; ++j) keep |= (u[j] >= 0 && !committed<MUT>(b, u[j])) ? (1u << j) : 0u;
       const int32_t cnt = __builtin_popcount(keep);
       int32_t incl = cnt;
 #pragma unroll
@@ -541,6 +569,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
     }
     if (tid == 0) {
       st_dev(&b.C[v], tv);
+      mark_committed(b, v);
       maxc_acc = max(maxc_acc, tv);
       bytes += 20 + 4ull * static_cast<uint64_t>(len + lo_len);  // own fields, C write, the push pass
     }
@@ -808,7 +837,8 @@ bool launch_inc_tail(const KeySource& k, const IncRoundSet& set, const BinLayout
 // each neighbour's row).  PD2: sum over the rows of column v of deg(row) - 1
 // = work(v) - 2 (rows of v), work counting each row entry and the row's
 // columns.  words(v): bitset words covering colors
-// 1..min(len, n)+1, the largest first fit v can ever take.
+// 1..min(len, ids)+1, the largest first fit v can ever take (ids: the
+// vertices a walk can reach, g.ids or else n).
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void inc_sizes_kernel(GraphView g, const int32_t* work, int32_t* len,
                                                            int32_t* words, int32_t* alen0,
@@ -831,11 +861,13 @@ __global__ __launch_bounds__(kBlock) void inc_sizes_kernel(GraphView g, const in
   const int32_t lc = static_cast<int32_t>(l > INT_MAX ? INT_MAX : l);
   st_dev(&len[v], lc);
   st_dev(&alen0[v], lc);
-  st_dev(&words[v], static_cast<int32_t>(min<int64_t>(l, g.n) / 32 + 1));
+  st_dev(&words[v], static_cast<int32_t>(min<int64_t>(l, max(g.n, g.ids)) / 32 + 1));
 }
 
 // Materializes the two-hop list of a vertex with a short first hop (one
-// thread).  At most len(v) entries are written.
+// thread).  At most len(v) entries are written.  Every fill keeps only
+// members below g.limit: the colorable vertices, or (a rank's ghost step,
+// whose walks pass through ghosts) the owned ones.
 template <int MODE>
 // Every fill stores the number of entries it wrote as the list length
 // (alen), so that a list never exposes an unwritten slot, even where the
@@ -849,10 +881,10 @@ __global__ __launch_bounds__(kBlock) void inc_fill_kernel(GraphView g, const int
   int32_t o = base;
   for (int32_t q = g.rp[v]; q < g.rp[v + 1]; ++q) {
     const int32_t u = g.ci[q];
-    if (MODE == kD2 && o < end) st_dev(&A[o++], u);
+    if (MODE == kD2 && u < g.limit && o < end) st_dev(&A[o++], u);
     for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
       const int32_t x = g.ci2[p];
-      if (x != v && o < end) st_dev(&A[o++], x);
+      if (x != v && x < g.limit && o < end) st_dev(&A[o++], x);
     }
   }
   st_dev(&alen[v], o - base);
@@ -875,8 +907,11 @@ __global__ __launch_bounds__(kBlock) void inc_fill_wave_kernel(GraphView g, cons
     int32_t u = -1, cnt = 0;
     if (q < q1) {
       u = g.ci[q];
-      cnt = (MODE == kD2 ? 1 : 0);
-      for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) cnt += g.ci2[p] != v;
+      cnt = (MODE == kD2 && u < g.limit) ? 1 : 0;
+      for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
+        const int32_t x = g.ci2[p];
+        cnt += x != v && x < g.limit;
+      }
     }
     int32_t incl = cnt;
 #pragma unroll
@@ -886,10 +921,10 @@ __global__ __launch_bounds__(kBlock) void inc_fill_wave_kernel(GraphView g, cons
     }
     int32_t o = out + incl - cnt;
     if (u >= 0) {
-      if (MODE == kD2 && o < end) st_dev(&A[o++], u);
+      if (MODE == kD2 && u < g.limit && o < end) st_dev(&A[o++], u);
       for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
         const int32_t x = g.ci2[p];
-        if (x != v && o < end) st_dev(&A[o++], x);
+        if (x != v && x < g.limit && o < end) st_dev(&A[o++], x);
       }
     }
     out += __shfl(incl, kWave - 1, kWave);
@@ -925,8 +960,11 @@ __global__ __launch_bounds__(kBlock) void inc_fill_heavy_kernel(GraphView g, con
       int32_t u = -1, cnt = 0;
       if (q < g.rp[v + 1]) {
         u = g.ci[q];
-        cnt = (MODE == kD2 ? 1 : 0);
-        for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) cnt += g.ci2[p] != v;
+        cnt = (MODE == kD2 && u < g.limit) ? 1 : 0;
+        for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
+          const int32_t x = g.ci2[p];
+          cnt += x != v && x < g.limit;
+        }
       }
       // inclusive scan of cnt within the wavefront, then across wavefronts
       int32_t incl = cnt;
@@ -944,10 +982,10 @@ __global__ __launch_bounds__(kBlock) void inc_fill_heavy_kernel(GraphView g, con
       }
       int32_t o = out + wbase + incl - cnt;
       if (u >= 0) {
-        if (MODE == kD2 && o < end) st_dev(&A[o++], u);
+        if (MODE == kD2 && u < g.limit && o < end) st_dev(&A[o++], u);
         for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
           const int32_t x = g.ci2[p];
-          if (x != v && o < end) st_dev(&A[o++], x);
+          if (x != v && x < g.limit && o < end) st_dev(&A[o++], x);
         }
       }
       out += tot;
@@ -972,7 +1010,57 @@ __global__ __launch_bounds__(kBlock) void inc_init_push_kernel(IncBufs b, int32_
   }
 }
 
+// Committed colors of every walk member, list member or not (a rank's
+// ghosts above g.limit), enter the bitset of each uncolored vertex: one
+// thread per first-hop entry, which walks its second-hop row.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void inc_init_pull_kernel(GraphView g, int32_t nnz1, const int32_t* C,
+                                                               const int32_t* fw_off, uint32_t* F) {
+  const int32_t q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= nnz1) return;
+  const int32_t v = row_of(g.rp, g.n, q);
+  if (ld_dev(&C[v]) != 0) return;
+  const int32_t w0 = fw_off[v];
+  const int32_t nw = fw_off[v + 1] - w0;
+  auto take = [&](int32_t x) {
+    const int32_t c = ld_dev(&C[x]);
+    const int32_t w = (c - 1) >> 5;
+    if (c != 0 && w < nw) {
+      const uint32_t bit = 1u << ((c - 1) & 31);
+      if (!(F[w0 + w] & bit)) atomicOr(&F[w0 + w], bit);
+    }
+  };
+  const int32_t u = g.ci[q];
+  if (MODE == kD2) take(u);
+  for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
+    const int32_t x = g.ci2[p];
+    if (x != v) take(x);
+  }
+}
+
 static inline int blocks_for(int64_t n) { return static_cast<int>((n + kBlock - 1) / kBlock); }
+
+// Per-call state of the byte and bit arrays: T8 cleared (0 is no tentative
+// color), the committed bit of every vertex with an initial color set.  One
+// thread per bitmap word.
+__global__ __launch_bounds__(kBlock) void inc_state_init_kernel(int32_t n, const int32_t* C, uint8_t* T8,
+                                                                uint32_t* done) {
+  const int32_t w = blockIdx.x * kBlock + threadIdx.x;
+  if (w > n / 32) return;
+  uint32_t bits = 0;
+  for (int i = 0; i < 32; ++i) {
+    const int32_t v = 32 * w + i;
+    if (v < n) {
+      bits |= (ld_dev(&C[v]) != 0 ? 1u : 0u) << i;
+      T8[v] = 0;
+    }
+  }
+  done[w] = bits;
+}
+
+void launch_inc_state_init(int32_t n, const int32_t* C, uint8_t* T8, uint32_t* done, hipStream_t st) {
+  hipLaunchKernelGGL(inc_state_init_kernel, dim3(blocks_for(n / 32 + 1)), dim3(kBlock), 0, st, n, C, T8, done);
+}
 
 void launch_inc_color(const IncBufs& b, const BinLayout& L, int round, int grid, hipStream_t st) {
   hipLaunchKernelGGL(inc_color_kernel, dim3(grid), dim3(kBlock), 0, st, b, L, round);
@@ -1074,10 +1162,11 @@ __global__ __launch_bounds__(kBlock) void inc_mark_kernel(GraphView g, const int
     const int32_t u = g.ci[q];
     // a plain (cacheable) read first skips most atomics of bits already set;
     // a stale read only costs an atomic that was not needed
-    if (MODE == kD2 && u != v && !(m[u >> 5] & (1u << (u & 31)))) atomicOr(&m[u >> 5], 1u << (u & 31));
+    if (MODE == kD2 && u != v && u < g.limit && !(m[u >> 5] & (1u << (u & 31))))
+      atomicOr(&m[u >> 5], 1u << (u & 31));
     for (int32_t p = g.rp2[u]; p < g.rp2[u + 1]; ++p) {
       const int32_t x = g.ci2[p];
-      if (x != v && !(m[x >> 5] & (1u << (x & 31)))) atomicOr(&m[x >> 5], 1u << (x & 31));
+      if (x != v && x < g.limit && !(m[x >> 5] & (1u << (x & 31)))) atomicOr(&m[x >> 5], 1u << (x & 31));
     }
   }
 }
@@ -1150,6 +1239,14 @@ void launch_inc_dedup(int32_t n, const int32_t* aoff, int32_t* alen, int32_t* A,
 void launch_inc_init_push(const IncBufs& b, int32_t n, const int32_t* A0, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(inc_init_push_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, st, b, n, A0);
 }
+template <int MODE>
+void launch_inc_init_pull(const GraphView& g, int32_t nnz1, const IncBufs& b, hipStream_t st) {
+  if (nnz1 > 0)
+    hipLaunchKernelGGL(inc_init_pull_kernel<MODE>, dim3(blocks_for(nnz1)), dim3(kBlock), 0, st, g, nnz1, b.C,
+                       b.fw_off, b.F);
+}
+template void launch_inc_init_pull<kD2>(const GraphView&, int32_t, const IncBufs&, hipStream_t);
+template void launch_inc_init_pull<kPD2>(const GraphView&, int32_t, const IncBufs&, hipStream_t);
 template void launch_inc_sizes<kD1>(const GraphView&, const int32_t*, int32_t*, int32_t*, int32_t*,
                                     unsigned long long*, hipStream_t);
 template void launch_inc_sizes<kD2>(const GraphView&, const int32_t*, int32_t*, int32_t*, int32_t*,

@@ -25,6 +25,10 @@ struct IncBufs {
                                // every tentative color is 1
   int32_t defer_split;         // round 1 without initial colors: losers keep the read-only lists
                                // untouched (round 2 splits and compacts them)
+  uint8_t* T8;                 // tentative colors as bytes, written and read in rounds <= t8_last
+  int32_t t8_last;             // last round whose tentative colors all fit a byte: a color taken in
+                               // round r is at most (largest initial color) + r
+  uint32_t* done;              // committed vertices, one bit each (the compaction test)
   const int32_t* fw_off;       // bitset word offsets, n+1 entries
   uint32_t* F;                 // forbidden-color bitsets (bit c-1 = color c)
   int32_t* maxc;               // largest committed color
@@ -35,6 +39,8 @@ struct IncBufs {
   int32_t* trace;
   int32_t trace_cap;
   int32_t* rounds_done;
+  int32_t round_base = 0;      // rounds the call ran before this engine run (trace and rounds_done
+                               // count from there; the engine's own logic counts from 1)
 };
 
 // Vertices per light chunk of a bin with `lanes` lanes per vertex: a chunk
@@ -117,6 +123,12 @@ template <int MODE>
 void launch_inc_bitmap_sets(const GraphView& g, const int32_t* deferred, int32_t i0, int32_t nb, uint32_t* bm,
                             int32_t words, const int32_t* aoff, int32_t* alen, int32_t* A, hipStream_t st);
 void launch_inc_init_push(const IncBufs& b, int32_t n, const int32_t* A0, hipStream_t st);
+// Initial colors of every member of each uncolored vertex's walk, lists or
+// not (g.ids > g.limit), into its bitset; nnz1 = g.rp[g.n].
+template <int MODE>
+void launch_inc_init_pull(const GraphView& g, int32_t nnz1, const IncBufs& b, hipStream_t st);
+// T8 cleared and the committed bits (n / 32 + 1 words) set from C.
+void launch_inc_state_init(int32_t n, const int32_t* C, uint8_t* T8, uint32_t* done, hipStream_t st);
 // Removes duplicates from the long two-hop lists (alen in: capacity, out:
 // distinct entries); bitmaps: grid x words zeroed uint32 (left zeroed).
 int dedup_grid(int32_t words);

@@ -19,11 +19,15 @@ constexpr int kOvfWords = 1024;  // LDS overflow bitset of the workgroup bins: 3
 
 struct GraphView {
   int32_t n;       // colorable vertices (ids [0, n))
-  int32_t limit;   // D1: neighbour ids >= limit are ignored (ghost-blind phase)
+  int32_t limit;   // D1: neighbour ids >= limit are ignored (ghost-blind phase); D2/PD2: the
+                   // incremental engine's lists keep members below limit only
   const int32_t* rp;   // hop 1: D1/D2 adjacency row_ptr; PD2 CSC col_ptr (column -> rows)
   const int32_t* ci;   // hop 1: D1/D2 adjacency col_idx; PD2 CSC row_idx
   const int32_t* rp2;  // hop 2: D2 adjacency row_ptr; PD2 CSR row_ptr (row -> columns)
   const int32_t* ci2;  // hop 2: D2 adjacency col_idx; PD2 CSR col_idx
+  int32_t ids = 0;     // D2/PD2: ids the walks reach (0: n); above limit, such members are
+                       // constraints only (a rank's ghosts): the incremental engine keeps
+                       // them out of its lists and takes their colors once, before round 1
 };
 
 struct BinLayout {

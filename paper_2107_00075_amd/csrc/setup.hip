@@ -370,7 +370,6 @@ __global__ __launch_bounds__(kBlock) void priority_kernel(int32_t n, const int32
 // pairs are judged on the phase-1 colors (a thread per owned-row entry, so a
 // hub's row spreads over many threads); losers are uncolored afterwards by
 // boundary_uncolor_kernel.  loser must be zeroed first.
-__device__ __forceinline__ int32_t row_of(const int32_t* rp, int32_t n, int32_t e);
 
 __global__ __launch_bounds__(kBlock) void boundary_kernel(int32_t n_owned, const int32_t* rp,
                                                           const int32_t* ci, const int32_t* C,
@@ -403,16 +402,6 @@ __global__ __launch_bounds__(kBlock) void boundary_kernel(int32_t n_owned, const
 // count is of distinct (v, x) pairs: pass 1 counts the conflicting entries,
 // pass 2 inserts them into an open-addressing set of (v, x) keys sized for
 // them and counts the insertions that found an empty slot.
-__device__ __forceinline__ int32_t row_of(const int32_t* rp, int32_t n, int32_t e) {
-  int32_t lo = 0, hi = n - 1;  // the last row whose start is <= e
-  while (lo < hi) {
-    const int32_t mid = (lo + hi + 1) >> 1;
-    if (rp[mid] <= e) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;

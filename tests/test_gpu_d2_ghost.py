@@ -38,6 +38,18 @@ def same(got, rl, st, ref, what):
 
 MAPPINGS = [{}, dict(bin_hi=(2, 8, 16, 40), lanes=(1, 2, 64), split_chunks=3),
             dict(bin_hi=(1, 2, 3, 4), lanes=(8, 32, 4), split_chunks=7)]
+# phase 1 on the library's choice, the pull engine, the incremental engine
+# with its tail kernel (a low threshold so that small graphs reach it) and
+# with per-round launches only
+ENGINES = [dict(engine=0), dict(engine=1), dict(engine=2, tail_threshold=1 << 20), dict(engine=2, flags=2)]
+
+
+def configs():
+    for mp in MAPPINGS:
+        yield mp
+    for en in ENGINES:
+        yield en
+    yield dict(MAPPINGS[1], engine=2)
 
 
 def d2_cases():
@@ -58,7 +70,7 @@ def test_d2_ghost_matches_oracle(gc, which):
     lg = gg.ghost_local_graph(g, owner, part, 2, gcol)
     ref = oracle.color_d2_ghost(lg, seed=7)
     assert ref.boundary_conflicts > 0
-    for mp in MAPPINGS:
+    for mp in configs():
         c, rl, st = gc.color_d2_ghost(lg.n_owned, lg.n_ghost, lg.n_g1, dev(lg.row_ptr), dev(lg.col), dev(lg.gid),
                                       dev(lg.ghost_colors), seed=7, params=gc.Params(**mp), trace_cap=4096)
         torch.cuda.synchronize()
@@ -73,7 +85,7 @@ def test_pd2_ghost_matches_oracle(gc, seed):
     lp = gg.pd2_local_pattern(b, owner, seed % 4, gcol)
     ref = oracle.color_pd2_ghost(lp, seed=seed)
     assert ref.boundary_conflicts > 0
-    for mp in MAPPINGS:
+    for mp in configs():
         c, rl, st = gc.color_pd2_ghost(lp.n_owned, lp.n_ghost, lp.n_rows, dev(lp.col_ptr), dev(lp.row_idx),
                                        dev(lp.row_ptr), dev(lp.col_idx), dev(lp.gid), dev(lp.ghost_colors),
                                        seed=seed, params=gc.Params(**mp), trace_cap=4096)
@@ -88,3 +100,41 @@ def test_ghost2_without_ghosts_is_the_plain_call(gc):
     c2, _ = gc.color_d2(dev(g.row_ptr), dev(g.col), seed=3)
     torch.cuda.synchronize()
     assert np.array_equal(c.cpu().numpy(), c2.cpu().numpy()) and st.boundary_conflicts == 0
+
+
+def test_pd2_ghost_heavy_owned_columns(gc):
+    """The heaviest columns owned by the rank: their lists (first hop above
+    1,024 rows) are built as bitmap sets, which keep owned members only."""
+    b = gg.bipartite_powerlaw(60000, 8000, 6, 2.1, 5)
+    deg = np.diff(b.col_ptr)
+    owner = gg.hash_partition(b.n_cols, 4, 5)
+    owner[np.argsort(deg)[-12:]] = 0
+    assert deg[owner == 0].max() > 1024
+    gcol = np.random.default_rng(5).integers(1, 80, b.n_cols).astype(np.int32)
+    lp = gg.pd2_local_pattern(b, owner, 0, gcol)
+    ref = oracle.color_pd2_ghost(lp, seed=4)
+    for mp in ENGINES:
+        c, rl, st = gc.color_pd2_ghost(lp.n_owned, lp.n_ghost, lp.n_rows, dev(lp.col_ptr), dev(lp.row_idx),
+                                       dev(lp.row_ptr), dev(lp.col_idx), dev(lp.gid), dev(lp.ghost_colors),
+                                       seed=4, params=gc.Params(**mp), trace_cap=4096)
+        torch.cuda.synchronize()
+        same(c.cpu().numpy(), rl.cpu().numpy(), st, ref, f"PD2 heavy {mp}")
+        if mp.get("engine") == 2:
+            assert st.engine == gc.ENGINE_INCREMENTAL
+
+
+def test_d2_ghost_heavy_hubs(gc):
+    """D2 on an R-MAT part whose hubs have first hops above 1,024 entries."""
+    g = gg.rmat(13, 8, 6)
+    owner = gg.hash_partition(g.n, 8, 6)
+    deg = g.degrees()
+    owner[np.argsort(deg)[-8:]] = 1
+    assert deg[owner == 1].max() > 1024
+    gcol = np.random.default_rng(6).integers(1, 200, g.n).astype(np.int32)
+    lg = gg.ghost_local_graph(g, owner, 1, 2, gcol)
+    ref = oracle.color_d2_ghost(lg, seed=2)
+    for mp in ENGINES:
+        c, rl, st = gc.color_d2_ghost(lg.n_owned, lg.n_ghost, lg.n_g1, dev(lg.row_ptr), dev(lg.col), dev(lg.gid),
+                                      dev(lg.ghost_colors), seed=2, params=gc.Params(**mp), trace_cap=4096)
+        torch.cuda.synchronize()
+        same(c.cpu().numpy(), rl.cpu().numpy(), st, ref, f"D2 hubs {mp}")
