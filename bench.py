@@ -273,25 +273,25 @@ def bench_d1(args, torch, gc, dev):
 
     # recolorDegrees (Section 3.3) on the R-MAT leg: colors and time against
     # the hash key of the timed steps
-    rd = None
-    name, g, rp, ci, colors = graphs[1]
-    rd_params = gc.Params(flags=gc.COLOR_FLAG_RECOLOR_DEGREES)
-    gc.color_d1(rp, ci, seed=1, out=colors, params=rd_params)
-    rd_ms = []
-    for _ in range(3):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, st = gc.color_d1(rp, ci, seed=1, out=colors, params=rd_params)
-        torch.cuda.synchronize()
-        rd_ms.append((time.perf_counter() - t0) * 1e3)
-    hash_st = stats[-1][1]
-    rd = {"graph": name, "colors": st.num_colors, "rounds": st.rounds, "ms": round(sorted(rd_ms)[1], 3),
-          "hash_key_colors": hash_st.num_colors, "hash_key_rounds": hash_st.rounds,
-          "hash_key_kernel_ms": round(per_graph[name]["kernel_ms"], 3)}
-    log(f"[bench] recolorDegrees on {name}: {st.num_colors} colors in {rd['ms']:.1f} ms "
-        f"(hash key: {hash_st.num_colors} colors)")
-
-    copy = stream_copy(torch, dev)
+    rd = copy = None
+    if not args.no_extras:
+        name, g, rp, ci, colors = graphs[1]
+        rd_params = gc.Params(flags=gc.COLOR_FLAG_RECOLOR_DEGREES)
+        gc.color_d1(rp, ci, seed=1, out=colors, params=rd_params)
+        rd_ms = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = gc.color_d1(rp, ci, seed=1, out=colors, params=rd_params)
+            torch.cuda.synchronize()
+            rd_ms.append((time.perf_counter() - t0) * 1e3)
+        hash_st = stats[-1][1]
+        rd = {"graph": name, "colors": st.num_colors, "rounds": st.rounds, "ms": round(sorted(rd_ms)[1], 3),
+              "hash_key_colors": hash_st.num_colors, "hash_key_rounds": hash_st.rounds,
+              "hash_key_kernel_ms": round(per_graph[name]["kernel_ms"], 3)}
+        log(f"[bench] recolorDegrees on {name}: {st.num_colors} colors in {rd['ms']:.1f} ms "
+            f"(hash key: {hash_st.num_colors} colors)")
+        copy = stream_copy(torch, dev)
 
     cpu = cpu_all = None
     if not args.no_cpu_baseline:
@@ -549,30 +549,53 @@ def bench_serve(args, torch, gc, dev):
             return srv.submit(3, b.row_ptr, b.col_idx, b.col_ptr, b.row_idx, seed=s.seed)[0]
         return srv.submit(s.kind, s.graph.row_ptr, s.graph.col, seed=s.seed)[0]
 
-    def run(rate):
-        """Open loop at `rate` jobs/s (None: all at t=0).  Returns latencies (s) and makespan."""
+    def run(rate, keep=None):
+        """Open loop at `rate` jobs/s (None: all at t=0).  Returns latencies (s) and makespan.
+        keep: a list that receives every job's host colors, in stream order."""
         rng = np.random.default_rng(123)
         gaps = rng.exponential(1.0 / rate, len(specs)) if rate else np.zeros(len(specs))
         arrive = np.cumsum(gaps)
         srv = gc.ColorServer(budget, max_slots=args.slots)
         lat, pending = [], {}
+        index = {}
         nxt = 0
         t0 = time.perf_counter()
         try:
             while nxt < len(specs) or pending:
                 now = time.perf_counter() - t0
                 while nxt < len(specs) and arrive[nxt] <= now:
-                    pending[submit(srv, specs[nxt])] = arrive[nxt]
+                    jid = submit(srv, specs[nxt])
+                    pending[jid] = arrive[nxt]
+                    index[jid] = nxt
                     nxt += 1
                 for jid in list(pending):
-                    if srv.poll(jid) is not None:
+                    r = srv.poll(jid)
+                    if r is not None:
                         lat.append(time.perf_counter() - t0 - pending.pop(jid))
+                        if keep is not None:
+                            keep[index[jid]] = r[0]
         finally:
             srv.close()
         return np.array(lat), time.perf_counter() - t0
 
-    _, span0 = run(None)  # warm-up (library and page-in)
+    served = [None] * len(specs)
+    _, span0 = run(None, keep=served)  # warm-up (library and page-in); its colorings are checked below
     log(f"[bench] serve warm-up: {span0:.2f} s")
+    # every served coloring against the plain single-graph call of its kind
+    same = True
+    for s, got in zip(specs, served):
+        if s.kind == 3:
+            b = s.pattern
+            ref, _ = gc.color_pd2(*(torch.from_numpy(a).to(dev) for a in (b.row_ptr, b.col_idx, b.col_ptr,
+                                                                          b.row_idx)), seed=s.seed)
+        else:
+            fn = gc.color_d2 if s.kind == 2 else gc.color_d1
+            ref, _ = fn(torch.from_numpy(s.graph.row_ptr).to(dev), torch.from_numpy(s.graph.col).to(dev),
+                        seed=s.seed)
+        if got is None or not np.array_equal(ref.cpu().numpy(), np.asarray(got)):
+            same = False
+            break
+    log(f"[bench] served colorings identical to the plain calls: {same}")
     lat_closed, span = run(None)
     sat = len(specs) / span
     log(f"[bench] serve closed-loop: {sat:.1f} graphs/s, p50 {np.percentile(lat_closed, 50) * 1e3:.1f} ms")
@@ -597,11 +620,13 @@ def bench_serve(args, torch, gc, dev):
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"{len(specs)} jobs as --workload batch, Poisson arrivals at 0.5/0.8/1.2x the "
+        "config": {"workload": f"{len(specs)} jobs as the batch workload (n log-uniform [1e3, {args.n_max:g}]), "
+                               f"Poisson arrivals at 0.5/0.8/1.2x the "
                                f"closed-loop rate; server budget {args.serve_budget_gib} GiB, {args.slots} slots",
                    "closed_loop_graphs_per_s": round(sat, 1),
                    "closed_loop_p50_ms": round(float(np.percentile(lat_closed, 50)) * 1e3, 3),
                    "loads": loads},
+        "identical_colorings": bool(same),
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -955,6 +980,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-d2pd2", action="store_true", help="d1: skip the D2 + PD2 block of the line")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="d1: skip the recolorDegrees and copy-ceiling blocks (after the timed steps), so that a "
+                         "profile of the run holds the timed steps' kernels only")
     ap.add_argument("--workload", default="d1", choices=["d1", "d2pd2", "batch", "serve", "ghost", "dist", "ghost2"])
     ap.add_argument("--ghost-scale", type=int, default=24, help="ghost: R-MAT scale of the partitioned graph")
     ap.add_argument("--jobs", type=int, default=300, help="batch/serve: jobs in the stream")

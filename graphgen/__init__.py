@@ -531,23 +531,27 @@ class JobSpec:
 
 def job_stream(count: int, seed: int, n_min: int = 1_000, n_max: int = 1_000_000,
                rate: float | None = None) -> list:
-    """count jobs.  n ~ log-uniform [n_min, n_max]; family in {ER (mean degree
-    U{8..64}), stencil (2D 5/9-point or 3D 7/27-point, side = round(n^(1/dim))),
-    R-MAT (scale = round(log2 n), edge factor U{8..16})} with equal
-    probability; kind D1/D2/PD2 with probability 0.7/0.2/0.1, D2 and PD2 only
-    over the ER and stencil families (a D2 coloring of a power-law graph needs
-    at least max-degree + 1 rounds).  rate: Poisson arrivals (jobs/s), else
-    all arrive at 0."""
+    """count jobs.  n ~ log-uniform [n_min, n_max]; kind D1/D2/PD2 with
+    probability 0.7/0.2/0.1; family in {ER (mean degree U{8..64}), stencil
+    (2D 5/9-point or 3D 7/27-point, side = round(n^(1/dim))), R-MAT (scale =
+    round(log2 n), edge factor U{8..16})}, each with probability 1/3 overall.
+    D2 and PD2 jobs use the ER and stencil families only (a D2 coloring of a
+    power-law graph needs at least max-degree + 1 rounds), so the kind is
+    drawn first and a D1 job is R-MAT with probability (1/3) / 0.7 = 10/21,
+    ER or stencil with 11/42 each; a D2/PD2 job is ER or stencil with 1/2
+    each.  rate: Poisson arrivals (jobs/s), else all arrive at 0."""
     rng = np.random.default_rng(seed)
     jobs = []
     t = 0.0
     for i in range(count):
         n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
-        fam = ("er", "stencil", "rmat")[int(rng.integers(0, 3))]
         u = rng.uniform()
         kind = 1 if u < 0.7 else (2 if u < 0.9 else 3)
-        if fam == "rmat":
-            kind = 1
+        f = rng.uniform()
+        if kind == 1:
+            fam = "rmat" if f < 10 / 21 else ("er" if f < 10 / 21 + 11 / 42 else "stencil")
+        else:
+            fam = "er" if f < 0.5 else "stencil"
         gseed = int(rng.integers(0, 2**31 - 1))
         if fam == "er":
             g = erdos_renyi(n, float(rng.integers(8, 65)), gseed)
