@@ -584,10 +584,11 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
     return COLOR_EHIP;
   if (hipStreamSynchronize(c.st) != hipSuccess) return COLOR_EHIP;
   const size_t list_entries = std::max<size_t>(1, total_list);
-  if ((e = w->inc_F.ensure(sizeof(uint32_t) * static_cast<size_t>(std::max(fw_total, 1)), false, c.st))) return e;
+  // word 0 of every vertex's bitset, then the further words
+  const size_t f_words = static_cast<size_t>(n) + static_cast<size_t>(fw_total);
+  if ((e = w->inc_F.ensure(sizeof(uint32_t) * f_words, false, c.st))) return e;
   if ((e = w->inc_B0.ensure(sizeof(int32_t) * list_entries, false, c.st))) return e;
-  if (hipMemsetAsync(w->inc_F.p, 0, sizeof(uint32_t) * static_cast<size_t>(std::max(fw_total, 1)), c.st) !=
-      hipSuccess)
+  if (hipMemsetAsync(w->inc_F.p, 0, sizeof(uint32_t) * f_words, c.st) != hipSuccess)
     return COLOR_EHIP;
   // Round 1 reads the unsplit lists (D1: the adjacency itself; D2/PD2: the
   // materialized two-hop lists) and its losers write their lists, split by
@@ -637,6 +638,7 @@ int run_incremental(Call& c, const GraphView& g, const KeySource& k, const int32
   ib.aoff = aoff;
   ib.fw_off = w->inc_fwoff.as<int32_t>();
   ib.F = w->inc_F.as<uint32_t>();
+  ib.Fx = ib.F + n;
   ib.maxc = &S->maxc;
   ib.acc = S->visits;
   ib.trace = w->trace.as<int32_t>();

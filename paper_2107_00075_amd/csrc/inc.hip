@@ -84,15 +84,24 @@ __device__ __forceinline__ uint64_t wsum(uint64_t x) {
   return x;
 }
 
-// Sets bit c-1 of F[x] unless it is already set (read first: most pushes
-// repeat a small color that an earlier neighbour already pushed).
+// Word w of x's bitset: word 0 (colors 1..32) in the dense array F, one
+// per vertex, so that a push of a small color (every push of the first 32
+// rounds) reads no offsets; words 1.. at fw_off[x] in Fx.  nullptr: beyond
+// any color x can take, irrelevant to its first fit.
+template <int MUT>
+__device__ __forceinline__ uint32_t* f_word(const IncBufs& b, int32_t x, int32_t w) {
+  if (w == 0) return b.F + x;
+  const int32_t w0 = ld_mut<MUT>(&b.fw_off[x]);
+  if (w > ld_mut<MUT>(&b.fw_off[x + 1]) - w0) return nullptr;
+  return b.Fx + w0 + (w - 1);
+}
+
+// Sets bit c-1 of x's bitset unless it is already set (read first: most
+// pushes repeat a small color that an earlier neighbour already pushed).
 template <int MUT>
 __device__ __forceinline__ void push_color(const IncBufs& b, int32_t x, int32_t c, uint64_t& pushes) {
-  const int32_t w0 = ld_mut<MUT>(&b.fw_off[x]);
-  const int32_t nw = ld_mut<MUT>(&b.fw_off[x + 1]) - w0;
-  const int32_t w = (c - 1) >> 5;
-  if (w >= nw) return;  // beyond any color x can take: irrelevant to its first fit
-  uint32_t* p = b.F + w0 + w;
+  uint32_t* p = f_word<MUT>(b, x, (c - 1) >> 5);
+  if (!p) return;
   const uint32_t bit = 1u << ((c - 1) & 31);
   if (!(ld_mut<MUT>(p) & bit)) {
     atomicOr(p, bit);
@@ -188,23 +197,30 @@ __device__ __forceinline__ void inc_color_phase(const IncBufs& b, const BinLayou
       ++bin;
     }
     const int32_t v = ld_mut<MUT>(&b.wl_in[L.off[bin] + j]);
-    const int32_t w0 = ld_mut<MUT>(&b.fw_off[v]);
-    const int32_t nw = min(ld_mut<MUT>(&b.fw_off[v + 1]) - w0, wmax);
-    int32_t t = 32 * nw + 1;
-    int32_t w = 0;
-    for (; w < nw; ++w) {
-      const uint32_t x = ld_mut<MUT>(&b.F[w0 + w]);
-      if (x != ~0u) {
-        t = 32 * w + __builtin_ctz(~x) + 1;
-        break;
+    // word 0 first; the offsets of the further words only when it is full
+    const uint32_t x0 = ld_mut<MUT>(&b.F[v]);
+    int32_t t, w = 0, nw = 1;
+    if (x0 != ~0u || wmax == 1) {
+      t = x0 != ~0u ? __builtin_ctz(~x0) + 1 : 33;
+    } else {
+      const int32_t w0 = ld_mut<MUT>(&b.fw_off[v]);
+      nw = min(ld_mut<MUT>(&b.fw_off[v + 1]) - w0 + 1, wmax);
+      t = 32 * nw + 1;
+      for (w = 1; w < nw; ++w) {
+        const uint32_t x = ld_mut<MUT>(&b.Fx[w0 + w - 1]);
+        if (x != ~0u) {
+          t = 32 * w + __builtin_ctz(~x) + 1;
+          break;
+        }
       }
+      bytes += 8;  // the two offsets
     }
     st_dev(&b.T[v], t);
     if (round <= b.t8_last) st_mut<MUT>(&b.T8[v], static_cast<uint8_t>(t));
     work += static_cast<uint64_t>(ld_mut<MUT>(&b.work[v]));
     lists += static_cast<uint64_t>(ld_mut<MUT>(&b.alen_in[v]));
-    // worklist id, two bitset offsets, the words scanned, static work, T write (and its byte)
-    bytes += 4 + 8 + 4 * static_cast<uint64_t>(min(w + 1, max(nw, 1))) + 4 + 4 + (round <= b.t8_last ? 1 : 0);
+    // worklist id, the words scanned, static work, T write (and its byte)
+    bytes += 4 + 4 * static_cast<uint64_t>(min(w + 1, nw)) + 4 + 4 + (round <= b.t8_last ? 1 : 0);
   }
   work = wsum(work);
   lists = wsum(lists);
@@ -323,11 +339,12 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
         bytes += 28 + 8ull * static_cast<uint64_t>(len) + 4ull * static_cast<uint64_t>(kept + kept_lo);
       }
     } else {
-      // push the color to every list entry: the whole list on the first
-      // pass, else both parts.  No committed-color gather first: a committed
-      // neighbour's bitset is never read again, so a push into it is
-      // harmless, and a list was compacted a few rounds ago at most
-      // (measured on MI355X: R-MAT 22 D1 40.9 -> 39.9 ms, PD2 unchanged).
+      // push the color to every list entry not yet committed: the whole
+      // list on the first pass, else both parts.  The committed test reads
+      // the bit array (cached; a 32-bit committed-color gather here had cost
+      // more than the pushes it saved); a neighbour committing in the same
+      // round may still get the push, which is harmless: a committed
+      // vertex's bitset is never read again.
       const int32_t cap = first_pass ? len : ld_mut<MUT>(&b.aoff[v + 1]) - base;
       const int32_t lo_len = first_pass ? 0 : ld_mut<MUT>(&b.llen[v]);
       for (int part = 0; part < 2; ++part) {
@@ -342,7 +359,7 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
           }
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            if (x[j] >= 0) push_color<MUT>(b, x[j], tv, pushes);
+            if (x[j] >= 0 && !committed<MUT>(b, x[j])) push_color<MUT>(b, x[j], tv, pushes);
         }
       }
       if (sub == 0) {
@@ -350,7 +367,7 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
         mark_committed(b, v);
         maxc_acc = max(maxc_acc, tv);
         s_ent[idx] = -1;
-        bytes += 20 + 4ull * static_cast<uint64_t>(len + lo_len);  // own fields, C write, the push pass
+        bytes += 20 + 8ull * static_cast<uint64_t>(len + lo_len);  // own fields, C write, entries + committed bits
       }
     }
   }
@@ -547,9 +564,8 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
       bytes += 24 + 8ull * static_cast<uint64_t>(len + lo_len) + 4ull * static_cast<uint64_t>(kept + kept_lo);
     }
   } else {
-    // push the color to every list entry (as in the lane-group path: no
-    // committed-color gather first): the whole list on the first pass, else
-    // both parts
+    // push the color to every list entry not yet committed (as in the
+    // lane-group path): the whole list on the first pass, else both parts
     const int32_t cap = first_pass ? len : ld_mut<MUT>(&b.aoff[v + 1]) - base;
     const int32_t lo_len = first_pass ? 0 : ld_mut<MUT>(&b.llen[v]);
     for (int part = 0; part < 2; ++part) {
@@ -564,14 +580,14 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
         }
 #pragma unroll
         for (int j = 0; j < kIncBatch; ++j)
-          if (x[j] >= 0) push_color<MUT>(b, x[j], tv, pushes);
+          if (x[j] >= 0 && !committed<MUT>(b, x[j])) push_color<MUT>(b, x[j], tv, pushes);
       }
     }
     if (tid == 0) {
       st_dev(&b.C[v], tv);
       mark_committed(b, v);
       maxc_acc = max(maxc_acc, tv);
-      bytes += 20 + 4ull * static_cast<uint64_t>(len + lo_len);  // own fields, C write, the push pass
+      bytes += 20 + 8ull * static_cast<uint64_t>(len + lo_len);  // own fields, C write, entries + committed bits
     }
   }
   __syncthreads();
@@ -836,9 +852,10 @@ bool launch_inc_tail(const KeySource& k, const IncRoundSet& set, const BinLayout
 // itself, sum over u in N(v) of deg(u) = work(v) - deg(v) (v appears once in
 // each neighbour's row).  PD2: sum over the rows of column v of deg(row) - 1
 // = work(v) - 2 (rows of v), work counting each row entry and the row's
-// columns.  words(v): bitset words covering colors
-// 1..min(len, ids)+1, the largest first fit v can ever take (ids: the
-// vertices a walk can reach, g.ids or else n).
+// columns.  words(v): the bitset words beyond word 0 (which every vertex has
+// in the dense array) that cover colors 1..min(len, ids)+1, the largest
+// first fit v can ever take (ids: the vertices a walk can reach, g.ids or
+// else n).
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void inc_sizes_kernel(GraphView g, const int32_t* work, int32_t* len,
                                                            int32_t* words, int32_t* alen0,
@@ -861,7 +878,7 @@ __global__ __launch_bounds__(kBlock) void inc_sizes_kernel(GraphView g, const in
   const int32_t lc = static_cast<int32_t>(l > INT_MAX ? INT_MAX : l);
   st_dev(&len[v], lc);
   st_dev(&alen0[v], lc);
-  st_dev(&words[v], static_cast<int32_t>(min<int64_t>(l, max(g.n, g.ids)) / 32 + 1));
+  st_dev(&words[v], static_cast<int32_t>(min<int64_t>(l, max(g.n, g.ids)) / 32));
 }
 
 // Materializes the two-hop list of a vertex with a short first hop (one
@@ -1014,21 +1031,17 @@ __global__ __launch_bounds__(kBlock) void inc_init_push_kernel(IncBufs b, int32_
 // ghosts above g.limit), enter the bitset of each uncolored vertex: one
 // thread per first-hop entry, which walks its second-hop row.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void inc_init_pull_kernel(GraphView g, int32_t nnz1, const int32_t* C,
-                                                               const int32_t* fw_off, uint32_t* F) {
+__global__ __launch_bounds__(kBlock) void inc_init_pull_kernel(GraphView g, int32_t nnz1, IncBufs b) {
   const int32_t q = blockIdx.x * kBlock + threadIdx.x;
   if (q >= nnz1) return;
   const int32_t v = row_of(g.rp, g.n, q);
-  if (ld_dev(&C[v]) != 0) return;
-  const int32_t w0 = fw_off[v];
-  const int32_t nw = fw_off[v + 1] - w0;
+  if (ld_dev(&b.C[v]) != 0) return;
   auto take = [&](int32_t x) {
-    const int32_t c = ld_dev(&C[x]);
-    const int32_t w = (c - 1) >> 5;
-    if (c != 0 && w < nw) {
-      const uint32_t bit = 1u << ((c - 1) & 31);
-      if (!(F[w0 + w] & bit)) atomicOr(&F[w0 + w], bit);
-    }
+    const int32_t c = ld_dev(&b.C[x]);
+    if (c == 0) return;
+    uint32_t* p = f_word<0>(b, v, (c - 1) >> 5);
+    const uint32_t bit = 1u << ((c - 1) & 31);
+    if (p && !(*p & bit)) atomicOr(p, bit);
   };
   const int32_t u = g.ci[q];
   if (MODE == kD2) take(u);
@@ -1242,8 +1255,7 @@ void launch_inc_init_push(const IncBufs& b, int32_t n, const int32_t* A0, hipStr
 template <int MODE>
 void launch_inc_init_pull(const GraphView& g, int32_t nnz1, const IncBufs& b, hipStream_t st) {
   if (nnz1 > 0)
-    hipLaunchKernelGGL(inc_init_pull_kernel<MODE>, dim3(blocks_for(nnz1)), dim3(kBlock), 0, st, g, nnz1, b.C,
-                       b.fw_off, b.F);
+    hipLaunchKernelGGL(inc_init_pull_kernel<MODE>, dim3(blocks_for(nnz1)), dim3(kBlock), 0, st, g, nnz1, b);
 }
 template void launch_inc_init_pull<kD2>(const GraphView&, int32_t, const IncBufs&, hipStream_t);
 template void launch_inc_init_pull<kPD2>(const GraphView&, int32_t, const IncBufs&, hipStream_t);

@@ -29,8 +29,9 @@ struct IncBufs {
   int32_t t8_last;             // last round whose tentative colors all fit a byte: a color taken in
                                // round r is at most (largest initial color) + r
   uint32_t* done;              // committed vertices, one bit each (the compaction test)
-  const int32_t* fw_off;       // bitset word offsets, n+1 entries
-  uint32_t* F;                 // forbidden-color bitsets (bit c-1 = color c)
+  const int32_t* fw_off;       // offsets of the bitset words beyond word 0 in Fx, n+1 entries
+  uint32_t* F;                 // forbidden-color bitsets, word 0 (colors 1..32) of every vertex
+  uint32_t* Fx;                // their further words (bit c-1 = color c throughout)
   int32_t* maxc;               // largest committed color
   unsigned long long* acc;     // [0] sum |W|, [1] sum work, [2] list entries, [3] color bytes,
                                // [4] detect bytes, [5] pushes, [6] and [7] color and detect bytes
