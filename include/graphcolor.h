@@ -17,7 +17,8 @@
  * are judged at once on the round's tentative colors.  In a conflict the
  * vertex with the LOWER key loses, key(v) = (p(v), gid(v)) compared
  * lexicographically, p(v) = fmix32(gid(v) ^ fmix32(seed ^ 0x9E3779B9)) with
- * fmix32 the MurmurHash3 32-bit finalizer (a bijection, so keys never tie).
+ * fmix32 the MurmurHash3 32-bit finalizer (a bijection, so keys never tie);
+ * with COLOR_FLAG_RECOLOR_DEGREES the key is (deg(v), p(v), gid(v)).
  * The coloring is therefore a deterministic function of (graph, keys) and is
  * identical for every launch geometry, degree-bin setting, stream and
  * batching mode.  Colors are 1-based; 0 means "uncolored" (Section 3.2) and
