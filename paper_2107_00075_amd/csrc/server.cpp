@@ -108,6 +108,18 @@ struct ServedJob {
 
 using namespace gcol;
 
+// Heavy lanes: each a worker thread with its own stream and its own
+// workspace of fixed buffers (regions of the running job's arena space), so
+// that several long-walk jobs, whose rounds are mostly latency-bound, overlap
+// on the device.
+constexpr int kHeavyLanes = 3;
+
+struct HeavyLane {
+  std::thread thread;
+  hipStream_t stream = nullptr;
+  Workspace ws;
+};
+
 struct color_server {
   std::mutex mu;
   int device = 0;
@@ -128,14 +140,13 @@ struct color_server {
   bool in_flight = false;
   hipEvent_t epoch_done = nullptr;
   int error = COLOR_OK;
-  // heavy lane: jobs with long two-hop walks, colored one at a time by the
-  // single-graph calls (incremental engine) on their own stream and thread
+  // heavy lanes: jobs with long two-hop walks, each colored by the
+  // single-graph call of its kind (incremental engine) on a lane's stream and
+  // thread
   std::deque<uint64_t> heavy_queue;
-  std::thread heavy_thread;
-  std::condition_variable heavy_cv;  // wakes the heavy lane
+  HeavyLane heavy[kHeavyLanes];
+  std::condition_variable heavy_cv;  // wakes the heavy lanes
   std::condition_variable done_cv;   // a heavy job finished
-  hipStream_t heavy_stream = nullptr;
-  Workspace heavy_ws;  // fixed buffers: regions of the running heavy job's arena space
   bool stopping = false;
 };
 
@@ -370,13 +381,13 @@ double job_walk(const color_job& j, int32_t nnz) {
 
 // Copies a heavy job in, colors it with the single-graph call of its kind
 // and copies the colors out, all on the heavy lane's stream.
-int run_heavy(color_server* s, ServedJob& J) {
+int run_heavy(color_server* s, HeavyLane& lane, ServedJob& J) {
   char* p = s->arena_base + J.arena_off;
   const int32_t* h = J.h_in;
   auto put = [&](size_t entries) {
     int32_t* d = reinterpret_cast<int32_t*>(p);
     p += align_up(sizeof(int32_t) * entries);
-    if (entries && hipMemcpyAsync(d, h, sizeof(int32_t) * entries, hipMemcpyHostToDevice, s->heavy_stream) !=
+    if (entries && hipMemcpyAsync(d, h, sizeof(int32_t) * entries, hipMemcpyHostToDevice, lane.stream) !=
                        hipSuccess)
       return static_cast<int32_t*>(nullptr);
     h += entries;
@@ -396,7 +407,7 @@ int run_heavy(color_server* s, ServedJob& J) {
   int32_t* colors = reinterpret_cast<int32_t*>(p);
   p += align_up(sizeof(int32_t) * static_cast<size_t>(std::max(d.n, 1)));
   // the engine's buffers: the rest of the job's arena region
-  carve_workspace(&s->heavy_ws, p, J.plan);
+  carve_workspace(&lane.ws, p, J.plan);
   // Per-round launches only: the light lane's persistent kernel fills the
   // device at the same time, so a cooperative tail launch would mostly find
   // its workgroups not all resident and fall back after its check-in wait.
@@ -405,20 +416,21 @@ int run_heavy(color_server* s, ServedJob& J) {
   prm.flags = COLOR_FLAG_NO_TAIL;
   prm.engine = COLOR_ENGINE_INCREMENTAL;
   int rc = d.kind == COLOR_KIND_D2
-               ? color_d2_fixed(&s->heavy_ws, d.n, rp, ci, d.seed, colors, &J.stats, &prm, s->heavy_stream)
-               : color_pd2_fixed(&s->heavy_ws, J.n_csr_rows, d.n, rp, ci, cp, ri, d.seed, colors, &J.stats, &prm,
-                                 s->heavy_stream);
+               ? color_d2_fixed(&lane.ws, d.n, rp, ci, d.seed, colors, &J.stats, &prm, lane.stream)
+               : color_pd2_fixed(&lane.ws, J.n_csr_rows, d.n, rp, ci, cp, ri, d.seed, colors, &J.stats, &prm,
+                                 lane.stream);
   if (rc != COLOR_OK && rc != COLOR_ENOCONVERGE) return rc;
   J.rc = rc;
   J.colors.resize(static_cast<size_t>(d.n));
   if (hipMemcpyAsync(J.colors.data(), colors, sizeof(int32_t) * J.colors.size(), hipMemcpyDeviceToHost,
-                     s->heavy_stream) != hipSuccess ||
-      hipStreamSynchronize(s->heavy_stream) != hipSuccess)
+                     lane.stream) != hipSuccess ||
+      hipStreamSynchronize(lane.stream) != hipSuccess)
     return COLOR_EHIP;
   return COLOR_OK;
 }
 
-void heavy_lane(color_server* s) {
+void heavy_lane(color_server* s, int li) {
+  HeavyLane& lane = s->heavy[li];
   if (hipSetDevice(s->device) != hipSuccess) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->error = COLOR_EHIP;
@@ -440,7 +452,7 @@ void heavy_lane(color_server* s) {
     J.arena_off = off;
     J.state = JobState::Running;
     lk.unlock();
-    const int e = run_heavy(s, J);  // J stays put: only Done jobs are erased
+    const int e = run_heavy(s, lane, J);  // J stays put: only Done jobs are erased
     lk.lock();
     s->arena.release(J.arena_off, J.footprint);
     J.footprint = 0;
@@ -455,15 +467,15 @@ void heavy_lane(color_server* s) {
 }
 
 void destroy_server(color_server* s) {
-  if (s->heavy_thread.joinable()) {
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->stopping = true;
-    }
-    s->heavy_cv.notify_all();
-    s->heavy_thread.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
   }
-  if (s->heavy_stream) (void)hipStreamSynchronize(s->heavy_stream);
+  s->heavy_cv.notify_all();
+  for (HeavyLane& lane : s->heavy) {
+    if (lane.thread.joinable()) lane.thread.join();
+    if (lane.stream) (void)hipStreamSynchronize(lane.stream);
+  }
   if (s->compute) (void)hipStreamSynchronize(s->compute);
   if (s->copy) (void)hipStreamSynchronize(s->copy);
   for (auto& kv : s->jobs) free_job_resources(s, kv.second);
@@ -477,7 +489,8 @@ void destroy_server(color_server* s) {
   if (s->h_words) (void)hipHostFree(s->h_words);
   if (s->compute) (void)hipStreamDestroy(s->compute);
   if (s->copy) (void)hipStreamDestroy(s->copy);
-  if (s->heavy_stream) (void)hipStreamDestroy(s->heavy_stream);
+  for (HeavyLane& lane : s->heavy)
+    if (lane.stream) (void)hipStreamDestroy(lane.stream);
   delete s;
 }
 
@@ -503,12 +516,14 @@ color_server* color_server_create(size_t hbm_budget_bytes, int32_t max_slots, in
   if (hipGetDevice(&s->device) != hipSuccess) return fail(COLOR_EHIP);
   if (hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->heavy_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&s->epoch_done, hipEventDisableTiming) != hipSuccess)
     return fail(COLOR_EHIP);
-  if (hipHostMalloc(reinterpret_cast<void**>(&s->heavy_ws.host), sizeof(Scalars), hipHostMallocDefault) !=
-          hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&s->arena_base), hbm_budget_bytes) != hipSuccess ||
+  for (HeavyLane& lane : s->heavy) {
+    if (hipStreamCreateWithFlags(&lane.stream, hipStreamNonBlocking) != hipSuccess) return fail(COLOR_EHIP);
+    if (hipHostMalloc(reinterpret_cast<void**>(&lane.ws.host), sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
+      return fail(COLOR_ENOMEM);
+  }
+  if (hipMalloc(reinterpret_cast<void**>(&s->arena_base), hbm_budget_bytes) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&s->d_jobs), sizeof(BatchJob) * ns) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&s->d_words), sizeof(uint64_t) * ns) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&s->d_ctr), kAlign) != hipSuccess ||
@@ -532,7 +547,7 @@ color_server* color_server_create(size_t hbm_budget_bytes, int32_t max_slots, in
     return fail(COLOR_EHIP);
   s->slot_job.assign(ns, 0);
   try {
-    s->heavy_thread = std::thread(heavy_lane, s);
+    for (int i = 0; i < kHeavyLanes; ++i) s->heavy[i].thread = std::thread(heavy_lane, s, i);
   } catch (...) {
     return fail(COLOR_ENOMEM);
   }
