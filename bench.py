@@ -560,9 +560,13 @@ def bench_serve(args, torch, gc, dev):
         index = {}
         nxt = 0
         t0 = time.perf_counter()
+        t_log = t0
         try:
             while nxt < len(specs) or pending:
                 now = time.perf_counter() - t0
+                if now + t0 - t_log > 10.0:
+                    t_log = now + t0
+                    log(f"[bench] serve: {len(lat)} of {len(specs)} jobs done after {now:.1f} s")
                 while nxt < len(specs) and arrive[nxt] <= now:
                     jid = submit(srv, specs[nxt])
                     pending[jid] = arrive[nxt]
