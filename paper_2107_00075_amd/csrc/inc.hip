@@ -278,13 +278,16 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
     // conflict (a lane-by-lane stop would keep the group scanning until its
     // slowest lane reached the end; measured on MI355X, two entries per step
     // beat four: R-MAT 22 D1 39.3 -> 38.4 ms)
-    for (int32_t e0 = 0; e0 < len; e0 += 2 * G) {
+    // wide groups take one entry per lane in their first step (a loser
+    // mostly meets its conflict near the front of its list)
+    for (int32_t e0 = 0, per = (G >= 32 ? 1 : 2); e0 < len; e0 += per * G, per = 2) {
       int32_t u[2], t[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int32_t e = e0 + sub + j * G;
-        u[j] = e < len ? ld_mut<MUT>(&A[e]) : -1;
-        read += e < len ? 1 : 0;
+        const bool in = j < per && e < len;
+        u[j] = in ? ld_mut<MUT>(&A[e]) : -1;
+        read += in ? 1 : 0;
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
@@ -412,29 +415,44 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
 // at a barrier once per kBlock * kIncBatch entries.
 constexpr int kIncBatch = 8;
 
+// A heavy vertex's own fields, loaded ahead for a batch of heavy units at
+// once (one round trip for the batch instead of two per vertex).
+struct HeavyVertex {
+  int32_t v, tv, base, end, len, llen;
+};
+constexpr int kHeavyBatch = 8;
+
+// Returns the bin of the next worklist if v lost (its append is left to the
+// caller, batched), else -1.
 template <int MUT>
-__device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBufs& b, const BinLayout& L, int round,
-                                                 int32_t v, int32_t* s_wc, int32_t& maxc_acc, uint64_t& bytes,
-                                                 uint64_t& pushes) {
+__device__ __forceinline__ int inc_detect_block(const KeySource& k, const IncBufs& b, const BinLayout& L, int round,
+                                                const HeavyVertex& h, int32_t* s_wc, int32_t& maxc_acc,
+                                                uint64_t& bytes, uint64_t& pushes) {
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const bool first_pass = b.A_in != b.A_out;
   const bool t8 = round <= b.t8_last;
-  const int32_t tv = ld_mut<MUT>(&b.T[v]);
+  const int32_t v = h.v;
+  const int32_t tv = h.tv;
   const uint64_t kv = key_of(k, v);
-  const int32_t base = ld_mut<MUT>(&b.aoff[v]);
-  const int32_t len = ld_mut<MUT>(&b.alen_in[v]);
+  const int32_t base = h.base;
+  const int32_t len = h.len;
   const int32_t* A = b.A_in + base;
   constexpr int32_t step = kBlock * kIncBatch;
   bool lose = false;
   uint32_t read = 0, gath = 0;
-  for (int32_t e0 = 0; e0 < len; e0 += step) {
+  // steps of one, two, then kIncBatch entries per thread: a losing vertex
+  // mostly meets a conflict near the front, where a full step would read
+  // kIncBatch times more than it needs (measured on MI355X: R-MAT 22 D1
+  // 34.8 -> 32.5 ms per call, the PD2 pattern 64.4 -> 62.9 ms)
+  for (int32_t e0 = 0, per = 1; e0 < len; e0 += per * kBlock, per = (per == 1 ? 2 : kIncBatch)) {
     int32_t u[kIncBatch], t[kIncBatch];
 #pragma unroll
     for (int j = 0; j < kIncBatch; ++j) {
       const int32_t e = e0 + j * kBlock + tid;
-      u[j] = e < len ? ld_mut<MUT>(&A[e]) : -1;
-      read += e < len ? 1u : 0u;
+      const bool in = j < per && e < len;
+      u[j] = in ? ld_mut<MUT>(&A[e]) : -1;
+      read += in ? 1u : 0u;
     }
     // only a higher-key neighbour can beat v: before the lists are split by
     // key, compare keys first and read the tentative colors of those only
@@ -453,20 +471,17 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
     }
   }
   bytes += 4ull * read + (t8 ? 1ull : 4ull) * gath;  // list entries and tentative colors this thread read
+  int next_bin = -1;
   if (lose && !compact_now(b, round, v)) {
-    if (tid == 0) {
-      const int nb = inc_bin_of(L, first_pass ? len : len + ld_mut<MUT>(&b.llen[v]));
-      const int32_t p = atomicAdd(&b.cnt_out[nb], 1);
-      st_dev(&b.wl_out[L.off[nb] + p], v);
-      bytes += 28;
-    }
+    next_bin = inc_bin_of(L, first_pass ? len : len + h.llen);
+    if (tid == 0) bytes += 28;
   } else if (lose) {
     // keep the neighbours that are not committed (yet), order free; the
     // first pass also splits them by key (higher to the front, lower to the
     // back).  Later passes compact the front part in place: every entry of a
     // step is read before the barrier that precedes the step's writes, and
     // writes land below the step's first entry or inside it.
-    const int32_t cap = ld_mut<MUT>(&b.aoff[v + 1]) - base;
+    const int32_t cap = h.end - base;
     int32_t kept = 0, kept_lo = 0;
     int32_t* s_lo = s_wc + kWavesPerBlock;
     for (int32_t e0 = 0; e0 < len; e0 += step) {
@@ -524,7 +539,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
     // late would push over every lower-key neighbour it had in round 1).
     // Back index q = 0, 1, ... is list position cap-1-q; kept entries move
     // to back indices below or at their own, in step order as above.
-    const int32_t lo_len = first_pass ? 0 : ld_mut<MUT>(&b.llen[v]);
+    const int32_t lo_len = first_pass ? 0 : h.llen;
     for (int32_t q0 = 0; q0 < lo_len; q0 += step) {
       int32_t u[kIncBatch];
       uint32_t keep = 0;
@@ -555,19 +570,17 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
       kept_lo += tot;
       __syncthreads();
     }
+    next_bin = inc_bin_of(L, kept + kept_lo);
     if (tid == 0) {
       st_dev(&b.alen_out[v], kept);
       st_dev(&b.llen[v], kept_lo);
-      const int nb = inc_bin_of(L, kept + kept_lo);
-      const int32_t p = atomicAdd(&b.cnt_out[nb], 1);
-      st_dev(&b.wl_out[L.off[nb] + p], v);
       bytes += 24 + 8ull * static_cast<uint64_t>(len + lo_len) + 4ull * static_cast<uint64_t>(kept + kept_lo);
     }
   } else {
     // push the color to every list entry not yet committed (as in the
     // lane-group path): the whole list on the first pass, else both parts
-    const int32_t cap = first_pass ? len : ld_mut<MUT>(&b.aoff[v + 1]) - base;
-    const int32_t lo_len = first_pass ? 0 : ld_mut<MUT>(&b.llen[v]);
+    const int32_t cap = first_pass ? len : h.end - base;
+    const int32_t lo_len = first_pass ? 0 : h.llen;
     for (int part = 0; part < 2; ++part) {
       const int32_t pb = part == 0 ? 0 : cap - lo_len;
       const int32_t pe = part == 0 ? len : cap;
@@ -591,6 +604,7 @@ __device__ __forceinline__ void inc_detect_block(const KeySource& k, const IncBu
     }
   }
   __syncthreads();
+  return next_bin;
 }
 
 struct IncDetectShared {
@@ -601,6 +615,8 @@ struct IncDetectShared {
   int32_t wc[4 * kWavesPerBlock + 4];   // per-target-bin wave offsets, then per-bin bases
   unsigned long long acc[2];
   IncMap M;
+  HeavyVertex hv[kHeavyBatch];  // the batch of heavy units in hand
+  int8_t hb[kHeavyBatch];       // the next worklist's bin of each, or -1 (committed)
 };
 
 template <int MUT>
@@ -645,17 +661,58 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
       default: inc_detect_chunk<64, MUT>(k, b, L, round, wl, count, s_ent, s_tb, s_wc, maxc_acc, bytes, pushes); break;
     }
   }
-  // heavy units: the first one of every workgroup is its own (no atomic),
-  // later ones are handed out by a counter
-  for (int32_t u = lb; u < M.heavy_total;) {
-    const int bin = u < M.cnt[kBlockBin] ? kBlockBin : kSplitBin;
-    const int32_t j = bin == kBlockBin ? u : u - M.cnt[kBlockBin];
-    const int32_t v = ld_mut<MUT>(&b.wl_in[L.off[bin] + j]);
-    inc_detect_block<MUT>(k, b, L, round, v, s_wc, maxc_acc, bytes, pushes);
-    if (threadIdx.x == 0) s_unit = static_cast<int32_t>(gridDim.x) + atomicAdd(&b.tile_ctr[1], 1);
+  // heavy units, kHeavyBatch at a time: first the workgroup's own
+  // (units lb, lb + G, lb + 2G, ... : no atomic), then batches of consecutive
+  // units above G * kHeavyBatch handed out by a counter.  The batch's vertex
+  // fields are loaded at once, and its losers are appended together, one
+  // counter atomic per target bin.
+  const int32_t G = static_cast<int32_t>(gridDim.x);
+  const int64_t static_end = static_cast<int64_t>(G) * kHeavyBatch;
+  int32_t dyn = -1;  // first unit of a handed-out batch; -1: the own batch
+  while (true) {
+    if (threadIdx.x < kHeavyBatch) {
+      const int j = threadIdx.x;
+      const int64_t u = dyn < 0 ? static_cast<int64_t>(lb) + static_cast<int64_t>(j) * G : dyn + j;
+      HeavyVertex h{-1, 0, 0, 0, 0, 0};
+      if (u < M.heavy_total) {
+        const int32_t ui = static_cast<int32_t>(u);
+        const int bin = ui < M.cnt[kBlockBin] ? kBlockBin : kSplitBin;
+        const int32_t jj = bin == kBlockBin ? ui : ui - M.cnt[kBlockBin];
+        h.v = ld_mut<MUT>(&b.wl_in[L.off[bin] + jj]);
+        h.tv = ld_mut<MUT>(&b.T[h.v]);
+        h.base = ld_mut<MUT>(&b.aoff[h.v]);
+        h.end = ld_mut<MUT>(&b.aoff[h.v + 1]);
+        h.len = ld_mut<MUT>(&b.alen_in[h.v]);
+        h.llen = ld_mut<MUT>(&b.llen[h.v]);
+      }
+      sh.hv[j] = h;
+      sh.hb[j] = -1;
+    }
     __syncthreads();
-    u = s_unit;
+    for (int j = 0; j < kHeavyBatch; ++j) {
+      const HeavyVertex h = sh.hv[j];
+      if (h.v < 0) continue;
+      const int nb = inc_detect_block<MUT>(k, b, L, round, h, s_wc, maxc_acc, bytes, pushes);
+      if (threadIdx.x == 0) sh.hb[j] = static_cast<int8_t>(nb);
+    }
     __syncthreads();
+    // the batch's losers: thread t appends those of target bin t
+    if (threadIdx.x < 4) {
+      const int t = threadIdx.x == 3 ? kBlockBin : threadIdx.x;
+      int32_t c = 0;
+      for (int j = 0; j < kHeavyBatch; ++j) c += sh.hb[j] == t ? 1 : 0;
+      if (c > 0) {
+        int32_t p = atomicAdd(&b.cnt_out[t], c);
+        for (int j = 0; j < kHeavyBatch; ++j)
+          if (sh.hb[j] == t) st_dev(&b.wl_out[L.off[t] + p++], sh.hv[j].v);
+      }
+    }
+    if (dyn < 0 && static_end >= M.heavy_total) break;
+    if (threadIdx.x == 0) s_unit = static_cast<int32_t>(static_end) + kHeavyBatch * atomicAdd(&b.tile_ctr[1], 1);
+    __syncthreads();
+    dyn = s_unit;
+    __syncthreads();
+    if (dyn >= M.heavy_total) break;
   }
   maxc_acc = [&] {
     int32_t x = maxc_acc;
