@@ -992,7 +992,7 @@ def main():
     ap.add_argument("--jobs", type=int, default=300, help="batch/serve: jobs in the stream")
     ap.add_argument("--n-max", type=float, default=3e4, help="batch/serve: largest job size (vertices)")
     ap.add_argument("--stream-seed", type=int, default=5)
-    ap.add_argument("--slots", type=int, default=64, help="serve: job slots")
+    ap.add_argument("--slots", type=int, default=256, help="serve: job slots")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for counter scaling)")
