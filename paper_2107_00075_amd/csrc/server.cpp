@@ -140,6 +140,7 @@ struct color_server {
   bool in_flight = false;
   hipEvent_t epoch_done = nullptr;
   int error = COLOR_OK;
+  std::vector<uint64_t> draining;  // jobs whose colors are being copied out
   // heavy lanes: jobs with long two-hop walks, each colored by the
   // single-graph call of its kind (incremental engine) on a lane's stream and
   // thread
@@ -263,19 +264,26 @@ int collect_epoch(color_server* s) {
       return COLOR_EHIP;
     if (hipEventRecord(J.ev, s->copy) != hipSuccess) return COLOR_EHIP;
     J.state = JobState::Draining;
+    s->draining.push_back(id);
   }
   return COLOR_OK;
 }
 
-// Jobs whose copy out has completed become Done and free their resources.
+// Jobs whose copy out has completed become Done and free their resources
+// (a list of the draining jobs: every poll comes here, so no pass over all
+// jobs).
 void retire_drained(color_server* s) {
-  for (auto& kv : s->jobs) {
-    ServedJob& J = kv.second;
-    if (J.state != JobState::Draining) continue;
-    if (hipEventQuery(J.ev) != hipSuccess) continue;
+  size_t keep = 0;
+  for (size_t i = 0; i < s->draining.size(); ++i) {
+    ServedJob& J = s->jobs.at(s->draining[i]);
+    if (hipEventQuery(J.ev) != hipSuccess) {
+      s->draining[keep++] = s->draining[i];
+      continue;
+    }
     J.state = JobState::Done;
     free_job_resources(s, J);
   }
+  s->draining.resize(keep);
 }
 
 // Launches the next epoch over every resident job (newly copied-in jobs
