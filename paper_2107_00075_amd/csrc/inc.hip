@@ -112,17 +112,24 @@ __device__ __forceinline__ void push_color(const IncBufs& b, int32_t x, int32_t 
 // A loser compacts its list to the neighbours not yet committed in the first
 // kCompactAlways rounds (where most neighbours commit), whenever its list is
 // still the read-only adjacency (round 1 of D1), and else once every
-// kCompactPeriod rounds.  Entries of committed neighbours left in a list are
-// harmless: a committed neighbour's tentative color is its committed color,
-// which the vertex's own tentative color avoids, and pushes skip committed
-// vertices.  (Measured on MI355X against 4 and 4: R-MAT 22 D1 45.0 -> 41.5 ms,
-// the 4M x 1M PD2 pattern 78.5 -> 75.1 ms.)
+// kCompactPeriod rounds (kTailCompactPeriod in the tail kernel, whose rounds
+// commit few vertices each).  Entries of committed neighbours left in a list
+// are harmless: a committed neighbour's tentative color is its committed
+// color, which the vertex's own tentative color avoids, and pushes skip
+// committed vertices.  (Measured on MI355X: every 4th against every 8th
+// round, R-MAT 22 D1 45.0 -> 41.5 ms, the 4M x 1M PD2 pattern 78.5 -> 75.1
+// ms; later, with the small first scan steps, every 16th round and every
+// 32nd in the tail: R-MAT 22 per-round detect 414 -> 404 us per launch, the
+// whole call within run-to-run noise.)
 constexpr int kCompactAlways = 2;
-constexpr int kCompactPeriod = 8;  // a power of two
+constexpr int kCompactPeriod = 16;      // a power of two
+constexpr int kTailCompactPeriod = 32;  // a power of two
 
+template <int MUT>
 __device__ __forceinline__ bool compact_now(const IncBufs& b, int round, int32_t v) {
   if (b.defer_split) return false;
-  return b.A_in != b.A_out || round <= kCompactAlways || ((round + v) & (kCompactPeriod - 1)) == 0;
+  constexpr int period = MUT ? kTailCompactPeriod : kCompactPeriod;
+  return b.A_in != b.A_out || round <= kCompactAlways || ((round + v) & (period - 1)) == 0;
 }
 
 // The conflict test's gather: a neighbour's tentative color from the byte
@@ -305,7 +312,7 @@ __device__ __forceinline__ void inc_detect_chunk(const KeySource& k, const IncBu
     }
     // list entries and tentative colors this lane read
     bytes += 4ull * static_cast<uint64_t>(read) + (t8 ? 1ull : 4ull) * static_cast<uint64_t>(gath);
-    if (lose && !compact_now(b, round, v)) {
+    if (lose && !compact_now<MUT>(b, round, v)) {
       if (sub == 0) {
         s_ent[idx] = v;
         s_tb[idx] = static_cast<int8_t>(inc_bin_of(L, first_pass ? len : len + ld_mut<MUT>(&b.llen[v])));
@@ -472,7 +479,7 @@ __device__ __forceinline__ int inc_detect_block(const KeySource& k, const IncBuf
   }
   bytes += 4ull * read + (t8 ? 1ull : 4ull) * gath;  // list entries and tentative colors this thread read
   int next_bin = -1;
-  if (lose && !compact_now(b, round, v)) {
+  if (lose && !compact_now<MUT>(b, round, v)) {
     next_bin = inc_bin_of(L, first_pass ? len : len + h.llen);
     if (tid == 0) bytes += 28;
   } else if (lose) {
