@@ -268,6 +268,12 @@ def bench_d1(args, torch, gc, dev):
                 "avg_launch_us": round(ns / max(launches, 1) / 1e3, 3),
                 "alg_bytes_per_launch": int(b / max(launches, 1)),
                 "launches_per_step": launches // max(args.steps, 1)}
+    # every timed round kernel: algorithmic bytes and HIP-event time per launch
+    kernels = {kn: {"launches_per_step": kv[2] // max(args.steps, 1),
+                    "avg_launch_us": round(kv[1] / max(kv[2], 1) / 1e3, 3),
+                    "alg_bytes_per_launch": int(kv[0] / max(kv[2], 1)),
+                    "achieved_gb_per_s": round(kv[0] / kv[1], 1) if kv[1] else None}
+               for kn, kv in kern.items()}
     for name, pg in per_graph.items():
         pg["edges_per_s_kernels_only"] = round(pg["nnz"] / (pg["kernel_ms"] / 1e3), 1) if pg["kernel_ms"] else None
 
@@ -329,6 +335,7 @@ def bench_d1(args, torch, gc, dev):
                                "symmetrized, deduplicated; int32 CSR; seed 1",
                    "graphs": per_graph},
         "roofline": roofline,
+        "kernels": kernels,
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
         "stream_copy": copy,
