@@ -175,6 +175,26 @@ def load_traffic(kernel, workload):
         return None
 
 
+def counter_rate(kern, workload):
+    """Counter-measured HBM bytes (FETCH_SIZE + WRITE_SIZE from the committed
+    summary) of all timed round kernels, summed over their launches, over
+    their summed HIP-event time: the whole coloring's %HBM.  None unless the
+    summary covers every one of them on the current sources."""
+    total_b = total_ns = 0
+    for kn, (b_alg, ns, nl) in kern.items():
+        t = load_traffic(kn, workload)
+        if t is None:
+            return None
+        total_b += t * nl
+        total_ns += ns
+    if total_ns == 0:
+        return None
+    gbs = total_b / total_ns
+    return {"bytes": int(total_b), "kernel_ms": round(total_ns / 1e6, 3), "gb_per_s": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "kernels": sorted(kern), "note": "round kernels only (setup and list building excluded)"}
+
+
 def copy_calibration(torch, dev):
     """One plain device copy of COPY_BYTES (its counters scale FETCH_SIZE and
     WRITE_SIZE to bytes)."""
@@ -272,8 +292,10 @@ def bench_d1(args, torch, gc, dev):
     kernels = {kn: {"launches_per_step": kv[2] // max(args.steps, 1),
                     "avg_launch_us": round(kv[1] / max(kv[2], 1) / 1e3, 3),
                     "alg_bytes_per_launch": int(kv[0] / max(kv[2], 1)),
-                    "achieved_gb_per_s": round(kv[0] / kv[1], 1) if kv[1] else None}
+                    "achieved_gb_per_s": round(kv[0] / kv[1], 1) if kv[1] else None,
+                    "counter_bytes_per_launch": load_traffic(kn, "d1")}
                for kn, kv in kern.items()}
+    hbm_rate = counter_rate(kern, "d1")
     for name, pg in per_graph.items():
         pg["edges_per_s_kernels_only"] = round(pg["nnz"] / (pg["kernel_ms"] / 1e3), 1) if pg["kernel_ms"] else None
 
@@ -316,7 +338,8 @@ def bench_d1(args, torch, gc, dev):
     sub = None
     if not args.no_d2pd2:
         r = bench_d2pd2(args, torch, gc, dev)
-        sub = {k: r[k] for k in ("metric", "value", "unit", "ms_per_step", "config", "roofline", "cpu_baseline")}
+        sub = {k: r[k] for k in ("metric", "value", "unit", "ms_per_step", "config", "roofline", "hbm_counter_rate",
+                                 "cpu_baseline")}
 
     return {
         "metric": "edges colored/s (D1)",
@@ -336,6 +359,7 @@ def bench_d1(args, torch, gc, dev):
                    "graphs": per_graph},
         "roofline": roofline,
         "kernels": kernels,
+        "hbm_counter_rate": hbm_rate,
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
         "stream_copy": copy,
@@ -441,6 +465,7 @@ def bench_d2pd2(args, torch, gc, dev):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, "d2pd2"),
                      "avg_launch_us": round(ns / max(launches, 1) / 1e3, 3),
                      "alg_bytes_per_launch": int(byts / max(launches, 1))},
+        "hbm_counter_rate": counter_rate(kern, "d2pd2"),
         "cpu_baseline": cpu,
     }
 
