@@ -1,15 +1,16 @@
 // Served form: continuous batching over the batched persistent engine.
 //
 // A server owns one HBM arena (the budget given at creation), a table of
-// job slots in device memory and two streams of default priority: the
-// compute stream runs epochs of the persistent kernel, the copy stream moves
-// admitted jobs' arrays in and finished jobs' colors out while an epoch
-// runs.  An epoch runs every resident job for at most kEpochRounds rounds
-// (jobs park at their epoch budget and resume in the next epoch); between
-// epochs the host retires finished jobs, frees their slots and arena space,
-// and admits queued jobs whose footprint fits.  A job's coloring is the same
-// as the single-graph call's: the engine's rounds do not depend on which
-// other jobs share a launch or on where a job parks.
+// job slots in device memory and streams of default priority: the compute
+// stream runs epochs of the persistent kernel, the copy stream moves admitted
+// jobs' arrays in and finished jobs' colors out while an epoch runs, and each
+// heavy lane (jobs with long two-hop walks, colored by the single-graph
+// calls) has its own.  An epoch runs every resident job for at most
+// kEpochRounds rounds (jobs park at their epoch budget and resume in the next
+// epoch); between epochs the host retires finished jobs, frees their slots
+// and arena space, and admits queued jobs whose footprint fits.  A job's
+// coloring is the same as the single-graph call's: the engine's rounds do not
+// depend on which other jobs share a launch or on where a job parks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -379,7 +380,7 @@ bool busy(const color_server* s) {
   return false;
 }
 
-// Two-hop walk per visit above which a job goes to the heavy lane (the same
+// Two-hop walk per visit above which a job goes to the heavy lanes (the same
 // bound as the single-graph engine choice and color_batch).
 constexpr double kLongWalk = 128.0;
 
@@ -660,7 +661,7 @@ int color_server_drain(color_server* s) {
   while (busy(s)) {
     int e = advance(s, true);
     if (e) return e;
-    // nothing launched: the heavy lane holds the remaining work or the arena
+    // nothing launched: the heavy lanes hold the remaining work or the arena
     // space queued jobs wait for; let it run
     if (!s->in_flight && busy(s)) s->done_cv.wait_for(lk, std::chrono::milliseconds(1));
   }
