@@ -80,3 +80,19 @@ def test_traffic_only_for_its_workload_and_sources(bench, tmp_path, monkeypatch)
     assert bench.load_traffic("inc_color_kernel", "d1") is None          # not measured
     path.write_text(json.dumps(dict(good, source_hash="0" * 16)))
     assert bench.load_traffic("inc_detect_kernel", "d1") is None          # kernels changed since
+
+
+def test_counter_rate_sums_every_kernel_or_reports_none(bench, monkeypatch):
+    """The whole coloring's counter rate: counter bytes per launch times
+    launches, summed over the timed round kernels, over their summed time;
+    None as soon as one kernel has no counter figure."""
+    per_launch = {"inc_detect_kernel": 600, "inc_tail_kernel": 5000}
+    monkeypatch.setattr(bench, "load_traffic", lambda k, w: per_launch.get(k))
+    kern = {"inc_detect_kernel": (300, 2000, 4), "inc_tail_kernel": (900, 1000, 1)}  # (alg bytes, ns, launches)
+    r = bench.counter_rate(kern, "d1")
+    assert r["bytes"] == 600 * 4 + 5000 * 1
+    assert r["kernel_ms"] == round(3000 / 1e6, 3)
+    assert r["gb_per_s"] == round((600 * 4 + 5000) / 3000, 1)
+    assert r["frac_of_peak"] == round((600 * 4 + 5000) / 3000 / bench.HBM_PEAK_GBS, 4)
+    kern["inc_color_kernel"] = (10, 10, 1)
+    assert bench.counter_rate(kern, "d1") is None
