@@ -311,9 +311,10 @@ int color_d1_noalloc(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
  * phase 2 compares every owned vertex with every distinct ghost within two
  * hops against the ghosts' colors (the lower key loses; boundary_conflicts
  * counts each such pair once); phase 3 recolors the owned losers with the
- * ghosts' colors as constraints.  Phase 1 runs on the engine `params` names
- * or the library's choice (the incremental engine's lists then hold only the
- * owned members of each walk); phase 3 on the pull engine.  Errors as
+ * ghosts' colors as constraints.  Both phases run on the engine `params`
+ * names or the library's choice (the incremental engine's lists then hold
+ * only the owned members of each walk; in phase 3 the ghosts' colors enter
+ * the losers' forbidden sets once, before its first round).  Errors as
  * color_d2. */
 int color_d2_ghost(int32_t n_owned, int32_t n_ghost, int32_t n_g1, const int32_t* row_ptr,
                    const int32_t* col_idx, const int32_t* gid, const int32_t* ghost_colors, uint32_t seed,

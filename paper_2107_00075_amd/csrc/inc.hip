@@ -210,16 +210,25 @@ __device__ __forceinline__ void inc_color_phase(const IncBufs& b, const BinLayou
     if (x0 != ~0u || wmax == 1) {
       t = x0 != ~0u ? __builtin_ctz(~x0) + 1 : 33;
     } else {
+      // the further words four at a time: independent loads in flight
+      // instead of one round trip per word
       const int32_t w0 = ld_mut<MUT>(&b.fw_off[v]);
       nw = min(ld_mut<MUT>(&b.fw_off[v + 1]) - w0 + 1, wmax);
       t = 32 * nw + 1;
-      for (w = 1; w < nw; ++w) {
-        const uint32_t x = ld_mut<MUT>(&b.Fx[w0 + w - 1]);
-        if (x != ~0u) {
-          t = 32 * w + __builtin_ctz(~x) + 1;
-          break;
+      bool found = false;
+      for (w = 1; w < nw && !found; w += 4) {
+        uint32_t x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = w + j < nw ? ld_mut<MUT>(&b.Fx[w0 + w + j - 1]) : ~0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (!found && x[j] != ~0u) {
+            t = 32 * (w + j) + __builtin_ctz(~x[j]) + 1;
+            found = true;
+          }
         }
       }
+      w = found ? (t - 1) / 32 : nw;  // the word that held t (or all of them)
       bytes += 8;  // the two offsets
     }
     st_dev(&b.T[v], t);
@@ -646,8 +655,23 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
   int32_t maxc_acc = 0;
   uint64_t bytes = 0, pushes = 0;
   const int32_t lb = xcd_block();
-  const int32_t c0 = static_cast<int32_t>(static_cast<int64_t>(lb) * M.light_total / gridDim.x);
-  const int32_t c1 = static_cast<int32_t>(static_cast<int64_t>(lb + 1) * M.light_total / gridDim.x);
+  // A small round of the tail kernel hands its light bins to whole
+  // workgroups as well, widest bin first, while the heavy vertices and the
+  // promoted ones together are no more than the workgroups: the grid would
+  // otherwise idle while a few lane groups step through their chunks (two
+  // vertices per group, one after the other, each list a few entries per
+  // step).  Every workgroup takes the same decision from the same counts.
+  const int32_t G = static_cast<int32_t>(gridDim.x);
+  int32_t light_total = M.light_total, heavy_total = M.heavy_total, light_bins = 3;
+  if (MUT != 0) {
+    while (light_bins > 0 && heavy_total + M.cnt[light_bins - 1] <= G) {
+      --light_bins;
+      heavy_total += M.cnt[light_bins];
+      light_total -= M.chunks[light_bins];
+    }
+  }
+  const int32_t c0 = static_cast<int32_t>(static_cast<int64_t>(lb) * light_total / gridDim.x);
+  const int32_t c1 = static_cast<int32_t>(static_cast<int64_t>(lb + 1) * light_total / gridDim.x);
   for (int32_t c = c0; c < c1; ++c) {
     int bin = 0;
     int32_t cc = c;
@@ -673,7 +697,6 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
   // units above G * kHeavyBatch handed out by a counter.  The batch's vertex
   // fields are loaded at once, and its losers are appended together, one
   // counter atomic per target bin.
-  const int32_t G = static_cast<int32_t>(gridDim.x);
   const int64_t static_end = static_cast<int64_t>(G) * kHeavyBatch;
   int32_t dyn = -1;  // first unit of a handed-out batch; -1: the own batch
   while (true) {
@@ -681,10 +704,18 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
       const int j = threadIdx.x;
       const int64_t u = dyn < 0 ? static_cast<int64_t>(lb) + static_cast<int64_t>(j) * G : dyn + j;
       HeavyVertex h{-1, 0, 0, 0, 0, 0};
-      if (u < M.heavy_total) {
-        const int32_t ui = static_cast<int32_t>(u);
-        const int bin = ui < M.cnt[kBlockBin] ? kBlockBin : kSplitBin;
-        const int32_t jj = bin == kBlockBin ? ui : ui - M.cnt[kBlockBin];
+      if (u < heavy_total) {
+        // units: bin 3, bin 4, then the promoted light bins from bin 2 down
+        int32_t jj = static_cast<int32_t>(u);
+        int bin = kBlockBin;
+        if (jj >= M.cnt[kBlockBin]) {
+          jj -= M.cnt[kBlockBin];
+          bin = kSplitBin;
+          for (int lb2 = 2; jj >= M.cnt[bin] && lb2 >= light_bins; --lb2) {
+            jj -= M.cnt[bin];
+            bin = lb2;
+          }
+        }
         h.v = ld_mut<MUT>(&b.wl_in[L.off[bin] + jj]);
         h.tv = ld_mut<MUT>(&b.T[h.v]);
         h.base = ld_mut<MUT>(&b.aoff[h.v]);
@@ -714,12 +745,12 @@ __device__ __forceinline__ void inc_detect_phase(const KeySource& k, const IncBu
           if (sh.hb[j] == t) st_dev(&b.wl_out[L.off[t] + p++], sh.hv[j].v);
       }
     }
-    if (dyn < 0 && static_end >= M.heavy_total) break;
+    if (dyn < 0 && static_end >= heavy_total) break;
     if (threadIdx.x == 0) s_unit = static_cast<int32_t>(static_end) + kHeavyBatch * atomicAdd(&b.tile_ctr[1], 1);
     __syncthreads();
     dyn = s_unit;
     __syncthreads();
-    if (dyn >= M.heavy_total) break;
+    if (dyn >= heavy_total) break;
   }
   maxc_acc = [&] {
     int32_t x = maxc_acc;
