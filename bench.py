@@ -45,6 +45,9 @@ Profiling helpers (no GPU):
     --summarize-pmc FETCH_DIR WRITE_DIR   turns two rocprofv3 --pmc runs
                        (FETCH_SIZE, WRITE_SIZE) of `bench.py --copy-calibration`
                        into profiles/pmc_traffic.json
+    --call-rate TRACE_DIR STEPS   %HBM of whole calls (every dispatch): the
+                       committed counter summary over the kernel time of one
+                       step of a rocprofv3 --kernel-trace run of STEPS steps
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -1020,6 +1023,53 @@ def summarize_pmc(fetch_dir, write_dir, workload, out):
     print(json.dumps({"written": out, "kernels": len(kernels), "fetch_scale": f_scale, "write_scale": w_scale}))
 
 
+def _trace_rows(d):
+    """(kernel name, dispatches, summed ns) from the rocpd database of a
+    rocprofv3 --kernel-trace run (its `kernels` view)."""
+    import sqlite3
+    out = {}
+    dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+    if not dbs:
+        raise SystemExit(f"no rocpd database (*.db) under {d}")
+    for fn in dbs:
+        con = sqlite3.connect(fn)
+        for name, cnt, ns in con.execute("select name, count(*), sum(end - start) from kernels group by name"):
+            k = _short(name)
+            c0, n0 = out.get(k, (0, 0))
+            out[k] = (c0 + cnt, n0 + ns)
+        con.close()
+    return out
+
+
+def call_rate(trace, traffic, steps):
+    """%HBM of whole coloring calls, every dispatch counted: each kernel's
+    counter bytes per launch times its dispatches in one step of the counter
+    run, over one step's summed kernel time in a kernel trace of the same
+    workload (`trace`: name -> (dispatches, ns) over `steps` steps).  The
+    runtime's own copy and fill kernels and torch's kernels (the counter
+    calibration) are left out of both sums; a kernel the trace lacks makes
+    the result None."""
+    total_b = total_ns = 0
+    kernels = []
+    for k, v in traffic["kernels"].items():
+        if k.startswith("__amd_rocclr") or k.startswith("at::"):
+            continue
+        t = trace.get(k)
+        if t is None:
+            # long template names are cut at different places by the two tools
+            t = next((tv for tk, tv in trace.items() if tk[:60] == k[:60]), None)
+        if t is None:
+            return None
+        total_b += int(v["hbm_bytes_per_launch"]) * int(v["dispatches"])
+        total_ns += t[1] / steps
+        kernels.append(k)
+    if total_ns == 0:
+        return None
+    gbs = total_b / total_ns
+    return {"bytes_per_step": int(total_b), "kernel_ms_per_step": round(total_ns / 1e6, 3),
+            "gb_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "kernels": len(kernels)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -1041,7 +1091,16 @@ def main():
                     help="also run one 1 GiB device copy (for counter scaling)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--pmc-out", default=None, help="default: the workload's profiles/pmc_traffic*.json")
+    ap.add_argument("--call-rate", nargs=2, metavar=("TRACE_DIR", "STEPS"),
+                    help="%%HBM of whole calls from a kernel-trace run of STEPS steps (warm-up included) "
+                         "and the workload's committed counter summary")
     args = ap.parse_args()
+    if args.call_rate:
+        with open(traffic_file(args.workload)) as f:
+            traffic = json.load(f)
+        r = call_rate(_trace_rows(args.call_rate[0]), traffic, int(args.call_rate[1]))
+        print(json.dumps({"workload": args.workload, "source_hash": traffic.get("source_hash"), "call_rate": r}))
+        return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload,
                       args.pmc_out or traffic_file(args.workload))

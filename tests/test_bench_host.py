@@ -96,3 +96,34 @@ def test_counter_rate_sums_every_kernel_or_reports_none(bench, monkeypatch):
     assert r["frac_of_peak"] == round((600 * 4 + 5000) / 3000 / bench.HBM_PEAK_GBS, 4)
     kern["inc_color_kernel"] = (10, 10, 1)
     assert bench.counter_rate(kern, "d1") is None
+
+
+def test_call_rate_counts_every_dispatch_of_a_step(bench, tmp_path):
+    """The whole-call rate: counter bytes per launch times the counter run's
+    dispatches (one step), over one step's kernel time from a kernel-trace
+    database; the runtime's copies and torch's kernels are left out, and a
+    kernel the trace lacks gives None."""
+    import sqlite3
+    db = tmp_path / "run_results.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start integer, end integer)")
+    rows = [("void gcol::inc_tail_kernel(gcol::KeySource)", 0, 4000)] * 2 + \
+           [("void gcol::bin_kernel<3>(int)", 0, 100)] * 2 + \
+           [("__amd_rocclr_copyBuffer", 0, 999999)] * 2
+    con.executemany("insert into kernels values (?, ?, ?)", rows)
+    con.commit()
+    con.close()
+    trace = bench._trace_rows(str(tmp_path))
+    assert trace["inc_tail_kernel"] == (2, 8000) and trace["bin_kernel<PD2>"] == (2, 200)
+    traffic = {"kernels": {
+        "inc_tail_kernel": {"hbm_bytes_per_launch": 3000, "dispatches": 1},
+        "bin_kernel<PD2>": {"hbm_bytes_per_launch": 50, "dispatches": 1},
+        "__amd_rocclr_copyBuffer": {"hbm_bytes_per_launch": 10 ** 9, "dispatches": 5},
+        "at::native::vectorized_elementwise_kernel<4>": {"hbm_bytes_per_launch": 10 ** 9, "dispatches": 1}}}
+    r = bench.call_rate(trace, traffic, steps=2)
+    assert r["bytes_per_step"] == 3050
+    assert r["kernel_ms_per_step"] == round((8000 + 200) / 2 / 1e6, 3)
+    assert r["gb_per_s"] == round(3050 / ((8000 + 200) / 2), 1)
+    assert r["kernels"] == 2
+    traffic["kernels"]["inc_color_kernel"] = {"hbm_bytes_per_launch": 1, "dispatches": 1}
+    assert bench.call_rate(trace, traffic, steps=2) is None
