@@ -275,12 +275,15 @@ int collect_epoch(color_server* s) {
 
 // Jobs whose copy out has completed become Done and free their resources
 // (a list of the draining jobs: every poll comes here, so no pass over all
-// jobs).
-void retire_drained(color_server* s) {
+// jobs).  A failed copy is an error of the server, not a copy still running.
+int retire_drained(color_server* s) {
   size_t keep = 0;
+  int rc = COLOR_OK;
   for (size_t i = 0; i < s->draining.size(); ++i) {
     ServedJob& J = s->jobs.at(s->draining[i]);
-    if (hipEventQuery(J.ev) != hipSuccess) {
+    const hipError_t q = hipEventQuery(J.ev);
+    if (q != hipSuccess) {
+      if (q != hipErrorNotReady) rc = COLOR_EHIP;
       s->draining[keep++] = s->draining[i];
       continue;
     }
@@ -288,6 +291,7 @@ void retire_drained(color_server* s) {
     free_job_resources(s, J);
   }
   s->draining.resize(keep);
+  return rc;
 }
 
 // Launches the next epoch over every resident job (newly copied-in jobs
@@ -299,7 +303,9 @@ int launch_epoch(color_server* s) {
     const uint64_t id = s->slot_job[i];
     if (!id) continue;
     ServedJob& J = s->jobs[id];
-    if (J.state == JobState::Copying && hipEventQuery(J.ev) == hipSuccess) {
+    const hipError_t q = J.state == JobState::Copying ? hipEventQuery(J.ev) : hipErrorNotReady;
+    if (q != hipSuccess && q != hipErrorNotReady) return COLOR_EHIP;  // the copy in failed
+    if (J.state == JobState::Copying && q == hipSuccess) {
       if (J.desc.n == 0) {  // nothing to color: finished at once
         job_stats(J.rec, &J.stats);
         J.state = JobState::Done;
@@ -350,7 +356,7 @@ int advance(color_server* s, bool wait) {
       return s->error = COLOR_EHIP;
     }
   }
-  retire_drained(s);
+  if ((e = retire_drained(s))) return s->error = e;
   if ((e = admit(s))) return s->error = e;
   if (!s->in_flight) {
     if (wait) {
@@ -368,7 +374,7 @@ int advance(color_server* s, bool wait) {
     for (auto& kv : s->jobs)
       if (kv.second.state == JobState::Draining && hipEventSynchronize(kv.second.ev) != hipSuccess)
         return s->error = COLOR_EHIP;
-    retire_drained(s);
+    if ((e = retire_drained(s))) return s->error = e;
   }
   return COLOR_OK;
 }
