@@ -21,6 +21,11 @@ resident in HBM before timing.
               traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE and
               WRITE_SIZE runs (profiles/pmc_traffic.json, taken on the same
               library sources, scaled by a plain copy's counters), else null.
+    kernels: per timed round kernel, its launches per step, HIP-event time
+             per launch, algorithmic bytes and counter bytes per launch
+    hbm_counter_rate: the counter bytes of every timed round kernel over
+             their summed time (the coloring's %HBM), while the counter
+             summary matches the library sources, else null
     cpu_baseline: the CPU oracle on a bounded sample of the same workload.
 
 Other workloads (one JSON line each, same keys):
