@@ -493,8 +493,12 @@ int color_server_submit(color_server* s, const color_host_job* job, uint64_t* jo
 
 /* Advances the server (admits queued jobs, runs rounds of the resident
  * jobs).  Returns COLOR_OK when job_id has finished (host_colors receives
- * its n colors, stats is filled; the job's slot and memory are freed),
- * COLOR_EPENDING when it has not, COLOR_EINVAL for an unknown id. */
+ * its n colors, stats is filled; the job's slot and memory are freed), the
+ * job's own error code when its coloring failed (COLOR_ENOCONVERGE at the
+ * round cap, the colors then holding the committed partial state; other
+ * jobs go on), COLOR_EPENDING when it has not finished, COLOR_EINVAL for an
+ * unknown id.  A failed launch, copy or event on the server's streams is
+ * the server's error: this call and every later one return COLOR_EHIP. */
 int color_server_poll(color_server* s, uint64_t job_id, int32_t* host_colors, color_stats* stats);
 
 /* Runs the server until every accepted job has finished. */
