@@ -42,6 +42,22 @@ def test_library_exports_every_declared_symbol(lib):
     assert set(_declared()) == set(_binding.EXPORTED)
 
 
+def test_no_undeclared_c_entry_points(lib):
+    """Every unmangled function the library exports is one the header
+    declares (the C++ internals stay mangled or hidden)."""
+    import shutil
+    import subprocess
+    from paper_2107_00075_amd import _binding
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--defined-only", _binding.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {parts[2] for parts in (line.split() for line in out.splitlines())
+                if len(parts) == 3 and parts[1] == "T" and not parts[2].startswith("_Z")}
+    assert exported == set(_declared())
+
+
 def test_strerror(lib):
     from paper_2107_00075_amd import _binding as b
     assert lib.color_strerror(0) == b"ok"
